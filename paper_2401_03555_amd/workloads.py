@@ -1,0 +1,144 @@
+"""Seeded synthetic workloads shaped like the paper's case studies.
+
+This module only *describes* inputs: systems, grids, input sets, noise levels
+and specifications as plain dicts of numbers.  It holds none of the method's
+arithmetic, so both the GPU library and the CPU oracle can be fed from it.
+
+System dict keys: ``kind`` ("affine" | "unicycle"), ``A``, ``B``, ``c`` (affine),
+``dt`` (unicycle), ``lb``, ``ub``, ``n`` (cells per dimension; cells tile
+[lb, ub]), ``inputs`` (count x dim_u array, first component slowest),
+``sigma`` (diagonal noise standard deviations), ``k_sigma`` (window half-width in
+standard deviations; 0 means dense rows).
+Spec dict keys: ``kind`` ("safety" | "reach" | "reach_avoid"), ``target``,
+``avoid`` (lists of [lo, hi] boxes), ``eps``, ``max_sweeps``.
+"""
+import itertools
+import math
+
+import numpy as np
+
+SEED = 240103555
+
+
+def _grid_inputs(*axes):
+    return np.array(list(itertools.product(*axes)), dtype=np.float64)
+
+
+def robot2d():
+    """2D robot, reach-avoid, dense rows (stand-in for the paper's 2D robot study).
+
+    x+ = x + 0.5 u + w on [-10,10]^2, 20x20 cells of width 1, u in {-1,0,1}^2,
+    sigma = 0.25; target [5,8]^2, avoid [-2,2]^2, eps 1e-8.
+    """
+    system = dict(kind="affine", A=np.eye(2), B=0.5 * np.eye(2), c=np.zeros(2),
+                  lb=[-10.0, -10.0], ub=[10.0, 10.0], n=[20, 20],
+                  inputs=_grid_inputs([-1.0, 0.0, 1.0], [-1.0, 0.0, 1.0]),
+                  sigma=[0.25, 0.25], k_sigma=0.0)
+    spec = dict(kind="reach_avoid", target=[[[5.0, 5.0], [8.0, 8.0]]],
+                avoid=[[[-2.0, -2.0], [2.0, 2.0]]], eps=1e-8, max_sweeps=100000)
+    return system, spec
+
+
+def unicycle3d(n=(50, 50, 24)):
+    """3D unicycle vehicle, reach-avoid, +-6 sigma windows (stand-in for the 3D vehicle study).
+
+    x0+ = x0 + 0.1 v cos th, x1+ = x1 + 0.1 v sin th, th+ = th + 0.1 om on
+    [-5,5]^2 x [-pi,pi] (no wrap), v in {0.5,1,1.5,2}, om in {-1,-.5,0,.5,1}
+    (v-major), sigma = (0.05, 0.05, 0.02); target [3,4.5]^2 x all th,
+    avoid [-1,1] x [-3,1] x all th, eps 1e-8.
+    """
+    pi = math.pi
+    system = dict(kind="unicycle", dt=0.1, lb=[-5.0, -5.0, -pi], ub=[5.0, 5.0, pi], n=list(n),
+                  inputs=_grid_inputs([0.5, 1.0, 1.5, 2.0], [-1.0, -0.5, 0.0, 0.5, 1.0]),
+                  sigma=[0.05, 0.05, 0.02], k_sigma=6.0)
+    spec = dict(kind="reach_avoid", target=[[[3.0, 3.0, -pi], [4.5, 4.5, pi]]],
+                avoid=[[[-1.0, -3.0, -pi], [1.0, 1.0, pi]]], eps=1e-8, max_sweeps=100000)
+    return system, spec
+
+
+def room5d(cells=10):
+    """5D ring of rooms, stay-in-domain safety, +-6 sigma windows (stand-in for the 5D room study).
+
+    x_i+ = 0.85 x_i + 0.05 (x_{i-1} + x_{i+1}) + 0.75 + 0.25 u + w_i, indices
+    mod 5, u in {0,1,2,3}; [19,21]^5 with ``cells`` per dimension (10 -> width
+    0.2, 100,000 states); sigma 0.05; avoid = leaving the domain only.
+    """
+    d = 5
+    A = np.zeros((d, d))
+    for i in range(d):
+        A[i, i] = 0.85
+        A[i, (i - 1) % d] = 0.05
+        A[i, (i + 1) % d] = 0.05
+    system = dict(kind="affine", A=A, B=np.full((d, 1), 0.25), c=np.full(d, 0.75),
+                  lb=[19.0] * d, ub=[21.0] * d, n=[cells] * d,
+                  inputs=np.array([[0.0], [1.0], [2.0], [3.0]]),
+                  sigma=[0.05] * d, k_sigma=6.0)
+    spec = dict(kind="safety", target=[], avoid=[], eps=1e-8, max_sweeps=50)
+    return system, spec
+
+
+def random_linear(rng, d=None):
+    """One instance of the batched generator: 2D or 3D x+ = A x + B u + w.
+
+    A = rho M / specrad(M), M ~ N(0,1), rho ~ U(0.6, 0.95); B ~ N(0, 0.3^2);
+    10-60 cells per dimension on [-10,10]^d; inputs on a uniform grid in
+    [-1,1]^d with 2-5 points per axis and 4-25 points in total; sigma_i =
+    U(0.1, 0.5) cell widths; disjoint grid-aligned target and avoid boxes.
+    """
+    if d is None:
+        d = int(rng.integers(2, 4))
+    M = rng.normal(size=(d, d))
+    rho = rng.uniform(0.6, 0.95)
+    A = rho * M / max(abs(np.linalg.eigvals(M)))
+    B = rng.normal(scale=0.3, size=(d, d))
+    n = [int(x) for x in rng.integers(10, 61, size=d)]
+    while True:
+        k = [int(x) for x in rng.integers(2, 6, size=d)]
+        if 4 <= int(np.prod(k)) <= 25:
+            break
+    inputs = _grid_inputs(*[np.linspace(-1.0, 1.0, kk) for kk in k])
+    lb, ub = [-10.0] * d, [10.0] * d
+    w = [20.0 / ni for ni in n]
+    sigma = [rng.uniform(0.1, 0.5) * wi for wi in w]
+    boxes = []
+    for _ in range(2):
+        while True:
+            span = [int(rng.integers(1, max(2, ni // 4) + 1)) for ni in n]
+            start = [int(rng.integers(0, ni - sp + 1)) for ni, sp in zip(n, span)]
+            box = [[lb[i] + start[i] * w[i] for i in range(d)],
+                   [lb[i] + (start[i] + span[i]) * w[i] for i in range(d)]]
+            cells = [(start[i], start[i] + span[i]) for i in range(d)]
+            if not boxes or any(c[1] <= o[0] or o[1] <= c[0]
+                                for c, o in zip(cells, boxes[0][1])):
+                boxes.append((box, cells))
+                break
+    system = dict(kind="affine", A=A, B=B, c=np.zeros(d), lb=lb, ub=ub, n=n, inputs=inputs,
+                  sigma=sigma, k_sigma=6.0)
+    spec = dict(kind="reach_avoid", target=[boxes[0][0]], avoid=[boxes[1][0]], eps=1e-8,
+                max_sweeps=100000)
+    return system, spec
+
+
+def batched(count=384, seed=SEED):
+    rng = np.random.default_rng(seed)
+    return [random_linear(rng) for _ in range(count)]
+
+
+def tiny_affine(d=2, n=6, seed=1, k_sigma=6.0, n_inputs=3):
+    """A small random affine system for property and parity tests."""
+    rng = np.random.default_rng(seed)
+    M = rng.normal(size=(d, d))
+    A = 0.8 * M / max(abs(np.linalg.eigvals(M)))
+    B = rng.normal(scale=0.5, size=(d, 1))
+    system = dict(kind="affine", A=A, B=B, c=rng.normal(scale=0.2, size=d),
+                  lb=[-2.0] * d, ub=[2.0] * d, n=[n] * d,
+                  inputs=np.linspace(-1.0, 1.0, n_inputs).reshape(-1, 1),
+                  sigma=[0.3 * 4.0 / n] * d, k_sigma=k_sigma)
+    return system
+
+
+CONFIGS = {
+    "robot2d": robot2d,
+    "unicycle3d": unicycle3d,
+    "room5d": room5d,
+}
