@@ -1,0 +1,233 @@
+/*
+ * impact.h -- C ABI of the MI355X (gfx950) IMDP library.
+ *
+ * The library builds interval-MDP abstractions of gridded stochastic systems
+ *     x+ = f(x, u) + w,   w ~ N(0, diag(sigma^2)),
+ * and runs interval iteration over them (IMPaCT, arXiv 2401.03555):
+ *   - impact_build_imdp        : Def. 3.1 bounds, built as in Alg. 2, with
+ *                                the out-of-domain entry of Remark 4.1;
+ *   - impact_interval_iterate  : eq. (5.1)/(5.2), Alg. 3 (safety) and Alg. 4
+ *                                (reach-avoid; reachability when the avoid set
+ *                                is empty), the LP solved by the sorting method
+ *                                of Section 6.2.
+ * All arithmetic is IEEE FP64.  Every function returns a status code and never
+ * throws; on a negative status a message is available from impact_last_error()
+ * (thread-local) and outputs are unspecified.
+ *
+ * Conventions shared by every entry point
+ *  - Grid: dimension i has n[i] >= 1 cells tiling [lb[i], ub[i]], width
+ *    w_i = (ub_i - lb_i)/n_i, cell edge k = lb_i + k*w_i (edge n_i = ub_i).
+ *    States are the cells in C order (last dimension fastest); 1 <= dim <= 8.
+ *  - Inputs: a finite list (count x dim_u, row-major); row (s, u) has index
+ *    s * count + u.  dim_u == 0 with count == 1 gives an interval Markov
+ *    chain (Section 6.3): the policy is then identically 0.
+ *  - Row layout of the abstraction: for row (s,u) the entries are the cells of
+ *    its target window in C order over the window box, then OUT (leaving
+ *    [lb, ub]) and, when windowed, TAIL (in-domain mass outside the window,
+ *    lower bound 0).  Dense rows (k_sigma == 0) list every cell and have no
+ *    TAIL.
+ *  - Mean box: the per-dimension range of f over the source cell, padded
+ *    outward by 2^-48 times the sum of magnitudes of the terms; affine sums
+ *    are evaluated in index order as (sum_j a_ij x_j + sum_j b_ij u_j) + c_i,
+ *    the unicycle as x0 + (dt v) cos-range, x1 + (dt v) sin-range,
+ *    x2 + (dt om).  Windows are the cells meeting [m_lo - k sigma,
+ *    m_hi + k sigma], computed as floor(((m - k*sigma) - lb)/w).
+ *  - Streams: all device work is enqueued on impact_device.stream (a
+ *    hipStream_t; NULL = the null stream).  Calls synchronize that stream
+ *    before returning.
+ */
+#ifndef IMPACT_H
+#define IMPACT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IMPACT_MAX_DIM 8
+#define IMPACT_MAX_ROW 4096 /* longest supported row (entries incl. OUT/TAIL) */
+
+/* Status codes.  > 0: success with a flag; < 0: failure. */
+enum {
+  IMPACT_OK = 0,
+  IMPACT_NOT_CONVERGED = 1, /* a pass hit max_sweeps; outputs hold the current
+                               (sound) brackets */
+  IMPACT_E_INVAL = -1,      /* malformed argument                        */
+  IMPACT_E_NOMEM = -2,      /* the allocator returned NULL               */
+  IMPACT_E_HIP = -3,        /* a HIP runtime call failed                 */
+  IMPACT_E_UNSUPPORTED = -4 /* valid but outside the supported envelope  */
+};
+
+/* System kinds. */
+enum {
+  IMPACT_SYS_AFFINE = 0,  /* f = A x + B u + c                                  */
+  IMPACT_SYS_UNICYCLE = 1 /* f = (x0 + dt u0 cos x2, x1 + dt u0 sin x2, x2 + dt u1),
+                             dim_x = 3, dim_u = 2, no wrap of x2              */
+};
+
+/* Dynamics (Def. 2.1 restricted to additive Gaussian noise).  Host pointers,
+ * row-major, read during the call only.  A: dim_x*dim_x, B: dim_x*dim_u,
+ * c: dim_x (affine); dt (unicycle). */
+typedef struct {
+  int32_t kind, dim_x, dim_u;
+  const double *A, *B, *c;
+  double dt;
+} impact_system;
+
+/* Grid (the partition of X, Section 2).  Host pointers, dim entries each. */
+typedef struct {
+  int32_t dim;
+  const double *lb, *ub;
+  const int32_t *n;
+} impact_grid;
+
+/* Finite input set U-hat.  Host pointer, count x dim_u row-major. */
+typedef struct {
+  int32_t count, dim_u;
+  const double *values;
+} impact_inputs;
+
+/* Diagonal Gaussian noise (Section 4.1, NORMAL with diagonal covariance).
+ * Host pointer to dim_x standard deviations, each > 0. */
+typedef struct {
+  const double *sigma;
+} impact_noise;
+
+/* Storage of the built bounds. */
+enum {
+  IMPACT_STORE_AUTO = 0,    /* library's choice (currently BOUNDS)           */
+  IMPACT_STORE_BOUNDS = 1,  /* every entry's (lo, hi) kept in HBM            */
+  IMPACT_STORE_FACTORS = 2  /* per-dimension factors kept; entry products
+                               recomputed in every sweep                     */
+};
+
+/* Target window: k_sigma > 0 keeps cells within +-k_sigma standard
+ * deviations of the mean box plus a TAIL entry; k_sigma == 0 is dense. */
+typedef struct {
+  double k_sigma;
+  int32_t storage;
+} impact_window;
+
+/* Device memory and stream.  alloc/free may be NULL (hipMalloc/hipFree are
+ * used).  alloc(bytes, ctx) returns device memory or NULL; free(ptr, ctx)
+ * releases it.  stream is a hipStream_t. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *ctx);
+  void (*free)(void *ptr, void *ctx);
+  void *ctx;
+  void *stream;
+} impact_device;
+
+/* Opaque abstraction handle; owns its device buffers. */
+typedef struct impact_imdp impact_imdp;
+
+/*
+ * Build the abstraction (Def. 3.1; Alg. 2; Remark 4.1).  For every row (s,u)
+ * and every window cell t:
+ *   lo(s,u,t) = prod_i min(g_i(m_lo_i), g_i(m_hi_i)),
+ *   hi(s,u,t) = prod_i g_i(clamp(midpoint_i(t), m_lo_i, m_hi_i)),
+ * g_i(m) the N(m, sigma_i^2) mass of the cell's i-th side; OUT bounds the mass
+ * leaving [lb, ub], TAIL the in-domain mass outside the window.  The result is
+ * specification independent (labels are applied at iteration time).
+ * Arguments: host structs above; dev may be NULL (defaults).  *out receives
+ * the handle (release with impact_imdp_free).
+ * Errors: E_INVAL (bad dims/sizes/sigma/kind), E_NOMEM (allocation failed),
+ * E_UNSUPPORTED (a row longer than IMPACT_MAX_ROW), E_HIP.
+ */
+int impact_build_imdp(const impact_system *sys, const impact_grid *grid,
+                      const impact_inputs *inputs, const impact_noise *noise,
+                      const impact_window *window, const impact_device *dev,
+                      impact_imdp **out);
+
+/* Specification kinds (Section 3.1). */
+enum { IMPACT_SAFETY = 0, IMPACT_REACH = 1, IMPACT_REACH_AVOID = 2 };
+
+/* Specification.  Boxes are host arrays [n][2][dim] (lo then hi); a cell is
+ * labelled by its centre (closed boxes, widened by 1e-9 cell widths); avoid
+ * wins over target.  SAFETY: avoid boxes are the unsafe set, n_target must be
+ * 0.  REACH: n_avoid must be 0.  Leaving [lb, ub] is always unsafe / failure.
+ * pessimistic must be 1 (the paper's IMDP_lower = true policy).
+ * max_sweeps >= 1 caps each of the two passes. */
+typedef struct {
+  int32_t kind, n_target, n_avoid;
+  const double *target_boxes, *avoid_boxes;
+  int32_t pessimistic;
+  int64_t max_sweeps;
+} impact_spec;
+
+/*
+ * Interval iteration with the sorting-method LP (eq. (5.1)/(5.2); Alg. 3 and
+ * Alg. 4; Section 6.2).  Pass 1: V0 = 0, V1 = 1 on the SAFE cells; Jacobi
+ * sweeps; reach / reach-avoid take the minimising LP and the max over u,
+ * safety the maximising LP and the min over u; pi(s) is the optimising input
+ * of the V0 results (lowest index on exact ties).  Pass 2: reset, u fixed by
+ * pi, opposite LP direction.  Each pass runs while max(V1 - V0) > eps, at most
+ * spec->max_sweeps sweeps.
+ * Outputs (caller-owned DEVICE buffers of n_states elements, C order):
+ *   reach, reach-avoid: lo = V0 of pass 1, hi = V1 of pass 2;
+ *   safety: lo = 1 - V1 of pass 1, hi = 1 - V0 of pass 2 (safety probability);
+ *   target cells lo = hi = 1, avoid cells lo = hi = 0;
+ *   policy = input index on SAFE cells, -1 elsewhere.
+ * Returns IMPACT_OK, IMPACT_NOT_CONVERGED (a cap fired; outputs valid), or an
+ * error (E_INVAL, E_NOMEM, E_UNSUPPORTED, E_HIP).
+ */
+int impact_interval_iterate(impact_imdp *imdp, const impact_spec *spec, double eps,
+                            double *lo, double *hi, int32_t *policy);
+
+/* Statistics of the last impact_interval_iterate call on this handle. */
+typedef struct {
+  int64_t sweeps[2];    /* sweeps run in pass 1 / pass 2                 */
+  double gap[2];        /* max(V1 - V0) over SAFE cells at the end       */
+  int32_t converged[2]; /* 1 if the pass met eps                         */
+  int64_t n_safe;       /* number of SAFE cells                          */
+  int64_t updates[2];   /* (s,u)-row LP pairs solved per pass            */
+  double sweep_ms[2];   /* summed sweep-kernel time (only with timing on) */
+  double iterate_ms;    /* wall time of the call (only with timing on)   */
+} impact_iter_info;
+
+int impact_last_iter_info(const impact_imdp *imdp, impact_iter_info *info);
+
+/* Shape and footprint of a built abstraction. */
+typedef struct {
+  int64_t n_states, n_rows, n_entries; /* entries include OUT / TAIL      */
+  int32_t dim, n_inputs, windowed, storage;
+  int32_t max_row;       /* longest row (entries incl. OUT / TAIL)       */
+  int64_t device_bytes;  /* bytes held by the handle                     */
+  double build_ms;       /* build-kernel time, from HIP events           */
+} impact_imdp_info;
+
+int impact_imdp_get_info(const impact_imdp *imdp, impact_imdp_info *info);
+
+/*
+ * Copy rows [row0, row0 + nrows) of the abstraction out, in the row layout
+ * above (bounds are expanded from factors when FACTORS storage is in use).
+ * All pointers are DEVICE buffers owned by the caller:
+ *   window : nrows * 2 * dim int32 (klo[0..dim) then W[0..dim) per row)
+ *   ot     : nrows * 4 doubles (OUT lo, OUT hi, TAIL lo, TAIL hi)
+ *   counts : nrows int64 (window cells per row, i.e. excluding OUT / TAIL)
+ *   entries: may be NULL; else (sum of counts) * 2 doubles, (lo, hi) pairs
+ *            of the window cells of each row back to back (OUT/TAIL are in ot)
+ * Errors: E_INVAL on a bad range.
+ */
+int impact_imdp_export_rows(const impact_imdp *imdp, int64_t row0, int64_t nrows,
+                            int32_t *window, double *ot, int64_t *counts,
+                            double *entries);
+
+/* Enable (1) / disable (0) per-kernel HIP-event timing on this handle. */
+int impact_set_timing(impact_imdp *imdp, int32_t enable);
+
+/* Release the handle and every device buffer it owns.  NULL is a no-op. */
+void impact_imdp_free(impact_imdp *imdp);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *impact_last_error(void);
+
+/* Library version string. */
+const char *impact_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,523 @@
+// abi.hip -- the C ABI declared in include/impact.h: argument validation,
+// device allocation through the caller's allocator, and the host side of the
+// build and of interval iteration (sweep batches with a device-side stop test).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <string>
+#include <vector>
+
+#include "impact_internal.hpp"
+
+using namespace impact;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIP_TRY(expr)                                 \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) throw HipError{_e, #expr};  \
+  } while (0)
+
+struct NoMem {
+  size_t bytes;
+};
+
+}  // namespace
+
+struct impact_imdp {
+  impact_device dev{};
+  hipStream_t st = nullptr;
+  SysParams hp{};
+  SysParams* dp = nullptr;
+  double* dU = nullptr;
+  int64_t n_states = 0, n_rows = 0, n_cells = 0;
+  int32_t d = 0, nu = 0, windowed = 0, storage = IMPACT_STORE_BOUNDS, max_row = 0, fs = 0;
+  int64_t* row_off = nullptr;
+  int32_t* win = nullptr;
+  double4* ot = nullptr;
+  double2* ent = nullptr;
+  double2* fac = nullptr;
+  std::vector<void*> owned;
+  int64_t bytes = 0;
+  impact_iter_info last{};
+  bool timing = false;
+  bool hip_used = false;  // set before the first HIP call on this handle
+  double build_ms = 0.0;
+
+  void sync() {
+    if (hip_used) (void)hipStreamSynchronize(st);
+  }
+
+  void* alloc(size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    void* p = nullptr;
+    if (dev.alloc) {
+      p = dev.alloc(bytes, dev.ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    if (!p) throw NoMem{bytes};
+    return p;
+  }
+  void release(void* p) {
+    if (!p) return;
+    if (dev.free)
+      dev.free(p, dev.ctx);
+    else
+      (void)hipFree(p);
+  }
+  template <class T>
+  T* own(int64_t elems) {
+    T* p = (T*)alloc((size_t)elems * sizeof(T));
+    owned.push_back(p);
+    bytes += elems * (int64_t)sizeof(T);
+    return p;
+  }
+  ~impact_imdp() {
+    sync();
+    for (void* p : owned) release(p);
+  }
+};
+
+namespace {
+
+// Scoped temporaries of one call, returned to the caller's allocator on exit.
+struct Scratch {
+  impact_imdp* h;
+  std::vector<void*> ps;
+  explicit Scratch(impact_imdp* hh) : h(hh) {}
+  template <class T>
+  T* get(int64_t elems) {
+    T* p = (T*)h->alloc((size_t)(elems > 0 ? elems : 1) * sizeof(T));
+    ps.push_back(p);
+    return p;
+  }
+  ~Scratch() {
+    h->sync();
+    for (void* p : ps) h->release(p);
+  }
+};
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+int validate_build(const impact_system* sys, const impact_grid* grid, const impact_inputs* in,
+                   const impact_noise* noise, const impact_window* win) {
+  if (!sys || !grid || !in || !noise || !win) return fail(IMPACT_E_INVAL, "null argument");
+  const int d = grid->dim;
+  if (d < 1 || d > IMPACT_MAX_DIM) return fail(IMPACT_E_INVAL, "grid.dim must be in [1, 8]");
+  if (sys->dim_x != d) return fail(IMPACT_E_INVAL, "system.dim_x != grid.dim");
+  if (!grid->lb || !grid->ub || !grid->n) return fail(IMPACT_E_INVAL, "grid arrays are null");
+  int64_t ns = 1;
+  for (int i = 0; i < d; ++i) {
+    if (grid->n[i] < 1) return fail(IMPACT_E_INVAL, "grid.n must be >= 1");
+    if (!is_finite(grid->lb[i]) || !is_finite(grid->ub[i]) || !(grid->lb[i] < grid->ub[i]))
+      return fail(IMPACT_E_INVAL, "grid bounds must be finite with lb < ub");
+    ns *= grid->n[i];
+    if (ns > 0x7fffffffLL) return fail(IMPACT_E_UNSUPPORTED, "more than 2^31-1 states");
+  }
+  if (in->count < 1) return fail(IMPACT_E_INVAL, "inputs.count must be >= 1");
+  if (in->dim_u < 0 || in->dim_u > IMPACT_MAX_DIM || in->dim_u != sys->dim_u)
+    return fail(IMPACT_E_INVAL, "inputs.dim_u must equal system.dim_u and be in [0, 8]");
+  if (in->dim_u > 0 && !in->values) return fail(IMPACT_E_INVAL, "inputs.values is null");
+  for (int64_t k = 0; k < (int64_t)in->count * in->dim_u; ++k)
+    if (!is_finite(in->values[k])) return fail(IMPACT_E_INVAL, "non-finite input value");
+  if (!noise->sigma) return fail(IMPACT_E_INVAL, "noise.sigma is null");
+  for (int i = 0; i < d; ++i)
+    if (!is_finite(noise->sigma[i]) || !(noise->sigma[i] > 0.0))
+      return fail(IMPACT_E_INVAL, "noise.sigma must be finite and > 0");
+  if (!is_finite(win->k_sigma) || win->k_sigma < 0.0)
+    return fail(IMPACT_E_INVAL, "window.k_sigma must be finite and >= 0");
+  if (win->storage < IMPACT_STORE_AUTO || win->storage > IMPACT_STORE_FACTORS)
+    return fail(IMPACT_E_INVAL, "unknown window.storage");
+  if (sys->kind == IMPACT_SYS_AFFINE) {
+    if (!sys->A || !sys->c || (sys->dim_u > 0 && !sys->B))
+      return fail(IMPACT_E_INVAL, "affine system needs A, c (and B when dim_u > 0)");
+    for (int k = 0; k < d * d; ++k)
+      if (!is_finite(sys->A[k])) return fail(IMPACT_E_INVAL, "non-finite A");
+    for (int k = 0; k < d * sys->dim_u; ++k)
+      if (!is_finite(sys->B[k])) return fail(IMPACT_E_INVAL, "non-finite B");
+    for (int k = 0; k < d; ++k)
+      if (!is_finite(sys->c[k])) return fail(IMPACT_E_INVAL, "non-finite c");
+  } else if (sys->kind == IMPACT_SYS_UNICYCLE) {
+    if (d != 3 || sys->dim_u != 2) return fail(IMPACT_E_INVAL, "unicycle needs dim_x 3, dim_u 2");
+    if (!is_finite(sys->dt)) return fail(IMPACT_E_INVAL, "non-finite dt");
+  } else {
+    return fail(IMPACT_E_INVAL, "unknown system kind");
+  }
+  return IMPACT_OK;
+}
+
+void fill_params(SysParams& p, const impact_system* sys, const impact_grid* g,
+                 const impact_inputs* in, const impact_noise* nz, const impact_window* w) {
+  std::memset(&p, 0, sizeof(p));
+  const int d = g->dim;
+  p.kind = sys->kind;
+  p.d = d;
+  p.du = in->dim_u;
+  p.nu = in->count;
+  p.windowed = w->k_sigma > 0.0;
+  p.dt = sys->dt;
+  p.k_sigma = w->k_sigma;
+  if (sys->kind == IMPACT_SYS_AFFINE) {
+    for (int k = 0; k < d * d; ++k) p.A[k] = sys->A[k];
+    for (int k = 0; k < d * in->dim_u; ++k) p.B[k] = sys->B[k];
+    for (int k = 0; k < d; ++k) p.c[k] = sys->c[k];
+  }
+  int64_t ns = 1;
+  for (int i = 0; i < d; ++i) {
+    p.lb[i] = g->lb[i];
+    p.ub[i] = g->ub[i];
+    p.n[i] = g->n[i];
+    p.w[i] = (g->ub[i] - g->lb[i]) / (double)g->n[i];
+    p.sigma[i] = nz->sigma[i];
+    ns *= g->n[i];
+  }
+  int64_t s = 1;
+  for (int i = d - 1; i >= 0; --i) {
+    p.stride[i] = s;
+    s *= g->n[i];
+  }
+  p.n_states = ns;
+  p.n_rows = ns * in->count;
+}
+
+float event_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  return ms;
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const NoMem& e) {
+    return fail(IMPACT_E_NOMEM, "device allocation of " + std::to_string(e.bytes) + " bytes failed");
+  } catch (const HipError& e) {
+    return fail(IMPACT_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  } catch (const std::exception& e) {
+    return fail(IMPACT_E_INVAL, e.what());
+  } catch (...) {
+    return fail(IMPACT_E_INVAL, "unknown error");
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* impact_last_error(void) { return g_err.c_str(); }
+
+const char* impact_version(void) { return "impact-gfx950 0.1"; }
+
+int impact_build_imdp(const impact_system* sys, const impact_grid* grid,
+                      const impact_inputs* inputs, const impact_noise* noise,
+                      const impact_window* window, const impact_device* dev,
+                      impact_imdp** out) {
+  g_err.clear();
+  if (!out) return fail(IMPACT_E_INVAL, "out is null");
+  *out = nullptr;
+  int rc = validate_build(sys, grid, inputs, noise, window);
+  if (rc != IMPACT_OK) return rc;
+  impact_imdp* h = new impact_imdp();
+  if (dev) h->dev = *dev;
+  h->st = (hipStream_t)h->dev.stream;
+  rc = guarded([&]() -> int {
+    SysParams& p = h->hp;
+    fill_params(p, sys, grid, inputs, noise, window);
+    h->d = p.d;
+    h->nu = p.nu;
+    h->windowed = p.windowed;
+    h->n_states = p.n_states;
+    h->n_rows = p.n_rows;
+    h->storage = window->storage == IMPACT_STORE_FACTORS ? IMPACT_STORE_FACTORS
+                                                         : IMPACT_STORE_BOUNDS;
+    const int64_t R = h->n_rows;
+    // every allocation is requested before the first HIP call
+    h->dp = h->own<SysParams>(1);
+    h->dU = h->own<double>(std::max<int64_t>(1, (int64_t)p.nu * p.du));
+    h->win = h->own<int32_t>(R * 2 * p.d);
+    h->ot = h->own<double4>(R);
+    h->row_off = h->own<int64_t>(R + 1);
+    Scratch tmp(h);
+    int64_t* cnt = tmp.get<int64_t>(R);
+    int32_t* maxima = tmp.get<int32_t>(2);
+    const int64_t te = scan_tmp_elems(R);
+    int64_t* stmp = tmp.get<int64_t>(te);
+
+    h->hip_used = true;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipMemcpyAsync(h->dp, &p, sizeof(SysParams), hipMemcpyHostToDevice, h->st));
+    if ((int64_t)p.nu * p.du > 0)
+      HIP_TRY(hipMemcpyAsync(h->dU, inputs->values, sizeof(double) * p.nu * p.du,
+                             hipMemcpyHostToDevice, h->st));
+    HIP_TRY(hipMemsetAsync(maxima, 0, 2 * sizeof(int32_t), h->st));
+    if (e0) HIP_TRY(hipEventRecord(e0, h->st));
+    HIP_TRY(launch_row_geom(h->dp, h->dU, R, h->win, h->ot, cnt, maxima, h->st));
+    HIP_TRY(exclusive_scan_i64(cnt, h->row_off, R, stmp, te, h->st));
+    int64_t total = 0;
+    int32_t mx[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(&total, h->row_off + R, sizeof(int64_t), hipMemcpyDeviceToHost, h->st));
+    HIP_TRY(hipMemcpyAsync(mx, maxima, sizeof(mx), hipMemcpyDeviceToHost, h->st));
+    HIP_TRY(hipStreamSynchronize(h->st));
+    h->n_cells = total;
+    h->max_row = mx[0];
+    h->fs = mx[1] > 0 ? mx[1] : 1;
+    if (h->max_row > IMPACT_MAX_ROW)
+      return fail(IMPACT_E_UNSUPPORTED, "a row has " + std::to_string(h->max_row) +
+                                            " entries (max " + std::to_string(IMPACT_MAX_ROW) + ")");
+    if (h->fs > kMaxFactors)
+      return fail(IMPACT_E_UNSUPPORTED, "per-row factor list longer than " +
+                                            std::to_string(kMaxFactors));
+    if (h->storage == IMPACT_STORE_FACTORS)
+      h->fac = h->own<double2>(R * (int64_t)h->fs);
+    else
+      h->ent = h->own<double2>(total);
+    HIP_TRY(launch_expand(h->dp, h->dU, R, h->win, h->row_off, h->ent, h->fac, h->fs, p.d, h->st));
+    if (e1) HIP_TRY(hipEventRecord(e1, h->st));
+    HIP_TRY(hipStreamSynchronize(h->st));
+    if (e0) {
+      h->build_ms = event_ms(e0, e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
+    return IMPACT_OK;
+  });
+  if (rc != IMPACT_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return IMPACT_OK;
+}
+
+int impact_set_timing(impact_imdp* h, int32_t enable) {
+  if (!h) return fail(IMPACT_E_INVAL, "null handle");
+  h->timing = enable != 0;
+  return IMPACT_OK;
+}
+
+int impact_imdp_get_info(const impact_imdp* h, impact_imdp_info* info) {
+  if (!h || !info) return fail(IMPACT_E_INVAL, "null argument");
+  std::memset(info, 0, sizeof(*info));
+  info->n_states = h->n_states;
+  info->n_rows = h->n_rows;
+  info->n_entries = h->n_cells + h->n_rows * (1 + h->windowed);
+  info->dim = h->d;
+  info->n_inputs = h->nu;
+  info->windowed = h->windowed;
+  info->storage = h->storage;
+  info->max_row = h->max_row;
+  info->device_bytes = h->bytes;
+  info->build_ms = h->build_ms;
+  return IMPACT_OK;
+}
+
+int impact_last_iter_info(const impact_imdp* h, impact_iter_info* info) {
+  if (!h || !info) return fail(IMPACT_E_INVAL, "null argument");
+  *info = h->last;
+  return IMPACT_OK;
+}
+
+int impact_imdp_export_rows(const impact_imdp* hc, int64_t row0, int64_t nrows, int32_t* window,
+                            double* ot, int64_t* counts, double* entries) {
+  g_err.clear();
+  if (!hc) return fail(IMPACT_E_INVAL, "null handle");
+  impact_imdp* h = const_cast<impact_imdp*>(hc);
+  if (row0 < 0 || nrows < 0 || row0 + nrows > h->n_rows)
+    return fail(IMPACT_E_INVAL, "row range out of bounds");
+  if (nrows > 0 && (!window || !ot || !counts))
+    return fail(IMPACT_E_INVAL, "window/ot/counts must be device buffers");
+  return guarded([&]() -> int {
+    HIP_TRY(launch_export(h->dp, row0, nrows, h->win, h->ot, h->row_off, h->ent, h->fac, h->fs,
+                          h->d, h->windowed, window, ot, counts, entries, h->st));
+    HIP_TRY(hipStreamSynchronize(h->st));
+    return IMPACT_OK;
+  });
+}
+
+int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps, double* lo,
+                            double* hi, int32_t* policy) {
+  g_err.clear();
+  if (!h || !spec) return fail(IMPACT_E_INVAL, "null argument");
+  if (!lo || !hi || !policy) return fail(IMPACT_E_INVAL, "lo/hi/policy must be device buffers");
+  if (spec->kind < IMPACT_SAFETY || spec->kind > IMPACT_REACH_AVOID)
+    return fail(IMPACT_E_INVAL, "unknown spec kind");
+  if (spec->n_target < 0 || spec->n_avoid < 0) return fail(IMPACT_E_INVAL, "negative box count");
+  if ((spec->n_target > 0 && !spec->target_boxes) || (spec->n_avoid > 0 && !spec->avoid_boxes))
+    return fail(IMPACT_E_INVAL, "box array is null");
+  if (spec->kind == IMPACT_SAFETY && spec->n_target != 0)
+    return fail(IMPACT_E_INVAL, "safety takes no target boxes");
+  if (spec->kind == IMPACT_REACH && spec->n_avoid != 0)
+    return fail(IMPACT_E_INVAL, "reachability takes no avoid boxes (use reach-avoid)");
+  if (spec->pessimistic != 1)
+    return fail(IMPACT_E_UNSUPPORTED, "only the pessimistic policy is implemented");
+  if (spec->max_sweeps < 1) return fail(IMPACT_E_INVAL, "max_sweeps must be >= 1");
+  if (!is_finite(eps) || !(eps > 0.0)) return fail(IMPACT_E_INVAL, "eps must be finite and > 0");
+  const int d = h->d;
+  for (int64_t k = 0; k < (int64_t)spec->n_target * 2 * d; ++k)
+    if (std::isnan(spec->target_boxes[k])) return fail(IMPACT_E_INVAL, "NaN in target box");
+  for (int64_t k = 0; k < (int64_t)spec->n_avoid * 2 * d; ++k)
+    if (std::isnan(spec->avoid_boxes[k])) return fail(IMPACT_E_INVAL, "NaN in avoid box");
+  for (int b = 0; b < spec->n_target; ++b)
+    for (int i = 0; i < d; ++i)
+      if (spec->target_boxes[b * 2 * d + i] > spec->target_boxes[b * 2 * d + d + i])
+        return fail(IMPACT_E_INVAL, "target box with lo > hi");
+  for (int b = 0; b < spec->n_avoid; ++b)
+    for (int i = 0; i < d; ++i)
+      if (spec->avoid_boxes[b * 2 * d + i] > spec->avoid_boxes[b * 2 * d + d + i])
+        return fail(IMPACT_E_INVAL, "avoid box with lo > hi");
+
+  return guarded([&]() -> int {
+    const auto t_start = std::chrono::steady_clock::now();
+    const int64_t N = h->n_states;
+    const bool safety = spec->kind == IMPACT_SAFETY;
+    Scratch tmp(h);
+    double* tb = tmp.get<double>((int64_t)spec->n_target * 2 * d);
+    double* ab = tmp.get<double>((int64_t)spec->n_avoid * 2 * d);
+    int8_t* cls = tmp.get<int8_t>(N);
+    int64_t* flag = tmp.get<int64_t>(N);
+    int64_t* pos = tmp.get<int64_t>(N + 1);
+    const int64_t te = scan_tmp_elems(N);
+    int64_t* stmp = tmp.get<int64_t>(te);
+    int32_t* safe = tmp.get<int32_t>(N);
+    double2* vb[2] = {tmp.get<double2>(N), tmp.get<double2>(N)};
+    int32_t* pi = tmp.get<int32_t>(N);
+    Ctrl* ctrl = tmp.get<Ctrl>(1);
+    h->hip_used = true;
+
+    if (spec->n_target > 0)
+      HIP_TRY(hipMemcpyAsync(tb, spec->target_boxes, sizeof(double) * spec->n_target * 2 * d,
+                             hipMemcpyHostToDevice, h->st));
+    if (spec->n_avoid > 0)
+      HIP_TRY(hipMemcpyAsync(ab, spec->avoid_boxes, sizeof(double) * spec->n_avoid * 2 * d,
+                             hipMemcpyHostToDevice, h->st));
+    HIP_TRY(launch_label(h->dp, N, tb, spec->n_target, ab, spec->n_avoid, cls, flag, h->st));
+    HIP_TRY(exclusive_scan_i64(flag, pos, N, stmp, te, h->st));
+    int64_t n_safe = 0;
+    HIP_TRY(hipMemcpyAsync(&n_safe, pos + N, sizeof(int64_t), hipMemcpyDeviceToHost, h->st));
+    HIP_TRY(hipStreamSynchronize(h->st));
+    HIP_TRY(launch_compact(cls, pos, N, safe, h->st));
+
+    impact_iter_info info{};
+    info.n_safe = n_safe;
+    std::vector<hipEvent_t> evs;
+    auto new_event = [&]() {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      evs.push_back(e);
+      return e;
+    };
+    Ctrl hc{};
+    for (int pass = 0; pass < 2; ++pass) {
+      SweepArgs a{};
+      a.row_off = h->row_off;
+      a.win = h->win;
+      a.ot = h->ot;
+      a.ent = h->ent;
+      a.fac = h->fac;
+      a.sys = h->dp;
+      a.pi = pi;
+      a.safe = safe;
+      a.ctrl = ctrl;
+      a.n_safe = n_safe;
+      a.fs = h->fs;
+      a.pass = pass;
+      a.reach = !safety;
+      a.maximise = pass == 0 ? safety : !safety;
+      a.nu = h->nu;
+      a.d = d;
+      a.windowed = h->windowed;
+      a.storage = h->storage;
+      a.out_val = safety ? 1.0 : 0.0;
+      a.inputs_per_state = pass == 0 ? h->nu : 1;
+      int G = 1;
+      if (h->max_row <= 512) G = std::max(1, 4 / a.inputs_per_state);
+      while (G > 1 && G * a.inputs_per_state > 256) --G;
+      if (a.inputs_per_state > 256)
+        return fail(IMPACT_E_UNSUPPORTED, "more than 256 inputs per state");
+      a.states_per_block = G;
+
+      HIP_TRY(launch_init_values(cls, N, safety, vb[0], vb[1], pass == 0 ? pi : nullptr, h->st));
+      HIP_TRY(launch_ctrl_init(ctrl, eps, spec->max_sweeps, h->st));
+      int64_t sweeps = 0;
+      double gap = n_safe > 0 ? 1.0 : 0.0;
+      int converged = gap <= eps;
+      float sweep_ms = 0.f;
+      if (!converged) {
+        int64_t launched = 0, chunk = 2;
+        std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
+        for (;;) {
+          const int64_t n = std::min<int64_t>(chunk, spec->max_sweeps - launched);
+          if (n <= 0) break;
+          for (int64_t k = 0; k < n; ++k) {
+            const int64_t idx = launched + k;
+            a.vin = vb[idx & 1];
+            a.vout = vb[(idx + 1) & 1];
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (h->timing) {
+              e0 = new_event();
+              e1 = new_event();
+              HIP_TRY(hipEventRecord(e0, h->st));
+            }
+            HIP_TRY(launch_sweep(a, h->max_row, h->st));
+            if (h->timing) {
+              HIP_TRY(hipEventRecord(e1, h->st));
+              marks.emplace_back(e0, e1);
+            }
+            HIP_TRY(launch_finish(ctrl, h->st));
+          }
+          launched += n;
+          HIP_TRY(hipMemcpyAsync(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->st));
+          HIP_TRY(hipStreamSynchronize(h->st));
+          if (hc.done) break;
+          chunk = std::min<int64_t>(chunk * 2, 64);
+        }
+        sweeps = hc.sweeps;
+        gap = hc.gap;
+        converged = hc.converged;
+        for (int64_t k = 0; k < sweeps && k < (int64_t)marks.size(); ++k)
+          sweep_ms += event_ms(marks[k].first, marks[k].second);
+      }
+      info.sweeps[pass] = sweeps;
+      info.gap[pass] = gap;
+      info.converged[pass] = converged;
+      info.updates[pass] = sweeps * n_safe * a.inputs_per_state;
+      info.sweep_ms[pass] = sweep_ms;
+      HIP_TRY(launch_finalize(cls, N, vb[sweeps & 1], pi, pass, safety, pass == 0 ? lo : hi,
+                              policy, h->st));
+    }
+    HIP_TRY(hipStreamSynchronize(h->st));
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    info.iterate_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+            .count();
+    h->last = info;
+    return (info.converged[0] && info.converged[1]) ? IMPACT_OK : IMPACT_NOT_CONVERGED;
+  });
+}
+
+void impact_imdp_free(impact_imdp* h) {
+  if (!h) return;
+  delete h;
+}
+
+}  // extern "C"

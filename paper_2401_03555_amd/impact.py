@@ -1,0 +1,293 @@
+"""Python binding of the gfx950 IMDP library (``libimpact.so``, C ABI in
+``include/impact.h``).
+
+Argument marshalling only: every step of construction and iteration runs in
+the library's HIP kernels.  PyTorch supplies device memory (through its
+caching allocator, passed to the library as alloc/free callbacks) and the
+stream.  There is no fallback: if the library is not built, importing
+``lib()`` raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libimpact.so")
+
+OK, NOT_CONVERGED = 0, 1
+E_INVAL, E_NOMEM, E_HIP, E_UNSUPPORTED = -1, -2, -3, -4
+SYS_KINDS = {"affine": 0, "unicycle": 1}
+SPEC_KINDS = {"safety": 0, "reach": 1, "reach_avoid": 2}
+STORAGE = {"auto": 0, "bounds": 1, "factors": 2}
+
+# Every function the header declares (checked by the test suite).
+EXPORTS = ["impact_build_imdp", "impact_interval_iterate", "impact_last_iter_info",
+           "impact_imdp_get_info", "impact_imdp_export_rows", "impact_set_timing",
+           "impact_imdp_free", "impact_last_error", "impact_version"]
+
+_pd = C.POINTER(C.c_double)
+_pi32 = C.POINTER(C.c_int32)
+_pi64 = C.POINTER(C.c_int64)
+
+
+class System(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dim_x", C.c_int32), ("dim_u", C.c_int32),
+                ("A", _pd), ("B", _pd), ("c", _pd), ("dt", C.c_double)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("lb", _pd), ("ub", _pd), ("n", _pi32)]
+
+
+class Inputs(C.Structure):
+    _fields_ = [("count", C.c_int32), ("dim_u", C.c_int32), ("values", _pd)]
+
+
+class Noise(C.Structure):
+    _fields_ = [("sigma", _pd)]
+
+
+class Window(C.Structure):
+    _fields_ = [("k_sigma", C.c_double), ("storage", C.c_int32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Device(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p),
+                ("stream", C.c_void_p)]
+
+
+class Spec(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_target", C.c_int32), ("n_avoid", C.c_int32),
+                ("target_boxes", _pd), ("avoid_boxes", _pd), ("pessimistic", C.c_int32),
+                ("max_sweeps", C.c_int64)]
+
+
+class IterInfo(C.Structure):
+    _fields_ = [("sweeps", C.c_int64 * 2), ("gap", C.c_double * 2),
+                ("converged", C.c_int32 * 2), ("n_safe", C.c_int64),
+                ("updates", C.c_int64 * 2), ("sweep_ms", C.c_double * 2),
+                ("iterate_ms", C.c_double)]
+
+
+class ImdpInfo(C.Structure):
+    _fields_ = [("n_states", C.c_int64), ("n_rows", C.c_int64), ("n_entries", C.c_int64),
+                ("dim", C.c_int32), ("n_inputs", C.c_int32), ("windowed", C.c_int32),
+                ("storage", C.c_int32), ("max_row", C.c_int32), ("device_bytes", C.c_int64),
+                ("build_ms", C.c_double)]
+
+
+class ImpactError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"impact error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python paper_2401_03555_amd/build_lib.py`")
+        L = C.CDLL(LIB_PATH)
+        L.impact_build_imdp.restype = C.c_int
+        L.impact_build_imdp.argtypes = [C.POINTER(System), C.POINTER(Grid), C.POINTER(Inputs),
+                                        C.POINTER(Noise), C.POINTER(Window), C.POINTER(Device),
+                                        C.POINTER(C.c_void_p)]
+        L.impact_interval_iterate.restype = C.c_int
+        L.impact_interval_iterate.argtypes = [C.c_void_p, C.POINTER(Spec), C.c_double, _pd, _pd,
+                                              _pi32]
+        L.impact_last_iter_info.restype = C.c_int
+        L.impact_last_iter_info.argtypes = [C.c_void_p, C.POINTER(IterInfo)]
+        L.impact_imdp_get_info.restype = C.c_int
+        L.impact_imdp_get_info.argtypes = [C.c_void_p, C.POINTER(ImdpInfo)]
+        L.impact_imdp_export_rows.restype = C.c_int
+        L.impact_imdp_export_rows.argtypes = [C.c_void_p, C.c_int64, C.c_int64, _pi32, _pd,
+                                              _pi64, _pd]
+        L.impact_set_timing.restype = C.c_int
+        L.impact_set_timing.argtypes = [C.c_void_p, C.c_int32]
+        L.impact_imdp_free.restype = None
+        L.impact_imdp_free.argtypes = [C.c_void_p]
+        L.impact_last_error.restype = C.c_char_p
+        L.impact_last_error.argtypes = []
+        L.impact_version.restype = C.c_char_p
+        L.impact_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc < 0:
+        raise ImpactError(rc, lib().impact_last_error().decode())
+    return rc
+
+
+def _f64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_pd)
+
+
+def _torch_ptr(t, ctype):
+    return C.cast(C.c_void_p(t.data_ptr()), C.POINTER(ctype))
+
+
+class _TorchDevice:
+    """alloc/free callbacks backed by torch's caching allocator, plus the stream."""
+
+    def __init__(self, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.cuda.current_device()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+
+        def _alloc(nbytes, _ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:  # out of memory -> NULL -> IMPACT_E_NOMEM
+                return None
+
+        def _free(ptr, _ctx):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+        self.struct = Device(self._alloc, self._free, None, C.c_void_p(self.stream.cuda_stream))
+
+
+class _Marshal:
+    def __init__(self, system):
+        self.lb, self.ub = _f64(system["lb"]), _f64(system["ub"])
+        self.n = np.ascontiguousarray(np.asarray(system["n"], dtype=np.int32))
+        d = len(self.lb)
+        inputs = np.asarray(system["inputs"], dtype=np.float64)
+        if inputs.ndim == 1:
+            inputs = inputs.reshape(-1, 1) if inputs.size else np.zeros((1, 0))
+        self.inputs = np.ascontiguousarray(inputs)
+        du = self.inputs.shape[1]
+        self.sigma = _f64(system["sigma"])
+        self.grid = Grid(d, _dptr(self.lb), _dptr(self.ub), self.n.ctypes.data_as(_pi32))
+        self.inp = Inputs(self.inputs.shape[0], du, _dptr(self.inputs) if du else None)
+        self.noise = Noise(_dptr(self.sigma))
+        kind = system["kind"]
+        if kind == "affine":
+            self.A = _f64(system["A"]).reshape(d, d)
+            self.B = _f64(system["B"]).reshape(d, du) if du else _f64(np.zeros(1))
+            self.c = _f64(system.get("c", np.zeros(d)))
+            self.sys = System(0, d, du, _dptr(self.A), _dptr(self.B), _dptr(self.c), 0.0)
+        elif kind == "unicycle":
+            self.sys = System(1, d, du, None, None, None, float(system["dt"]))
+        else:
+            raise ValueError(f"unknown system kind {kind!r}")
+
+
+class Imdp:
+    """A built abstraction resident in HBM (owns a library handle)."""
+
+    def __init__(self, handle, dev):
+        self._h = handle
+        self._dev = dev  # keeps the allocator callbacks alive as long as the handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        i = ImdpInfo()
+        _check(lib().impact_imdp_get_info(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in ImdpInfo._fields_}
+
+    def set_timing(self, enable=True):
+        _check(lib().impact_set_timing(self._h, int(bool(enable))))
+
+    def export_rows(self, row0, nrows, entries=True):
+        """Rows [row0, row0 + nrows) as numpy: window, ot, counts (window cells), entries."""
+        torch = self._dev.torch
+        info = self.info()
+        d = info["dim"]
+        dev = f"cuda:{self._dev.device}"
+        win = torch.empty((nrows, 2 * d), dtype=torch.int32, device=dev)
+        ot = torch.empty((nrows, 4), dtype=torch.float64, device=dev)
+        cnt = torch.empty(nrows, dtype=torch.int64, device=dev)
+        _check(lib().impact_imdp_export_rows(self._h, row0, nrows, _torch_ptr(win, C.c_int32),
+                                             _torch_ptr(ot, C.c_double),
+                                             _torch_ptr(cnt, C.c_int64), None))
+        out = dict(win=win.cpu().numpy(), ot=ot.cpu().numpy(), counts=cnt.cpu().numpy())
+        if entries:
+            total = int(out["counts"].sum())
+            ent = torch.empty((max(total, 1), 2), dtype=torch.float64, device=dev)
+            _check(lib().impact_imdp_export_rows(self._h, row0, nrows, _torch_ptr(win, C.c_int32),
+                                                 _torch_ptr(ot, C.c_double),
+                                                 _torch_ptr(cnt, C.c_int64),
+                                                 _torch_ptr(ent, C.c_double)))
+            out["entries"] = ent.cpu().numpy()[:total]
+        return out
+
+    def iterate(self, spec, eps=None, max_sweeps=None, out=None):
+        """Interval iteration; returns dict(lo, hi, policy (torch cuda), status, info)."""
+        torch = self._dev.torch
+        d = self.info()["dim"]
+        n = self.info()["n_states"]
+        tb = _f64(np.asarray(spec.get("target") or np.zeros((0, 2, d))).reshape(-1, 2, d))
+        ab = _f64(np.asarray(spec.get("avoid") or np.zeros((0, 2, d))).reshape(-1, 2, d))
+        s = Spec(SPEC_KINDS[spec["kind"]], tb.shape[0], ab.shape[0],
+                 _dptr(tb) if tb.size else None, _dptr(ab) if ab.size else None, 1,
+                 int(max_sweeps if max_sweeps is not None else spec.get("max_sweeps", 100000)))
+        dev = f"cuda:{self._dev.device}"
+        if out is None:
+            lo = torch.empty(n, dtype=torch.float64, device=dev)
+            hi = torch.empty(n, dtype=torch.float64, device=dev)
+            pol = torch.empty(n, dtype=torch.int32, device=dev)
+        else:
+            lo, hi, pol = out
+        rc = _check(lib().impact_interval_iterate(
+            self._h, C.byref(s), float(eps if eps is not None else spec["eps"]),
+            _torch_ptr(lo, C.c_double), _torch_ptr(hi, C.c_double), _torch_ptr(pol, C.c_int32)))
+        return dict(lo=lo, hi=hi, policy=pol, status=rc, info=self.last_iter_info())
+
+    def last_iter_info(self):
+        i = IterInfo()
+        _check(lib().impact_last_iter_info(self._h, C.byref(i)))
+        return dict(sweeps=tuple(i.sweeps), gap=tuple(i.gap), converged=tuple(i.converged),
+                    n_safe=i.n_safe, updates=tuple(i.updates), sweep_ms=tuple(i.sweep_ms),
+                    iterate_ms=i.iterate_ms)
+
+    def free(self):
+        if self._h:
+            lib().impact_imdp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build_imdp(system, k_sigma=None, storage="bounds", stream=None, timing=False):
+    """Build the abstraction of ``system`` on the current CUDA(HIP) device."""
+    m = _Marshal(system)
+    dev = _TorchDevice(stream)
+    w = Window(float(system.get("k_sigma", 0.0) if k_sigma is None else k_sigma),
+               STORAGE[storage])
+    h = C.c_void_p()
+    _check(lib().impact_build_imdp(C.byref(m.sys), C.byref(m.grid), C.byref(m.inp),
+                                   C.byref(m.noise), C.byref(w), C.byref(dev.struct), C.byref(h)))
+    imdp = Imdp(h.value, dev)
+    if timing:
+        imdp.set_timing(True)
+    return imdp
+
+
+def version():
+    return lib().impact_version().decode()

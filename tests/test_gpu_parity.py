@@ -1,0 +1,328 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bounds: windows identical, entries / OUT / TAIL within 1e-12 absolute.
+Values: within 1e-9; policies identical except at ties (an input whose oracle
+LP value is within 1e-12 of the optimum).  Sweep counts identical.
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_03555_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+BOUND_TOL = 1e-12
+VALUE_TOL = 1e-9
+TIE_TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def I():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_03555_amd import impact
+    impact.lib()  # raises if the library is missing
+    return impact
+
+
+# ---------------------------------------------------------------------------
+# helpers
+# ---------------------------------------------------------------------------
+
+def compare_rows(gpu, orc, nrows, d, label):
+    """gpu: export of rows [row0, row0 + nrows); orc: oracle build of the same rows."""
+    assert gpu["win"].shape == (nrows, 2 * d)
+    win_bad = np.where((gpu["win"] != orc["win"]).any(1))[0]
+    assert len(win_bad) == 0, f"{label}: window mismatch in rows {win_bad[:10]}"
+    extra = 1 + int(orc["windowed"])
+    ncell = np.diff(orc["row_ptr"]) - extra
+    assert np.array_equal(gpu["counts"], ncell)
+    sel = np.ones(orc["row_ptr"][-1], bool)
+    sel[orc["row_ptr"][1:] - 1] = False
+    if extra == 2:
+        sel[orc["row_ptr"][1:] - 2] = False
+    olo, ohi = orc["lo"][sel], orc["hi"][sel]
+    glo, ghi = gpu["entries"][:, 0], gpu["entries"][:, 1]
+    assert len(glo) == len(olo)
+    dlo = np.abs(glo - olo).max(initial=0.0)
+    dhi = np.abs(ghi - ohi).max(initial=0.0)
+    dot = np.abs(gpu["ot"] - orc["ot"]).max(initial=0.0)
+    say(f"{label}: rows {nrows} cells {len(olo)} max|dlo| {dlo:.2e} max|dhi| {dhi:.2e} "
+        f"max|d ot| {dot:.2e}")
+    assert dlo <= BOUND_TOL and dhi <= BOUND_TOL and dot <= BOUND_TOL
+
+
+def gpu_build(I, system, storage="bounds"):
+    return I.build_imdp(system, storage=storage)
+
+
+def check_policy(pol_g, pol_o, q0, cls, reach, label):
+    safe = np.where(cls == 0)[0]
+    diff = safe[pol_g[safe] != pol_o[safe]]
+    bad = []
+    for s in diff:
+        q = q0[s]
+        best = q.max() if reach else q.min()
+        got = q[pol_g[s]]
+        if (reach and got < best - TIE_TOL) or (not reach and got > best + TIE_TOL):
+            bad.append(s)
+    say(f"{label}: policy differs on {len(diff)} of {len(safe)} SAFE cells, "
+        f"{len(bad)} not ties")
+    assert not bad, f"{label}: policy mismatch beyond ties at {bad[:10]}"
+
+
+def compare_iter(g, o, cls, reach, label, q0=None):
+    lo, hi = g["lo"].cpu().numpy(), g["hi"].cpu().numpy()
+    pol = g["policy"].cpu().numpy()
+    dlo = np.abs(lo - o["lo"]).max()
+    dhi = np.abs(hi - o["hi"]).max()
+    say(f"{label}: sweeps gpu {g['info']['sweeps']} oracle {tuple(o['sweeps'])} "
+        f"max|dlo| {dlo:.2e} max|dhi| {dhi:.2e} status {g['status']}")
+    assert tuple(g["info"]["sweeps"]) == tuple(o["sweeps"])
+    assert dlo <= VALUE_TOL and dhi <= VALUE_TOL
+    if q0 is not None:
+        check_policy(pol, np.asarray(o["policy"]), q0, cls, reach, label)
+    else:
+        assert np.array_equal(pol, o["policy"])
+
+
+SMALL_SYSTEMS = {
+    "affine2_window": lambda: W.tiny_affine(d=2, n=9, seed=2),
+    "affine3_window": lambda: W.tiny_affine(d=3, n=6, seed=3),
+    "affine2_dense": lambda: W.tiny_affine(d=2, n=7, seed=8, k_sigma=0.0),
+    "affine1_window": lambda: dict(kind="affine", A=[[0.9]], B=[[0.4]], c=[0.1], lb=[-3.0],
+                                   ub=[3.0], n=[61], inputs=[[-1.0], [0.0], [1.0]],
+                                   sigma=[0.08], k_sigma=6.0),
+    "unicycle_small": lambda: dict(W.unicycle3d(n=(10, 10, 6))[0], sigma=[0.3, 0.3, 0.2]),
+    "robot2d": lambda: W.robot2d()[0],
+    "room5d_4": lambda: W.room5d(cells=4)[0],
+}
+
+
+# ---------------------------------------------------------------------------
+# bound construction
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(SMALL_SYSTEMS))
+def test_build_parity_all_rows(I, name):
+    system = SMALL_SYSTEMS[name]()
+    say(f"build parity: {name}")
+    g = gpu_build(I, system)
+    info = g.info()
+    R, d = info["n_rows"], info["dim"]
+    o = oracle.build(system, system["k_sigma"])
+    assert info["n_entries"] == o["row_ptr"][-1]
+    compare_rows(g.export_rows(0, R), o, R, d, name)
+
+
+@pytest.mark.parametrize("name", ["unicycle3d", "room5d"])
+def test_build_parity_full_size_sampled(I, name):
+    system = (W.unicycle3d()[0] if name == "unicycle3d" else W.room5d()[0])
+    say(f"build parity (sampled rows, full size): {name}")
+    g = gpu_build(I, system)
+    info = g.info()
+    R, d = info["n_rows"], info["dim"]
+    rng = np.random.default_rng(5)
+    starts = sorted(set([0, R - 40] + list(rng.integers(0, R - 40, size=24))))
+    for s0 in starts:
+        rows = np.arange(s0, s0 + 40)
+        o = oracle.build(system, system["k_sigma"], rows=rows)
+        compare_rows(g.export_rows(int(s0), 40), o, 40, d, f"{name}[{s0}:{s0 + 40}]")
+    assert info["max_row"] <= 4096
+
+
+def test_factor_storage_matches_bound_storage(I):
+    system = W.tiny_affine(d=3, n=6, seed=4)
+    a = gpu_build(I, system, "bounds")
+    b = gpu_build(I, system, "factors")
+    R = a.info()["n_rows"]
+    ea, eb = a.export_rows(0, R), b.export_rows(0, R)
+    for k in ("win", "ot", "counts", "entries"):
+        assert np.array_equal(ea[k], eb[k]), k
+    spec = dict(kind="reach_avoid", target=[[[0.0, 0.0, 0.0], [1.0, 1.0, 1.0]]],
+                avoid=[[[-1.5, -1.5, -1.5], [-0.5, -0.5, -0.5]]], eps=1e-8, max_sweeps=5000)
+    ra, rb = a.iterate(spec), b.iterate(spec)
+    for k in ("lo", "hi", "policy"):
+        assert bool((ra[k] == rb[k]).all()), k
+
+
+# ---------------------------------------------------------------------------
+# interval iteration
+# ---------------------------------------------------------------------------
+
+SPECS = {
+    "affine2_window": dict(kind="reach_avoid", target=[[[0.5, 0.5], [1.5, 1.5]]],
+                           avoid=[[[-1.5, -1.5], [-0.5, -0.5]]]),
+    "affine3_window": dict(kind="reach", target=[[[0.0, 0.0, 0.0], [1.3, 1.3, 1.3]]], avoid=[]),
+    "affine2_dense": dict(kind="safety", target=[], avoid=[[[-0.5, -0.5], [0.5, 0.5]]]),
+    "affine1_window": dict(kind="reach_avoid", target=[[[1.0], [2.0]]], avoid=[[[-0.5], [0.0]]]),
+    "unicycle_small": dict(kind="reach_avoid", target=[[[2.0, 2.0, -4.0], [5.0, 5.0, 4.0]]],
+                           avoid=[[[-1.0, -1.0, -4.0], [1.0, 1.0, 4.0]]]),
+    "room5d_4": dict(kind="safety", target=[], avoid=[]),
+}
+
+
+@pytest.mark.parametrize("name", list(SPECS))
+def test_iterate_parity_small(I, name):
+    system = SMALL_SYSTEMS[name]()
+    spec = dict(SPECS[name], eps=1e-8, max_sweeps=3000 if name != "room5d_4" else 40)
+    say(f"iterate parity: {name} {spec['kind']}")
+    g = gpu_build(I, system)
+    rg = g.iterate(spec)
+    m = oracle.build(system, system["k_sigma"])
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    ro = oracle.iterate(m["n_states"], m["n_inputs"], m["row_ptr"], m["target"], m["lo"], m["hi"],
+                        cls, spec["kind"], spec["eps"], spec["max_sweeps"], want_q0=True)
+    assert rg["status"] == ro["status"]
+    compare_iter(rg, ro, cls, spec["kind"] != "safety", name, q0=ro["q0"])
+
+
+def test_iterate_parity_robot2d_converged(I):
+    with open(os.path.join(HERE, "golden", "robot2d_oracle.json")) as f:
+        gold = json.load(f)
+    system, spec = W.robot2d()
+    g = gpu_build(I, system)
+    rg = g.iterate(spec)
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    q0 = np.array([[np.nan if x is None else x for x in row] for row in gold["q0"]])
+    o = dict(lo=np.array(gold["lo"]), hi=np.array(gold["hi"]), policy=np.array(gold["policy"]),
+             sweeps=gold["sweeps"])
+    compare_iter(rg, o, cls, True, "robot2d (converged)", q0=q0)
+    assert rg["status"] == 0
+
+
+def test_iterate_parity_unicycle_full_size_fixed_sweeps(I):
+    system, spec = W.unicycle3d()
+    K = 2
+    say("unicycle3d full size, 2 sweeps per pass")
+    g = gpu_build(I, system)
+    rg = g.iterate(spec, max_sweeps=K)
+    m = oracle.build(system, system["k_sigma"])
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    ro = oracle.iterate(m["n_states"], m["n_inputs"], m["row_ptr"], m["target"], m["lo"], m["hi"],
+                        cls, spec["kind"], spec["eps"], K, want_q0=True)
+    assert rg["status"] == ro["status"] == 1
+    compare_iter(rg, ro, cls, True, "unicycle3d K=2", q0=ro["q0"])
+
+
+def test_iterate_properties_unicycle_full_size(I):
+    system, spec = W.unicycle3d()
+    g = gpu_build(I, system)
+    r = g.iterate(spec, max_sweeps=20000)
+    lo, hi = r["lo"].cpu().numpy(), r["hi"].cpu().numpy()
+    pol = r["policy"].cpu().numpy()
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    info = r["info"]
+    say(f"unicycle3d full: status {r['status']} info {info}")
+    assert info["n_safe"] == 53664
+    assert (lo >= -1e-15).all() and (hi <= 1 + 1e-12).all()
+    assert (lo <= hi + 1e-12).all()
+    assert set(np.unique(pol[cls == 0])) <= set(range(20)) and (pol[cls != 0] == -1).all()
+    assert (lo[cls == 1] == 1).all() and (lo[cls == 2] == 0).all()
+    if r["status"] == 0:
+        assert max(info["gap"]) <= spec["eps"]
+    # determinism: a second solve is bitwise identical
+    r2 = g.iterate(spec, max_sweeps=20000)
+    for k in ("lo", "hi", "policy"):
+        assert bool((r[k] == r2[k]).all()), k
+
+
+def test_room5d_full_size_fixed_sweeps_properties(I):
+    system, spec = W.room5d()
+    g = gpu_build(I, system)
+    info = g.info()
+    say(f"room5d full build: {info}")
+    r = g.iterate(spec, max_sweeps=3)
+    lo, hi = r["lo"].cpu().numpy(), r["hi"].cpu().numpy()
+    assert r["status"] == 1 and r["info"]["sweeps"] == (3, 3)
+    # FP64 rounding can put V a few ulps outside [0, 1] (the oracle does the same)
+    assert (lo >= -1e-12).all() and (hi <= 1 + 1e-12).all() and (lo <= hi + 1e-12).all()
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+def test_empty_safe_set_runs_no_sweeps(I):
+    system = W.tiny_affine(d=2, n=5, seed=3)
+    spec = dict(kind="reach", target=[[[-2.0, -2.0], [2.0, 2.0]]], avoid=[], eps=1e-8,
+                max_sweeps=10)
+    r = gpu_build(I, system).iterate(spec)
+    assert r["status"] == 0 and r["info"]["sweeps"] == (0, 0) and r["info"]["n_safe"] == 0
+    assert bool((r["lo"] == 1).all()) and bool((r["policy"] == -1).all())
+
+
+def test_imc_single_input(I):
+    system = W.tiny_affine(d=2, n=8, seed=14, n_inputs=1)
+    spec = dict(kind="reach", target=[[[0.0, 0.0], [1.0, 1.0]]], avoid=[], eps=1e-8,
+                max_sweeps=5000)
+    rg = gpu_build(I, system).iterate(spec)
+    ro = oracle.solve(system, system["k_sigma"], "reach", spec["target"], None, 1e-8, 5000)
+    compare_iter(rg, ro, ro["cls"], True, "imc")
+
+
+def test_rows_leaving_the_domain_have_only_out_and_tail(I):
+    # the mean of every row sits far outside [lb, ub]: empty windows
+    system = dict(kind="affine", A=[[1.0]], B=[[0.0]], c=[50.0], lb=[-1.0], ub=[1.0], n=[8],
+                  inputs=[[0.0]], sigma=[0.1], k_sigma=6.0)
+    g = gpu_build(I, system)
+    e = g.export_rows(0, 8)
+    o = oracle.build(system, 6.0)
+    assert (e["counts"] == 0).all()
+    compare_rows(e, o, 8, 1, "empty windows")
+    r = g.iterate(dict(kind="safety", target=[], avoid=[], eps=1e-8, max_sweeps=10))
+    assert r["status"] == 0 and bool((r["hi"].abs() < 1e-12).all())
+
+
+def test_longest_supported_row_and_rejection(I):
+    import paper_2401_03555_amd.impact as imp
+    ok = dict(kind="affine", A=np.eye(2) * 0.5, B=np.zeros((2, 1)), c=np.zeros(2),
+              lb=[-1.0, -1.0], ub=[1.0, 1.0], n=[63, 64], inputs=[[0.0]], sigma=[0.4, 0.4],
+              k_sigma=0.0)
+    g = gpu_build(I, ok)
+    assert g.info()["max_row"] == 63 * 64 + 1
+    spec = dict(kind="reach_avoid", target=[[[0.5, 0.5], [1.0, 1.0]]],
+                avoid=[[[-1.0, -1.0], [-0.5, -0.5]]], eps=1e-8, max_sweeps=2)
+    rg = g.iterate(spec)
+    m = oracle.build(ok, 0.0)
+    cls = oracle.label(ok, spec["target"], spec["avoid"])
+    ro = oracle.iterate(m["n_states"], 1, m["row_ptr"], m["target"], m["lo"], m["hi"], cls,
+                        "reach_avoid", 1e-8, 2)
+    compare_iter(rg, ro, cls, True, "4033-entry rows")
+    too_long = dict(ok, n=[64, 64])
+    with pytest.raises(imp.ImpactError) as ei:
+        gpu_build(I, too_long)
+    assert ei.value.code == imp.E_UNSUPPORTED
+
+
+def test_ragged_rows_mix_wave_and_block_paths(I):
+    # windows from 1 cell to > 512 entries inside one abstraction
+    system = dict(kind="affine", A=np.diag([0.5, 1.0]), B=np.array([[1.0], [0.0]]),
+                  c=np.zeros(2), lb=[-4.0, -4.0], ub=[4.0, 4.0], n=[40, 40],
+                  inputs=[[-3.0], [0.0], [3.0]], sigma=[0.02, 0.9], k_sigma=6.0)
+    g = gpu_build(I, system)
+    info = g.info()
+    say(f"ragged: max_row {info['max_row']}")
+    assert info["max_row"] > 512
+    o = oracle.build(system, 6.0)
+    compare_rows(g.export_rows(0, info["n_rows"]), o, info["n_rows"], 2, "ragged")
+    spec = dict(kind="reach_avoid", target=[[[2.0, -1.0], [3.0, 1.0]]],
+                avoid=[[[-1.0, -4.0], [0.0, 4.0]]], eps=1e-8, max_sweeps=300)
+    rg = g.iterate(spec)
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    ro = oracle.iterate(o["n_states"], 3, o["row_ptr"], o["target"], o["lo"], o["hi"], cls,
+                        "reach_avoid", 1e-8, 300, want_q0=True)
+    compare_iter(rg, ro, cls, True, "ragged", q0=ro["q0"])
