@@ -183,8 +183,12 @@ typedef struct {
   int32_t converged[2]; /* 1 if the pass met eps                         */
   int64_t n_safe;       /* number of SAFE cells                          */
   int64_t updates[2];   /* (s,u)-row LP pairs solved per pass            */
-  double sweep_ms[2];   /* summed sweep-kernel time (only with timing on) */
-  double iterate_ms;    /* wall time of the call (only with timing on)   */
+  int64_t launches[2];  /* sweep-kernel launches per pass (a launch after
+                           the stop test fired exits at once)            */
+  double sweep_ms[2];   /* HIP-event time of the launches that swept
+                           (timing on; else 0)                           */
+  double launch_ms[2];  /* HIP-event time of every sweep launch (timing on) */
+  double iterate_ms;    /* host wall time of the call                    */
 } impact_iter_info;
 
 int impact_last_iter_info(const impact_imdp *imdp, impact_iter_info *info);

@@ -458,12 +458,17 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
 
       HIP_TRY(launch_init_values(cls, N, safety, vb[0], vb[1], pass == 0 ? pi : nullptr, h->st));
       HIP_TRY(launch_ctrl_init(ctrl, eps, spec->max_sweeps, h->st));
-      int64_t sweeps = 0;
+      int64_t sweeps = 0, launched = 0;
       double gap = n_safe > 0 ? 1.0 : 0.0;
       int converged = gap <= eps;
-      float sweep_ms = 0.f;
+      float sweep_ms = 0.f, launch_ms = 0.f;
       if (!converged) {
-        int64_t launched = 0, chunk = 2;
+        // Sweeps go out in batches between host polls of the control block.
+        // The batch length is the number of sweeps still needed if the gap
+        // keeps contracting at its last observed rate (at most 64), so that
+        // few launches run after the stop test has fired.
+        int64_t chunk = 2, prev_sweeps = 0;
+        double prev_gap = 1.0;
         std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
         for (;;) {
           const int64_t n = std::min<int64_t>(chunk, spec->max_sweeps - launched);
@@ -489,19 +494,34 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
           HIP_TRY(hipMemcpyAsync(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->st));
           HIP_TRY(hipStreamSynchronize(h->st));
           if (hc.done) break;
-          chunk = std::min<int64_t>(chunk * 2, 64);
+          int64_t next = std::min<int64_t>(chunk * 2, 64);
+          if (hc.sweeps > prev_sweeps && hc.gap > 0.0 && hc.gap < prev_gap) {
+            const double rate = std::pow(hc.gap / prev_gap, 1.0 / (double)(hc.sweeps - prev_sweeps));
+            if (rate > 0.0 && rate < 1.0) {
+              const double need = std::ceil(std::log(eps / hc.gap) / std::log(rate));
+              if (need >= 1.0 && need < (double)next) next = (int64_t)need;
+            }
+          }
+          prev_sweeps = hc.sweeps;
+          prev_gap = hc.gap;
+          chunk = std::max<int64_t>(1, next);
         }
         sweeps = hc.sweeps;
         gap = hc.gap;
         converged = hc.converged;
-        for (int64_t k = 0; k < sweeps && k < (int64_t)marks.size(); ++k)
-          sweep_ms += event_ms(marks[k].first, marks[k].second);
+        for (int64_t k = 0; k < (int64_t)marks.size(); ++k) {
+          const float ms = event_ms(marks[k].first, marks[k].second);
+          launch_ms += ms;
+          if (k < sweeps) sweep_ms += ms;
+        }
       }
       info.sweeps[pass] = sweeps;
       info.gap[pass] = gap;
       info.converged[pass] = converged;
       info.updates[pass] = sweeps * n_safe * a.inputs_per_state;
       info.sweep_ms[pass] = sweep_ms;
+      info.launch_ms[pass] = launch_ms;
+      info.launches[pass] = launched;
       HIP_TRY(launch_finalize(cls, N, vb[sweeps & 1], pi, pass, safety, pass == 0 ? lo : hi,
                               policy, h->st));
     }

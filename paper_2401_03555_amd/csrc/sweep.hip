@@ -304,17 +304,20 @@ __device__ void solve_row(const SweepArgs& a, const SysParams& p, int64_t row, i
   q1 = lp_value<E, NW>(rs, rs.v1, r, mx, g, xk);
 }
 
+template <int PASS>
 __device__ __forceinline__ int64_t item_row(const SweepArgs& a, int64_t s0, int m, int U) {
   const int gi = m / U, ui = m - gi * U;
   const int64_t s = a.safe[s0 + gi];
-  const int u = a.pass == 0 ? ui : a.pi[s];
+  const int u = PASS == 0 ? ui : a.pi[s];
   return s * a.nu + u;
 }
 
 // WAVE_E: largest per-lane element count of single-wavefront rows (row
 // length <= 64 * WAVE_E); BLOCK_E: largest per-thread count of workgroup rows
 // (row length <= 256 * BLOCK_E), 0 when every row fits one wavefront.
-template <int WAVE_E, int BLOCK_E>
+// PASS 0: all inputs (policy pass); PASS 1: the input fixed by the policy.
+// The two passes are separate kernel symbols so that profiles tell them apart.
+template <int WAVE_E, int BLOCK_E, int PASS>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
   if (a.ctrl->done) return;
   __shared__ uint64_t xk[BLOCK_E > 0 ? 64 * kWaves * BLOCK_E : 1];
@@ -332,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
   if constexpr (BLOCK_E > 0) {
     // rows longer than one wavefront's capacity: the whole workgroup
     for (int m = 0; m < items; ++m) {
-      const int64_t row = item_row(a, s0, m, U);
+      const int64_t row = item_row<PASS>(a, s0, m, U);
       const int n = (int)(a.row_off[row + 1] - a.row_off[row]) + extra;
       if (n <= 64 * WAVE_E) continue;
       double q0, q1;
@@ -350,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
   }
   // short rows: one wavefront each
   for (int m = wv; m < items; m += kWaves) {
-    const int64_t row = item_row(a, s0, m, U);
+    const int64_t row = item_row<PASS>(a, s0, m, U);
     const int n = (int)(a.row_off[row + 1] - a.row_off[row]) + extra;
     if (n > 64 * WAVE_E) continue;
     double q0, q1;
@@ -383,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
       if (a.reach ? (q1 > b1) : (q1 < b1)) b1 = q1;
     }
     a.vout[s] = make_double2(b0, b1);
-    if (a.pass == 0) a.pi[s] = arg;
+    if (PASS == 0) a.pi[s] = arg;
     gap = b1 - b0;
     if (!(gap > 0.0)) gap = 0.0;
   }
@@ -531,27 +534,32 @@ hipError_t launch_ctrl_init(Ctrl* c, double eps, int64_t cap, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(const SweepArgs& a, int32_t max_row, hipStream_t st) {
-  if (a.n_safe == 0) return hipSuccess;
+template <int PASS>
+static hipError_t launch_sweep_pass(const SweepArgs& a, int32_t max_row, hipStream_t st) {
   const int64_t blocks = (a.n_safe + a.states_per_block - 1) / a.states_per_block;
   const dim3 g((unsigned)blocks), b(kBlock);
   if (max_row <= 64)
-    hipLaunchKernelGGL((k_sweep<1, 0>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_sweep<1, 0, PASS>), g, b, 0, st, a);
   else if (max_row <= 128)
-    hipLaunchKernelGGL((k_sweep<2, 0>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_sweep<2, 0, PASS>), g, b, 0, st, a);
   else if (max_row <= 256)
-    hipLaunchKernelGGL((k_sweep<4, 0>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_sweep<4, 0, PASS>), g, b, 0, st, a);
   else if (max_row <= 512)
-    hipLaunchKernelGGL((k_sweep<8, 0>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_sweep<8, 0, PASS>), g, b, 0, st, a);
   else if (max_row <= 1024)
-    hipLaunchKernelGGL((k_sweep<8, 4>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_sweep<8, 4, PASS>), g, b, 0, st, a);
   else if (max_row <= 2048)
-    hipLaunchKernelGGL((k_sweep<8, 8>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_sweep<8, 8, PASS>), g, b, 0, st, a);
   else if (max_row <= kMaxRow)
-    hipLaunchKernelGGL((k_sweep<8, 16>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_sweep<8, 16, PASS>), g, b, 0, st, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+hipError_t launch_sweep(const SweepArgs& a, int32_t max_row, hipStream_t st) {
+  if (a.n_safe == 0) return hipSuccess;
+  return a.pass == 0 ? launch_sweep_pass<0>(a, max_row, st) : launch_sweep_pass<1>(a, max_row, st);
 }
 
 hipError_t launch_finish(Ctrl* c, hipStream_t st) {

@@ -70,7 +70,8 @@ class Spec(C.Structure):
 class IterInfo(C.Structure):
     _fields_ = [("sweeps", C.c_int64 * 2), ("gap", C.c_double * 2),
                 ("converged", C.c_int32 * 2), ("n_safe", C.c_int64),
-                ("updates", C.c_int64 * 2), ("sweep_ms", C.c_double * 2),
+                ("updates", C.c_int64 * 2), ("launches", C.c_int64 * 2),
+                ("sweep_ms", C.c_double * 2), ("launch_ms", C.c_double * 2),
                 ("iterate_ms", C.c_double)]
 
 
@@ -259,7 +260,8 @@ class Imdp:
         i = IterInfo()
         _check(lib().impact_last_iter_info(self._h, C.byref(i)))
         return dict(sweeps=tuple(i.sweeps), gap=tuple(i.gap), converged=tuple(i.converged),
-                    n_safe=i.n_safe, updates=tuple(i.updates), sweep_ms=tuple(i.sweep_ms),
+                    n_safe=i.n_safe, updates=tuple(i.updates), launches=tuple(i.launches),
+                    sweep_ms=tuple(i.sweep_ms), launch_ms=tuple(i.launch_ms),
                     iterate_ms=i.iterate_ms)
 
     def free(self):

@@ -312,17 +312,19 @@ def test_ragged_rows_mix_wave_and_block_paths(I):
     # windows from 1 cell to > 512 entries inside one abstraction
     system = dict(kind="affine", A=np.diag([0.5, 1.0]), B=np.array([[1.0], [0.0]]),
                   c=np.zeros(2), lb=[-4.0, -4.0], ub=[4.0, 4.0], n=[40, 40],
-                  inputs=[[-3.0], [0.0], [3.0]], sigma=[0.02, 0.9], k_sigma=6.0)
+                  inputs=[[-3.0], [0.0], [3.0]], sigma=[0.2, 0.9], k_sigma=6.0)
     g = gpu_build(I, system)
     info = g.info()
     say(f"ragged: max_row {info['max_row']}")
     assert info["max_row"] > 512
+    counts = g.export_rows(0, info["n_rows"], entries=False)["counts"] + 2
+    assert (counts <= 64).any() and ((counts > 64) & (counts <= 512)).any()
     o = oracle.build(system, 6.0)
     compare_rows(g.export_rows(0, info["n_rows"]), o, info["n_rows"], 2, "ragged")
     spec = dict(kind="reach_avoid", target=[[[2.0, -1.0], [3.0, 1.0]]],
-                avoid=[[[-1.0, -4.0], [0.0, 4.0]]], eps=1e-8, max_sweeps=300)
+                avoid=[[[-1.0, -4.0], [0.0, 4.0]]], eps=1e-8, max_sweeps=40)
     rg = g.iterate(spec)
     cls = oracle.label(system, spec["target"], spec["avoid"])
     ro = oracle.iterate(o["n_states"], 3, o["row_ptr"], o["target"], o["lo"], o["hi"], cls,
-                        "reach_avoid", 1e-8, 300, want_q0=True)
+                        "reach_avoid", 1e-8, 40, want_q0=True)
     compare_iter(rg, ro, cls, True, "ragged", q0=ro["q0"])
