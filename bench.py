@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--workload", default="unicycle3d",
                     choices=["unicycle3d", "robot2d", "room5d"])
     ap.add_argument("--storage", default="bounds", choices=["bounds", "factors"])
+    ap.add_argument("--sweep-mode", default="auto", choices=["auto", "per_row", "state_box"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
 
@@ -113,7 +114,8 @@ def main():
     max_sweeps = spec["max_sweeps"]
 
     def step(timing=False):
-        imdp = impact.build_imdp(system, storage=args.storage, timing=timing)
+        imdp = impact.build_imdp(system, storage=args.storage, timing=timing,
+                                 sweep_mode=args.sweep_mode)
         r = imdp.iterate(spec, max_sweeps=max_sweeps)
         return imdp, r
 
@@ -159,6 +161,9 @@ def main():
         "config": {
             "workload": desc,
             "storage": args.storage,
+            "sweep_mode": args.sweep_mode,
+            "max_row": binfo["max_row"],
+            "max_box": binfo["max_box"],
             "n_states": binfo["n_states"],
             "n_inputs": binfo["n_inputs"],
             "n_entries": binfo["n_entries"],
@@ -175,7 +180,8 @@ def main():
             "served_p99_ms": None,
         },
         "roofline": {
-            "kernel": "k_sweep policy pass (all inputs per SAFE state)",
+            "kernel": ("k_sweep_sb" if (args.sweep_mode != "per_row" and binfo["max_row"] <= 512)
+                       else "k_sweep") + " policy pass (all inputs per SAFE state)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -141,6 +141,21 @@ int impact_build_imdp(const impact_system *sys, const impact_grid *grid,
                       const impact_window *window, const impact_device *dev,
                       impact_imdp **out);
 
+/*
+ * Build n abstractions with one launch of each construction kernel over the
+ * rows of all of them (the parallel loop of Alg. 2 spanning every system).
+ * sys, grid, inputs, noise, window are arrays of n structs (host); all windows
+ * must use the same storage mode.  out[i] receives the handle of system i;
+ * each is released with impact_imdp_free, and the shared device storage goes
+ * when the last of them is released.  Results equal n separate
+ * impact_build_imdp calls.  Errors as impact_build_imdp (the message names
+ * the failing system); on error no handle is returned.
+ */
+int impact_build_imdp_batch(int32_t n, const impact_system *sys, const impact_grid *grid,
+                            const impact_inputs *inputs, const impact_noise *noise,
+                            const impact_window *window, const impact_device *dev,
+                            impact_imdp **out);
+
 /* Specification kinds (Section 3.1). */
 enum { IMPACT_SAFETY = 0, IMPACT_REACH = 1, IMPACT_REACH_AVOID = 2 };
 
@@ -198,6 +213,8 @@ typedef struct {
   int64_t n_states, n_rows, n_entries; /* entries include OUT / TAIL      */
   int32_t dim, n_inputs, windowed, storage;
   int32_t max_row;       /* longest row (entries incl. OUT / TAIL)       */
+  int64_t max_box;       /* largest bounding box of one state's row windows
+                            (cells; the unit sorted once per state)      */
   int64_t device_bytes;  /* bytes held by the handle                     */
   double build_ms;       /* build-kernel time, from HIP events           */
 } impact_imdp_info;
@@ -219,10 +236,23 @@ int impact_imdp_export_rows(const impact_imdp *imdp, int64_t row0, int64_t nrows
                             int32_t *window, double *ot, int64_t *counts,
                             double *entries);
 
+/* How interval iteration orders entries (all give the same LP values).
+ *   AUTO       : STATE_BOX when every row has at most 512 entries, else PER_ROW
+ *   PER_ROW    : one bitonic sort per (state, input) row
+ *   STATE_BOX  : one bitonic sort per state over the bounding box of its rows'
+ *                windows; each row takes its order from it (the order of a
+ *                subset of a sorted list is the subset's sorted order).  Used
+ *                only when every row has at most 512 entries; states whose box
+ *                exceeds 512 cells sort per row. */
+enum { IMPACT_SWEEP_AUTO = 0, IMPACT_SWEEP_PER_ROW = 1, IMPACT_SWEEP_STATE_BOX = 2 };
+
+int impact_set_sweep_mode(impact_imdp *imdp, int32_t mode);
+
 /* Enable (1) / disable (0) per-kernel HIP-event timing on this handle. */
 int impact_set_timing(impact_imdp *imdp, int32_t enable);
 
-/* Release the handle and every device buffer it owns.  NULL is a no-op. */
+/* Release the handle; its device buffers go with the last handle of its build.
+ * NULL is a no-op. */
 void impact_imdp_free(impact_imdp *imdp);
 
 /* Message for the last failing call on this thread ("" if none). */

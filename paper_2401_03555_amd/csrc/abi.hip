@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -39,40 +40,35 @@ struct NoMem {
 
 }  // namespace
 
-struct impact_imdp {
+// Device buffers of one build (one or many systems), shared by the handles
+// (views) of the systems it holds and released with the last of them.
+struct Storage {
   impact_device dev{};
   hipStream_t st = nullptr;
-  SysParams hp{};
-  SysParams* dp = nullptr;
-  double* dU = nullptr;
-  int64_t n_states = 0, n_rows = 0, n_cells = 0;
-  int32_t d = 0, nu = 0, windowed = 0, storage = IMPACT_STORE_BOUNDS, max_row = 0, fs = 0;
-  int64_t* row_off = nullptr;
-  int32_t* win = nullptr;
-  double4* ot = nullptr;
-  double2* ent = nullptr;
-  double2* fac = nullptr;
+  bool hip_used = false;  // set before the first HIP call
   std::vector<void*> owned;
   int64_t bytes = 0;
-  impact_iter_info last{};
-  bool timing = false;
-  bool hip_used = false;  // set before the first HIP call on this handle
-  double build_ms = 0.0;
+  SysParams* d_sys = nullptr;
+  double* d_U = nullptr;
+  int32_t* win = nullptr;
+  double4* ot = nullptr;
+  int64_t* row_off = nullptr;
+  double2* ent = nullptr;
+  double2* fac = nullptr;
 
   void sync() {
     if (hip_used) (void)hipStreamSynchronize(st);
   }
-
-  void* alloc(size_t bytes) {
-    if (bytes == 0) bytes = 8;
+  void* alloc(size_t nbytes) {
+    if (nbytes == 0) nbytes = 8;
     void* p = nullptr;
     if (dev.alloc) {
-      p = dev.alloc(bytes, dev.ctx);
-    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = dev.alloc(nbytes, dev.ctx);
+    } else if (hipMalloc(&p, nbytes) != hipSuccess) {
       (void)hipGetLastError();
       p = nullptr;
     }
-    if (!p) throw NoMem{bytes};
+    if (!p) throw NoMem{nbytes};
     return p;
   }
   void release(void* p) {
@@ -84,35 +80,62 @@ struct impact_imdp {
   }
   template <class T>
   T* own(int64_t elems) {
-    T* p = (T*)alloc((size_t)elems * sizeof(T));
+    T* p = (T*)alloc((size_t)(elems > 0 ? elems : 1) * sizeof(T));
     owned.push_back(p);
     bytes += elems * (int64_t)sizeof(T);
     return p;
   }
-  ~impact_imdp() {
+  ~Storage() {
     sync();
     for (void* p : owned) release(p);
   }
 };
 
+// One system's abstraction: a view into a Storage.
+struct impact_imdp {
+  std::shared_ptr<Storage> store;
+  int32_t inst = 0;
+  hipStream_t st = nullptr;
+  SysParams hp{};
+  const SysParams* dp = nullptr;
+  const int64_t* row_off = nullptr;  // indexed by this system's row
+  const int32_t* win = nullptr;
+  const double4* ot = nullptr;
+  const double2* ent = nullptr;      // indexed by row_off values
+  const double2* fac = nullptr;
+  int64_t n_states = 0, n_rows = 0, n_cells = 0;
+  int32_t d = 0, nu = 0, windowed = 0, storage = IMPACT_STORE_BOUNDS, max_row = 0, fs = 0;
+  int64_t max_box = 0;  // largest bounding box of one state's row windows (cells)
+  int32_t sweep_mode = IMPACT_SWEEP_AUTO;
+  impact_iter_info last{};
+  bool timing = false;
+  double build_ms = 0.0;
+
+  void sync() { store->sync(); }
+  void* alloc(size_t nbytes) { return store->alloc(nbytes); }
+  void release(void* p) { store->release(p); }
+};
+
 namespace {
 
 // Scoped temporaries of one call, returned to the caller's allocator on exit.
-struct Scratch {
-  impact_imdp* h;
+template <class Owner>
+struct ScratchT {
+  Owner* h;
   std::vector<void*> ps;
-  explicit Scratch(impact_imdp* hh) : h(hh) {}
+  explicit ScratchT(Owner* hh) : h(hh) {}
   template <class T>
   T* get(int64_t elems) {
     T* p = (T*)h->alloc((size_t)(elems > 0 ? elems : 1) * sizeof(T));
     ps.push_back(p);
     return p;
   }
-  ~Scratch() {
+  ~ScratchT() {
     h->sync();
     for (void* p : ps) h->release(p);
   }
 };
+using Scratch = ScratchT<impact_imdp>;
 
 bool is_finite(double x) { return std::isfinite(x); }
 
@@ -226,6 +249,173 @@ const char* impact_last_error(void) { return g_err.c_str(); }
 
 const char* impact_version(void) { return "impact-gfx950 0.1"; }
 
+// Build n systems with one launch of each construction kernel over all of
+// their rows (Alg. 2's parallel loop spans every system).
+static int build_many(int32_t n, const impact_system* sys, const impact_grid* grid,
+                      const impact_inputs* inputs, const impact_noise* noise,
+                      const impact_window* window, const impact_device* dev, impact_imdp** out) {
+  for (int32_t i = 0; i < n; ++i) out[i] = nullptr;
+  for (int32_t i = 0; i < n; ++i) {
+    const int rc = validate_build(&sys[i], &grid[i], &inputs[i], &noise[i], &window[i]);
+    if (rc != IMPACT_OK) {
+      if (n > 1) g_err = "system " + std::to_string(i) + ": " + g_err;
+      return rc;
+    }
+    const bool fi = window[i].storage == IMPACT_STORE_FACTORS;
+    const bool f0 = window[0].storage == IMPACT_STORE_FACTORS;
+    if (fi != f0) return fail(IMPACT_E_INVAL, "all systems of a batch share one storage mode");
+  }
+  auto store = std::make_shared<Storage>();
+  if (dev) store->dev = *dev;
+  store->st = (hipStream_t)store->dev.stream;
+  const bool factors = window[0].storage == IMPACT_STORE_FACTORS;
+  std::vector<SysParams> hp(n);
+  std::vector<int64_t> row_base(n + 1, 0), state_base(n + 1, 0), u_off(n + 1, 0);
+  int64_t win_total = 0;
+  int32_t d_max = 1;
+  for (int32_t i = 0; i < n; ++i) {
+    fill_params(hp[i], &sys[i], &grid[i], &inputs[i], &noise[i], &window[i]);
+    hp[i].row_base = row_base[i];
+    hp[i].state_base = state_base[i];
+    hp[i].win_base = win_total;
+    row_base[i + 1] = row_base[i] + hp[i].n_rows;
+    state_base[i + 1] = state_base[i] + hp[i].n_states;
+    u_off[i + 1] = u_off[i] + (int64_t)hp[i].nu * hp[i].du;
+    win_total += hp[i].n_rows * 2 * hp[i].d;
+    d_max = std::max(d_max, hp[i].d);
+  }
+  const int64_t R = row_base[n], S = state_base[n];
+  std::vector<int64_t> fsz(n, 1);
+  std::vector<int32_t> max_row(n, 0);
+  std::vector<unsigned long long> bm(n, 0);
+  int64_t total = 0;
+  float build_ms = 0.f;
+  const int rc = guarded([&]() -> int {
+    Storage* st = store.get();
+    // every allocation of the first phase is requested before the first HIP call
+    st->d_sys = st->own<SysParams>(n);
+    st->d_U = st->own<double>(std::max<int64_t>(1, u_off[n]));
+    st->win = st->own<int32_t>(win_total);
+    st->ot = st->own<double4>(R);
+    st->row_off = st->own<int64_t>(R + 1);
+    ScratchT<Storage> tmp(st);
+    int64_t* cnt = tmp.get<int64_t>(R);
+    int32_t* maxima = tmp.get<int32_t>(2 * (int64_t)n);
+    unsigned long long* boxmax = tmp.get<unsigned long long>(n);
+    int64_t* d_row_base = tmp.get<int64_t>(n + 1);
+    int64_t* d_state_base = tmp.get<int64_t>(n + 1);
+    const int64_t te = scan_tmp_elems(R);
+    int64_t* stmp = tmp.get<int64_t>(te);
+    std::vector<double> U_all(std::max<int64_t>(1, u_off[n]));
+    for (int32_t i = 0; i < n; ++i) {
+      hp[i].U = st->d_U + u_off[i];
+      if (u_off[i + 1] > u_off[i])
+        std::memcpy(U_all.data() + u_off[i], inputs[i].values,
+                    sizeof(double) * (size_t)(u_off[i + 1] - u_off[i]));
+    }
+    st->hip_used = true;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipMemcpyAsync(st->d_U, U_all.data(), sizeof(double) * U_all.size(),
+                           hipMemcpyHostToDevice, st->st));
+    HIP_TRY(hipMemcpyAsync(st->d_sys, hp.data(), sizeof(SysParams) * n, hipMemcpyHostToDevice,
+                           st->st));
+    HIP_TRY(hipMemcpyAsync(d_row_base, row_base.data(), sizeof(int64_t) * (n + 1),
+                           hipMemcpyHostToDevice, st->st));
+    HIP_TRY(hipMemcpyAsync(d_state_base, state_base.data(), sizeof(int64_t) * (n + 1),
+                           hipMemcpyHostToDevice, st->st));
+    HIP_TRY(hipMemsetAsync(maxima, 0, 2 * sizeof(int32_t) * n, st->st));
+    HIP_TRY(hipMemsetAsync(boxmax, 0, sizeof(unsigned long long) * n, st->st));
+    const BuildTable T{st->d_sys, d_row_base, d_state_base, n};
+    HIP_TRY(hipEventRecord(e0, st->st));
+    HIP_TRY(launch_row_geom(T, R, st->win, st->ot, cnt, maxima, st->st));
+    HIP_TRY(exclusive_scan_i64(cnt, st->row_off, R, stmp, te, st->st));
+    std::vector<int32_t> mx(2 * (size_t)n);
+    HIP_TRY(hipMemcpyAsync(&total, st->row_off + R, sizeof(int64_t), hipMemcpyDeviceToHost,
+                           st->st));
+    HIP_TRY(hipMemcpyAsync(mx.data(), maxima, sizeof(int32_t) * 2 * n, hipMemcpyDeviceToHost,
+                           st->st));
+    HIP_TRY(hipStreamSynchronize(st->st));
+    int64_t fac_total = 0;
+    int32_t fs_max = 1;
+    for (int32_t i = 0; i < n; ++i) {
+      max_row[i] = mx[2 * i];
+      const int32_t fs = mx[2 * i + 1] > 0 ? mx[2 * i + 1] : 1;
+      if (max_row[i] > IMPACT_MAX_ROW)
+        return fail(IMPACT_E_UNSUPPORTED,
+                    (n > 1 ? "system " + std::to_string(i) + ": " : std::string()) + "a row has " +
+                        std::to_string(max_row[i]) + " entries (max " +
+                        std::to_string(IMPACT_MAX_ROW) + ")");
+      if (fs > kMaxFactors)
+        return fail(IMPACT_E_UNSUPPORTED, "per-row factor list longer than " +
+                                              std::to_string(kMaxFactors));
+      fsz[i] = fs;
+      hp[i].fs = fs;
+      hp[i].fac_base = fac_total;
+      if (factors) fac_total += hp[i].n_rows * (int64_t)fs;
+      fs_max = std::max(fs_max, fs);
+    }
+    HIP_TRY(hipMemcpyAsync(st->d_sys, hp.data(), sizeof(SysParams) * n, hipMemcpyHostToDevice,
+                           st->st));
+    if (factors)
+      st->fac = st->own<double2>(fac_total);
+    else
+      st->ent = st->own<double2>(total);
+    HIP_TRY(launch_expand(T, R, st->win, st->row_off, st->ent, st->fac, fs_max, d_max, st->st));
+    HIP_TRY(hipEventRecord(e1, st->st));
+    HIP_TRY(launch_state_box_max(T, S, st->win, boxmax, st->st));
+    HIP_TRY(hipMemcpyAsync(bm.data(), boxmax, sizeof(unsigned long long) * n,
+                           hipMemcpyDeviceToHost, st->st));
+    HIP_TRY(hipStreamSynchronize(st->st));
+    build_ms = event_ms(e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return IMPACT_OK;
+  });
+  if (rc != IMPACT_OK) return rc;
+  // per-system views (row offsets of the last system end at the total)
+  std::vector<int64_t> cells(n, 0);
+  {
+    std::vector<int64_t> starts(n + 1);
+    const int r = guarded([&]() -> int {
+      for (int32_t i = 0; i <= n; ++i)
+        HIP_TRY(hipMemcpyAsync(&starts[i], store->row_off + row_base[i], sizeof(int64_t),
+                               hipMemcpyDeviceToHost, store->st));
+      HIP_TRY(hipStreamSynchronize(store->st));
+      return IMPACT_OK;
+    });
+    if (r != IMPACT_OK) return r;
+    for (int32_t i = 0; i < n; ++i) cells[i] = starts[i + 1] - starts[i];
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    impact_imdp* h = new impact_imdp();
+    h->store = store;
+    h->inst = i;
+    h->st = store->st;
+    h->hp = hp[i];
+    h->dp = store->d_sys + i;
+    h->row_off = store->row_off + hp[i].row_base;
+    h->win = store->win + hp[i].win_base;
+    h->ot = store->ot + hp[i].row_base;
+    h->ent = store->ent;
+    h->fac = store->fac ? store->fac + hp[i].fac_base : nullptr;
+    h->n_states = hp[i].n_states;
+    h->n_rows = hp[i].n_rows;
+    h->n_cells = cells[i];
+    h->d = hp[i].d;
+    h->nu = hp[i].nu;
+    h->windowed = hp[i].windowed;
+    h->storage = factors ? IMPACT_STORE_FACTORS : IMPACT_STORE_BOUNDS;
+    h->max_row = max_row[i];
+    h->fs = (int32_t)fsz[i];
+    h->max_box = (int64_t)bm[i];
+    h->build_ms = build_ms;
+    out[i] = h;
+  }
+  return IMPACT_OK;
+}
+
 int impact_build_imdp(const impact_system* sys, const impact_grid* grid,
                       const impact_inputs* inputs, const impact_noise* noise,
                       const impact_window* window, const impact_device* dev,
@@ -233,85 +423,32 @@ int impact_build_imdp(const impact_system* sys, const impact_grid* grid,
   g_err.clear();
   if (!out) return fail(IMPACT_E_INVAL, "out is null");
   *out = nullptr;
-  int rc = validate_build(sys, grid, inputs, noise, window);
-  if (rc != IMPACT_OK) return rc;
-  impact_imdp* h = new impact_imdp();
-  if (dev) h->dev = *dev;
-  h->st = (hipStream_t)h->dev.stream;
-  rc = guarded([&]() -> int {
-    SysParams& p = h->hp;
-    fill_params(p, sys, grid, inputs, noise, window);
-    h->d = p.d;
-    h->nu = p.nu;
-    h->windowed = p.windowed;
-    h->n_states = p.n_states;
-    h->n_rows = p.n_rows;
-    h->storage = window->storage == IMPACT_STORE_FACTORS ? IMPACT_STORE_FACTORS
-                                                         : IMPACT_STORE_BOUNDS;
-    const int64_t R = h->n_rows;
-    // every allocation is requested before the first HIP call
-    h->dp = h->own<SysParams>(1);
-    h->dU = h->own<double>(std::max<int64_t>(1, (int64_t)p.nu * p.du));
-    h->win = h->own<int32_t>(R * 2 * p.d);
-    h->ot = h->own<double4>(R);
-    h->row_off = h->own<int64_t>(R + 1);
-    Scratch tmp(h);
-    int64_t* cnt = tmp.get<int64_t>(R);
-    int32_t* maxima = tmp.get<int32_t>(2);
-    const int64_t te = scan_tmp_elems(R);
-    int64_t* stmp = tmp.get<int64_t>(te);
+  if (!sys || !grid || !inputs || !noise || !window) return fail(IMPACT_E_INVAL, "null argument");
+  return build_many(1, sys, grid, inputs, noise, window, dev, out);
+}
 
-    h->hip_used = true;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipMemcpyAsync(h->dp, &p, sizeof(SysParams), hipMemcpyHostToDevice, h->st));
-    if ((int64_t)p.nu * p.du > 0)
-      HIP_TRY(hipMemcpyAsync(h->dU, inputs->values, sizeof(double) * p.nu * p.du,
-                             hipMemcpyHostToDevice, h->st));
-    HIP_TRY(hipMemsetAsync(maxima, 0, 2 * sizeof(int32_t), h->st));
-    if (e0) HIP_TRY(hipEventRecord(e0, h->st));
-    HIP_TRY(launch_row_geom(h->dp, h->dU, R, h->win, h->ot, cnt, maxima, h->st));
-    HIP_TRY(exclusive_scan_i64(cnt, h->row_off, R, stmp, te, h->st));
-    int64_t total = 0;
-    int32_t mx[2] = {0, 0};
-    HIP_TRY(hipMemcpyAsync(&total, h->row_off + R, sizeof(int64_t), hipMemcpyDeviceToHost, h->st));
-    HIP_TRY(hipMemcpyAsync(mx, maxima, sizeof(mx), hipMemcpyDeviceToHost, h->st));
-    HIP_TRY(hipStreamSynchronize(h->st));
-    h->n_cells = total;
-    h->max_row = mx[0];
-    h->fs = mx[1] > 0 ? mx[1] : 1;
-    if (h->max_row > IMPACT_MAX_ROW)
-      return fail(IMPACT_E_UNSUPPORTED, "a row has " + std::to_string(h->max_row) +
-                                            " entries (max " + std::to_string(IMPACT_MAX_ROW) + ")");
-    if (h->fs > kMaxFactors)
-      return fail(IMPACT_E_UNSUPPORTED, "per-row factor list longer than " +
-                                            std::to_string(kMaxFactors));
-    if (h->storage == IMPACT_STORE_FACTORS)
-      h->fac = h->own<double2>(R * (int64_t)h->fs);
-    else
-      h->ent = h->own<double2>(total);
-    HIP_TRY(launch_expand(h->dp, h->dU, R, h->win, h->row_off, h->ent, h->fac, h->fs, p.d, h->st));
-    if (e1) HIP_TRY(hipEventRecord(e1, h->st));
-    HIP_TRY(hipStreamSynchronize(h->st));
-    if (e0) {
-      h->build_ms = event_ms(e0, e1);
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-    }
-    return IMPACT_OK;
-  });
-  if (rc != IMPACT_OK) {
-    delete h;
-    return rc;
-  }
-  *out = h;
-  return IMPACT_OK;
+int impact_build_imdp_batch(int32_t n, const impact_system* sys, const impact_grid* grid,
+                            const impact_inputs* inputs, const impact_noise* noise,
+                            const impact_window* window, const impact_device* dev,
+                            impact_imdp** out) {
+  g_err.clear();
+  if (!out) return fail(IMPACT_E_INVAL, "out is null");
+  if (n < 1) return fail(IMPACT_E_INVAL, "n must be >= 1");
+  if (!sys || !grid || !inputs || !noise || !window) return fail(IMPACT_E_INVAL, "null argument");
+  return build_many(n, sys, grid, inputs, noise, window, dev, out);
 }
 
 int impact_set_timing(impact_imdp* h, int32_t enable) {
   if (!h) return fail(IMPACT_E_INVAL, "null handle");
   h->timing = enable != 0;
+  return IMPACT_OK;
+}
+
+int impact_set_sweep_mode(impact_imdp* h, int32_t mode) {
+  if (!h) return fail(IMPACT_E_INVAL, "null handle");
+  if (mode < IMPACT_SWEEP_AUTO || mode > IMPACT_SWEEP_STATE_BOX)
+    return fail(IMPACT_E_INVAL, "unknown sweep mode");
+  h->sweep_mode = mode;
   return IMPACT_OK;
 }
 
@@ -326,7 +463,8 @@ int impact_imdp_get_info(const impact_imdp* h, impact_imdp_info* info) {
   info->windowed = h->windowed;
   info->storage = h->storage;
   info->max_row = h->max_row;
-  info->device_bytes = h->bytes;
+  info->max_box = h->max_box;
+  info->device_bytes = h->store->bytes;
   info->build_ms = h->build_ms;
   return IMPACT_OK;
 }
@@ -402,7 +540,8 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
     double2* vb[2] = {tmp.get<double2>(N), tmp.get<double2>(N)};
     int32_t* pi = tmp.get<int32_t>(N);
     Ctrl* ctrl = tmp.get<Ctrl>(1);
-    h->hip_used = true;
+    double* gap_part = tmp.get<double>(std::max<int64_t>(1, N));
+    h->store->hip_used = true;
 
     if (spec->n_target > 0)
       HIP_TRY(hipMemcpyAsync(tb, spec->target_boxes, sizeof(double) * spec->n_target * 2 * d,
@@ -427,6 +566,9 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       return e;
     };
     Ctrl hc{};
+    // one sort per state over its rows' window box when every row fits a
+    // wavefront; otherwise one sort per row
+    const bool use_box = h->max_row <= 512 && h->sweep_mode != IMPACT_SWEEP_PER_ROW;
     for (int pass = 0; pass < 2; ++pass) {
       SweepArgs a{};
       a.row_off = h->row_off;
@@ -438,6 +580,7 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       a.pi = pi;
       a.safe = safe;
       a.ctrl = ctrl;
+      a.gap_part = gap_part;
       a.n_safe = n_safe;
       a.fs = h->fs;
       a.pass = pass;
@@ -464,15 +607,17 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       float sweep_ms = 0.f, launch_ms = 0.f;
       if (!converged) {
         // Sweeps go out in batches between host polls of the control block.
-        // The batch length is the number of sweeps still needed if the gap
-        // keeps contracting at its last observed rate (at most 64), so that
-        // few launches run after the stop test has fired.
-        int64_t chunk = 2, prev_sweeps = 0;
+        // A batch lasts about 2 ms of GPU time (from the last batch's per-sweep
+        // time) and never exceeds the number of sweeps still needed if the
+        // gap keeps contracting at its last observed rate, so few launches run
+        // after the stop test has fired.
+        int64_t chunk = 1, prev_sweeps = 0;
         double prev_gap = 1.0;
         std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
         for (;;) {
           const int64_t n = std::min<int64_t>(chunk, spec->max_sweeps - launched);
           if (n <= 0) break;
+          const auto c0 = std::chrono::steady_clock::now();
           for (int64_t k = 0; k < n; ++k) {
             const int64_t idx = launched + k;
             a.vin = vb[idx & 1];
@@ -483,18 +628,24 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
               e1 = new_event();
               HIP_TRY(hipEventRecord(e0, h->st));
             }
-            HIP_TRY(launch_sweep(a, h->max_row, h->st));
+            if (use_box)
+              HIP_TRY(launch_sweep_sb(a, h->max_box, h->max_row, h->st));
+            else
+              HIP_TRY(launch_sweep(a, h->max_row, h->st));
             if (h->timing) {
               HIP_TRY(hipEventRecord(e1, h->st));
               marks.emplace_back(e0, e1);
             }
-            HIP_TRY(launch_finish(ctrl, h->st));
+            HIP_TRY(launch_finish(ctrl, gap_part, sweep_blocks(a, use_box), h->st));
           }
           launched += n;
           HIP_TRY(hipMemcpyAsync(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->st));
           HIP_TRY(hipStreamSynchronize(h->st));
           if (hc.done) break;
-          int64_t next = std::min<int64_t>(chunk * 2, 64);
+          const double per_sweep_ms =
+              std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0)
+                  .count() / (double)n;
+          int64_t next = (int64_t)std::max(1.0, std::min(256.0, 2.0 / std::max(per_sweep_ms, 1e-3)));
           if (hc.sweeps > prev_sweeps && hc.gap > 0.0 && hc.gap < prev_gap) {
             const double rate = std::pow(hc.gap / prev_gap, 1.0 / (double)(hc.sweeps - prev_sweeps));
             if (rate > 0.0 && rate < 1.0) {
@@ -504,7 +655,7 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
           }
           prev_sweeps = hc.sweeps;
           prev_gap = hc.gap;
-          chunk = std::max<int64_t>(1, next);
+          chunk = next;
         }
         sweeps = hc.sweeps;
         gap = hc.gap;

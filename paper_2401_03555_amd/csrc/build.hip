@@ -3,10 +3,10 @@
 //
 //  k_row_geom : one thread per row -- mean box, per-dimension windows, OUT and
 //               TAIL bounds (Remark 4.1), window cell count.
-//  k_expand   : one wavefront per row -- per-dimension factor bounds into LDS
-//               (or HBM for FACTORS storage), then the entry products
-//               lo = prod_i flo_i, hi = prod_i fhi_i over the window in C order,
-//               written as coalesced (lo, hi) pairs.
+//  k_expand   : tiles of rows -- per-dimension factor bounds from shared edge
+//               erfc values (into LDS, or HBM for FACTORS storage), then the
+//               entry products lo = prod_i flo_i, hi = prod_i fhi_i over the
+//               window in C order, written as coalesced (lo, hi) pairs.
 //  k_export   : copies rows out in the ABI row layout.
 #include "impact_internal.hpp"
 
@@ -23,114 +23,268 @@ __device__ __forceinline__ int wave_max_i32(int x) {
   return x;
 }
 
-__global__ __launch_bounds__(kGeomThreads) void k_row_geom(const SysParams* __restrict__ sp,
-                                                           const double* __restrict__ U,
-                                                           int64_t n_rows, int32_t* __restrict__ win,
+__global__ __launch_bounds__(kGeomThreads) void k_row_geom(BuildTable T, int64_t n_rows,
+                                                           int32_t* __restrict__ win,
                                                            double4* __restrict__ ot,
                                                            int64_t* __restrict__ cnt,
                                                            int32_t* __restrict__ maxima) {
-  const SysParams& p = *sp;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int row_len = 0, fsum = 0;
+  int row_len = 0, fsum = 0, inst = 0;
   if (r < n_rows) {
+    inst = T.n == 1 ? 0 : find_base(T.row_base, T.n, r);
+    const SysParams& p = T.sys[inst];
     const int d = p.d;
-    const int64_t s = r / p.nu;
-    const int32_t u = (int32_t)(r - s * p.nu);
+    const int64_t rl = r - p.row_base;
+    const int64_t s = rl / p.nu;
+    const int32_t u = (int32_t)(rl - s * p.nu);
     double mlo[kMaxDim], mhi[kMaxDim];
-    mean_box(p, U, s, u, mlo, mhi);
+    mean_box(p, p.U, s, u, mlo, mhi);
     int32_t klo[kMaxDim], W[kMaxDim];
     int64_t ncell = 1;
-    for (int i = 0; i < d; ++i) {
+    IMPACT_FOR_DIMS(i, d) {
       window_dim(p, i, mlo[i], mhi[i], &klo[i], &W[i]);
       ncell *= W[i];
       fsum += W[i];
     }
-    for (int i = 0; i < d; ++i) {
-      win[r * 2 * d + i] = klo[i];
-      win[r * 2 * d + d + i] = W[i];
+    int32_t* wr = win + p.win_base + rl * 2 * d;
+    IMPACT_FOR_DIMS(i, d) {
+      wr[i] = klo[i];
+      wr[d + i] = W[i];
     }
     double4 o;
     out_tail(p, mlo, mhi, klo, W, &o);
     ot[r] = o;
     cnt[r] = ncell;
-    int64_t len = ncell + 1 + p.windowed;
+    const int64_t len = ncell + 1 + p.windowed;
     row_len = len > 0x3fffffff ? 0x3fffffff : (int)len;
+  } else {
+    inst = T.n - 1;
   }
-  row_len = wave_max_i32(row_len);
-  fsum = wave_max_i32(fsum);
-  if ((threadIdx.x & 63) == 0) {
-    atomicMax(&maxima[0], row_len);
-    atomicMax(&maxima[1], fsum);
+  // per-instance maxima: one atomic per wavefront when it holds one instance
+  const int first = __shfl(inst, 0);
+  if (__all(inst == first)) {
+    row_len = wave_max_i32(row_len);
+    fsum = wave_max_i32(fsum);
+    if ((threadIdx.x & 63) == 0) {
+      atomicMax(&maxima[2 * inst], row_len);
+      atomicMax(&maxima[2 * inst + 1], fsum);
+    }
+  } else if (r < n_rows) {
+    atomicMax(&maxima[2 * inst], row_len);
+    atomicMax(&maxima[2 * inst + 1], fsum);
   }
 }
 
 // Mixed-radix digits of v in the window radices W (last dimension fastest).
 __device__ __forceinline__ void unravel(int64_t v, const int32_t* W, int d, int32_t* j) {
-  for (int i = d - 1; i >= 0; --i) {
+  IMPACT_FOR_DIMS_REV(i, d) {
     j[i] = (int32_t)(v % W[i]);
     v /= W[i];
   }
 }
 
-__global__ __launch_bounds__(64 * kRowsPerBlock) void k_expand(
-    const SysParams* __restrict__ sp, const double* __restrict__ U, int64_t n_rows,
-    const int32_t* __restrict__ win, const int64_t* __restrict__ row_off,
-    double2* __restrict__ ent, double2* __restrict__ fac, int32_t fs) {
-  extern __shared__ double2 sh_fac[];
-  const SysParams& p = *sp;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t r = (int64_t)blockIdx.x * kRowsPerBlock + wv;
-  const bool live = r < n_rows;
-  const int d = p.d;
-  double2* f = sh_fac + wv * fs;
-  int32_t klo[kMaxDim], W[kMaxDim], fo[kMaxDim];
-  int64_t ncell = 0;
-  if (live) {
-    const int64_t s = r / p.nu;
-    const int32_t u = (int32_t)(r - s * p.nu);
+// k_expand: a workgroup takes a tile of B rows.
+//   A. one thread per row: mean box (LDS) and the row's window (LDS);
+//   B. one thread per (row, dimension, window edge): erfc(|z|/sqrt2) of the
+//      edge at both ends of the mean interval, z = (edge - m)/sigma, stored
+//      with the sign of z -- every interior edge is shared by two cells;
+//   C. one thread per (row, dimension, window cell): the cell mass at each end
+//      of the mean interval from its two edges (the same operations as the
+//      tail-aware formula), min of the two, and the max at the clamped
+//      midpoint (an end value, or a direct evaluation when the midpoint lies
+//      inside the interval);
+//   D. one wavefront per row: the window's products in C order, coalesced.
+// B is chosen by the host so that the tile fits in LDS.
+struct ExpandShape {
+  int32_t B;        // rows per workgroup
+  int32_t es;       // per-row stride of the edge table (>= sum_i (W_i + 1))
+  int32_t fs;       // per-row stride of the LDS factor table (>= sum_i W_i)
+  int32_t d;        // per-row stride / 2 of the mean-box and window tables
+  int32_t with_products;
+};
+
+// Byte offsets of the LDS tables of one tile (16-byte aligned).
+struct ExpandLayout {
+  size_t mb, wn, ev, fv, total;
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+__host__ __device__ inline ExpandLayout expand_layout(const ExpandShape& sh) {
+  ExpandLayout L;
+  L.mb = 0;
+  L.wn = align16(L.mb + (size_t)sh.B * 2 * sh.d * sizeof(double));
+  L.ev = align16(L.wn + (size_t)sh.B * (2 * sh.d + 1) * sizeof(int32_t));
+  L.fv = align16(L.ev + (size_t)sh.B * sh.es * 2 * sizeof(double));
+  L.total = align16(L.fv + (sh.with_products ? (size_t)sh.B * sh.fs * 2 * sizeof(double) : 0));
+  return L;
+}
+
+// erfc(|z|/sqrt2) with the sign of z attached: +e for z > 0, -e for z < 0,
+// and 2 (an impossible erfc value) for z == 0, so that the branch of the
+// tail-aware formula is recovered exactly.
+__device__ __forceinline__ double enc_erfc(double z) {
+  if (z == 0.0) return 2.0;
+  const double e = erfc(fabs(z) * kRsqrt2);
+  return z > 0.0 ? e : -e;
+}
+
+__device__ __forceinline__ double dec_erfc(double x) { return x == 2.0 ? 1.0 : fabs(x); }
+
+// Cell mass from the encoded edge values at its two edges (tail-aware form).
+__device__ __forceinline__ double mass_from_edges(double ea, double eb) {
+  const bool za_nonneg = !signbit(ea);
+  const bool zb_nonpos = signbit(eb) || eb == 2.0;
+  const double a = dec_erfc(ea), b = dec_erfc(eb);
+  double g;
+  if (za_nonneg)
+    g = 0.5 * (a - b);
+  else if (zb_nonpos)
+    g = 0.5 * (b - a);
+  else
+    g = (1.0 - 0.5 * a) - 0.5 * b;
+  return g < 0.0 ? 0.0 : (g > 1.0 ? 1.0 : g);
+}
+
+__global__ __launch_bounds__(256) void k_expand(BuildTable T, int64_t n_rows,
+                                                const int32_t* __restrict__ win,
+                                                const int64_t* __restrict__ row_off,
+                                                double2* __restrict__ ent, double2* __restrict__ fac,
+                                                ExpandShape sh) {
+  extern __shared__ double4 lds_raw[];
+  char* lds = (char*)lds_raw;
+  const int B = sh.B, es = sh.es, fs = sh.fs, D = sh.d;
+  const int64_t r0 = (int64_t)blockIdx.x * B;
+  const int nb = (int)(n_rows - r0 < B ? n_rows - r0 : B);
+  const ExpandLayout lay = expand_layout(sh);
+  double* mb = (double*)(lds + lay.mb);     // B * 2D: mlo then mhi
+  int32_t* wn = (int32_t*)(lds + lay.wn);   // B * (2D + 1): klo, W, instance
+  double* ev = (double*)(lds + lay.ev);     // B * es * 2 encoded edge values
+  double2* fv = (double2*)(lds + lay.fv);   // B * fs factor bounds (BOUNDS only)
+
+  // A. mean boxes and windows
+  for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+    const int64_t row = r0 + r;
+    const int inst = T.n == 1 ? 0 : find_base(T.row_base, T.n, row);
+    const SysParams& p = T.sys[inst];
+    const int d = p.d;
+    const int64_t rl = row - p.row_base;
+    const int64_t s = rl / p.nu;
+    const int32_t u = (int32_t)(rl - s * p.nu);
     double mlo[kMaxDim], mhi[kMaxDim];
-    mean_box(p, U, s, u, mlo, mhi);
+    mean_box(p, p.U, s, u, mlo, mhi);
+    const int32_t* wr = win + p.win_base + rl * 2 * d;
+    IMPACT_FOR_DIMS(i, d) {
+      mb[r * 2 * D + i] = mlo[i];
+      mb[r * 2 * D + D + i] = mhi[i];
+      wn[r * (2 * D + 1) + i] = wr[i];
+      wn[r * (2 * D + 1) + D + i] = wr[d + i];
+    }
+    wn[r * (2 * D + 1) + 2 * D] = inst;
+  }
+  __syncthreads();
+
+  // B. edge values at both ends of the mean interval
+  for (int t = threadIdx.x; t < nb * es; t += blockDim.x) {
+    const int r = t / es, e = t - r * es;
+    const int32_t* w = wn + r * (2 * D + 1);
+    const SysParams& p = T.sys[w[2 * D]];
+    const int d = p.d;
+    int i = -1, j = e, acc = 0;
+    IMPACT_FOR_DIMS(ii, d) {
+      if (i < 0 && e < acc + w[D + ii] + 1) {
+        i = ii;
+        j = e - acc;
+      }
+      acc += w[D + ii] + 1;
+    }
+    if (i < 0 || w[D + i] == 0) continue;
+    const double E = cell_edge(p, i, (int64_t)w[i] + j);
+    const double sg = p.sigma[i];
+    ev[(r * es + e) * 2 + 0] = enc_erfc((E - mb[r * 2 * D + i]) / sg);
+    ev[(r * es + e) * 2 + 1] = enc_erfc((E - mb[r * 2 * D + D + i]) / sg);
+  }
+  __syncthreads();
+
+  // C. per-dimension factor bounds
+  for (int t = threadIdx.x; t < nb * fs; t += blockDim.x) {
+    const int r = t / fs, c = t - r * fs;
+    const int32_t* w = wn + r * (2 * D + 1);
+    const SysParams& p = T.sys[w[2 * D]];
+    const int d = p.d;
+    int i = -1, j = c, acc = 0, eacc = 0, eo = 0;
+    IMPACT_FOR_DIMS(ii, d) {
+      if (i < 0 && c < acc + w[D + ii]) {
+        i = ii;
+        j = c - acc;
+        eo = eacc;
+      }
+      acc += w[D + ii];
+      eacc += w[D + ii] + 1;
+    }
+    if (i < 0) continue;
+    const int64_t k = (int64_t)w[i] + j;
+    const double* e0 = ev + (r * es + eo + j) * 2;
+    const double g1 = mass_from_edges(e0[0], e0[2]);
+    const double g2 = mass_from_edges(e0[1], e0[3]);
+    const double lo = g1 < g2 ? g1 : g2;
+    const double a = cell_edge(p, i, k), b = cell_edge(p, i, k + 1);
+    const double mid = 0.5 * (a + b);
+    const double mlo = mb[r * 2 * D + i], mhi = mb[r * 2 * D + D + i];
+    double hi;
+    if (mid < mlo)
+      hi = g1;
+    else if (mid > mhi)
+      hi = g2;
+    else
+      hi = gauss_mass(a, b, mid, p.sigma[i]);
+    if (hi < lo) hi = lo;
+    if (fac)
+      fac[p.fac_base + (r0 + r - p.row_base) * (int64_t)p.fs + c] = make_double2(lo, hi);
+    else
+      fv[r * fs + c] = make_double2(lo, hi);
+  }
+  if (fac) return;
+  __syncthreads();
+
+  // D. products, one wavefront per row
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+  for (int r = wv; r < nb; r += nwv) {
+    const int32_t* w = wn + r * (2 * D + 1);
+    const int d = T.sys[w[2 * D]].d;
+    int32_t W[kMaxDim], fo[kMaxDim], j[kMaxDim], inc[kMaxDim];
+    int64_t ncell = 1;
     int tot = 0;
-    ncell = 1;
-    for (int i = 0; i < d; ++i) {
-      klo[i] = win[r * 2 * d + i];
-      W[i] = win[r * 2 * d + d + i];
+    IMPACT_FOR_DIMS(i, d) {
+      W[i] = w[D + i];
       fo[i] = tot;
       tot += W[i];
       ncell *= W[i];
     }
-    for (int idx = lane; idx < tot; idx += 64) {
-      int i = 0;
-      while (i + 1 < d && idx >= fo[i + 1]) ++i;
-      const int64_t k = (int64_t)klo[i] + (idx - fo[i]);
-      double flo, fhi;
-      factor_bounds(cell_edge(p, i, k), cell_edge(p, i, k + 1), mlo[i], mhi[i], p.sigma[i], &flo,
-                    &fhi);
-      if (fac)
-        fac[r * fs + idx] = make_double2(flo, fhi);
-      else
-        f[idx] = make_double2(flo, fhi);
+    if (ncell == 0) continue;
+    int64_t a0 = lane, a1 = 64;
+    IMPACT_FOR_DIMS_REV(i, d) {
+      j[i] = (int32_t)(a0 % W[i]);
+      a0 /= W[i];
+      inc[i] = (int32_t)(a1 % W[i]);
+      a1 /= W[i];
     }
-  }
-  __syncthreads();
-  if (!live || fac || ncell == 0) return;
-  int32_t j[kMaxDim], inc[kMaxDim];
-  unravel(lane, W, d, j);
-  unravel(64, W, d, inc);
-  const int64_t base = row_off[r];
-  for (int64_t slot = lane; slot < ncell; slot += 64) {
-    double lo = 1.0, hi = 1.0;
-    for (int i = 0; i < d; ++i) {
-      const double2 fv = f[fo[i] + j[i]];
-      lo *= fv.x;
-      hi *= fv.y;
-    }
-    ent[base + slot] = make_double2(lo, hi);
-    int carry = 0;
-    for (int i = d - 1; i >= 0; --i) {
-      j[i] += inc[i] + carry;
-      carry = j[i] >= W[i];
-      if (carry) j[i] -= W[i];
+    const double2* f = fv + r * fs;
+    const int64_t base = row_off[r0 + r];
+    for (int64_t slot = lane; slot < ncell; slot += 64) {
+      double lo = 1.0, hi = 1.0;
+      IMPACT_FOR_DIMS(i, d) {
+        const double2 x = f[fo[i] + j[i]];
+        lo *= x.x;
+        hi *= x.y;
+      }
+      ent[base + slot] = make_double2(lo, hi);
+      int carry = 0;
+      IMPACT_FOR_DIMS_REV(i, d) {
+        j[i] += inc[i] + carry;
+        carry = j[i] >= W[i];
+        if (carry) j[i] -= W[i];
+      }
     }
   }
 }
@@ -159,7 +313,7 @@ __global__ __launch_bounds__(64 * kRowsPerBlock) void k_export(
   const int64_t dst = row_off[r] - row_off[row0];
   int32_t W[kMaxDim], fo[kMaxDim];
   int tot = 0;
-  for (int i = 0; i < d; ++i) {
+  IMPACT_FOR_DIMS(i, d) {
     W[i] = win[r * 2 * d + d + i];
     fo[i] = tot;
     tot += W[i];
@@ -172,7 +326,7 @@ __global__ __launch_bounds__(64 * kRowsPerBlock) void k_export(
       int32_t j[kMaxDim];
       unravel(slot, W, d, j);
       double lo = 1.0, hi = 1.0;
-      for (int i = 0; i < d; ++i) {
+      IMPACT_FOR_DIMS(i, d) {
         const double2 fv = fac[r * fs + fo[i] + j[i]];
         lo *= fv.x;
         hi *= fv.y;
@@ -184,23 +338,35 @@ __global__ __launch_bounds__(64 * kRowsPerBlock) void k_export(
   }
 }
 
-hipError_t launch_row_geom(const SysParams* sys, const double* U, int64_t n_rows, int32_t* win,
-                           double4* ot, int64_t* cnt, int32_t* maxima, hipStream_t st) {
+hipError_t launch_row_geom(const BuildTable& T, int64_t n_rows, int32_t* win, double4* ot,
+                           int64_t* cnt, int32_t* maxima, hipStream_t st) {
   if (n_rows == 0) return hipSuccess;
   const int64_t blocks = (n_rows + kGeomThreads - 1) / kGeomThreads;
-  hipLaunchKernelGGL(k_row_geom, dim3((unsigned)blocks), dim3(kGeomThreads), 0, st, sys, U,
-                     n_rows, win, ot, cnt, maxima);
+  hipLaunchKernelGGL(k_row_geom, dim3((unsigned)blocks), dim3(kGeomThreads), 0, st, T, n_rows, win,
+                     ot, cnt, maxima);
   return hipGetLastError();
 }
 
-hipError_t launch_expand(const SysParams* sys, const double* U, int64_t n_rows,
-                         const int32_t* win, const int64_t* row_off, double2* ent, double2* fac,
-                         int32_t fs, int32_t d, hipStream_t st) {
+hipError_t launch_expand(const BuildTable& T, int64_t n_rows, const int32_t* win,
+                         const int64_t* row_off, double2* ent, double2* fac, int32_t fs_max,
+                         int32_t d_max, hipStream_t st) {
   if (n_rows == 0) return hipSuccess;
-  const int64_t blocks = (n_rows + kRowsPerBlock - 1) / kRowsPerBlock;
-  const size_t lds = fac ? 0 : (size_t)kRowsPerBlock * fs * sizeof(double2);
-  hipLaunchKernelGGL(k_expand, dim3((unsigned)blocks), dim3(64 * kRowsPerBlock), lds, st, sys, U,
-                     n_rows, win, row_off, ent, fac, fs);
+  ExpandShape sh;
+  sh.fs = fs_max;
+  sh.es = fs_max + d_max;
+  sh.d = d_max;
+  sh.with_products = fac ? 0 : 1;
+  const size_t budget = 48 * 1024;
+  int B = 64;
+  for (; B > 1; B /= 2) {
+    sh.B = B;
+    if (expand_layout(sh).total <= budget) break;
+  }
+  sh.B = B;
+  const size_t lds = expand_layout(sh).total;
+  const int64_t blocks = (n_rows + B - 1) / B;
+  hipLaunchKernelGGL(k_expand, dim3((unsigned)blocks), dim3(256), lds, st, T, n_rows, win, row_off,
+                     ent, fac, sh);
   return hipGetLastError();
 }
 

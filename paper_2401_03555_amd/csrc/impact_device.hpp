@@ -21,6 +21,13 @@ constexpr double kTwoPi = 6.283185307179586;
 constexpr double kPi = 3.141592653589793;
 constexpr double kHalfPi = 1.5707963267948966;
 
+// Loops over the dimensions of a system, unrolled to the compile-time maximum
+// so that per-dimension arrays are indexed statically and stay in registers.
+#define IMPACT_FOR_DIMS(i, d) \
+  _Pragma("unroll") for (int i = 0; i < kMaxDim; ++i) if (i < (d))
+#define IMPACT_FOR_DIMS_REV(i, d) \
+  _Pragma("unroll") for (int i = kMaxDim - 1; i >= 0; --i) if (i < (d))
+
 enum SysKind : int32_t { kAffine = 0, kUnicycle = 1 };
 enum CellClass : int8_t { kSafe = 0, kTarget = 1, kAvoid = 2 };
 
@@ -37,7 +44,34 @@ struct SysParams {
   int32_t n[kMaxDim];
   int64_t stride[kMaxDim];  // C-order state strides
   int64_t n_states, n_rows;
+  // Placement of this system inside a (possibly multi-system) build.
+  const double* U;          // its inputs, nu x du (device)
+  int64_t row_base;         // first global row
+  int64_t state_base;       // first global state
+  int64_t win_base;         // offset of its window table (int32 elements)
+  int64_t fac_base;         // offset of its factor table (double2 elements)
+  int32_t fs, pad1;         // factor stride (max over its rows of sum_i W_i)
 };
+
+// Instances of one build: row r belongs to the last i with row_base[i] <= r.
+struct BuildTable {
+  const SysParams* sys;       // n entries
+  const int64_t* row_base;    // n + 1
+  const int64_t* state_base;  // n + 1
+  int32_t n;
+};
+
+__device__ __forceinline__ int find_base(const int64_t* __restrict__ base, int n, int64_t r) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (base[mid] <= r)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
 
 // Per-iteration-pass control block in device memory (sweep stop test on the
 // device; the host only polls it between launch batches).
@@ -66,7 +100,7 @@ __device__ inline void mean_box(const SysParams& p, const double* __restrict__ U
   const int d = p.d;
   double xl[kMaxDim], xh[kMaxDim];
   int64_t rem = s;
-  for (int i = d - 1; i >= 0; --i) {
+  IMPACT_FOR_DIMS_REV(i, d) {
     int64_t k = rem % p.n[i];
     rem /= p.n[i];
     xl[i] = cell_edge(p, i, k);
@@ -74,9 +108,9 @@ __device__ inline void mean_box(const SysParams& p, const double* __restrict__ U
   }
   const double* uv = U + (int64_t)u * p.du;
   if (p.kind == kAffine) {
-    for (int i = 0; i < d; ++i) {
+    IMPACT_FOR_DIMS(i, d) {
       double slo = 0.0, shi = 0.0, mag = 0.0;
-      for (int j = 0; j < d; ++j) {
+      IMPACT_FOR_DIMS(j, d) {
         double a = p.A[i * d + j];
         if (a >= 0.0) {
           slo += a * xl[j];
@@ -198,7 +232,7 @@ __device__ inline void window_dim(const SysParams& p, int i, double mlo, double 
 __device__ inline void out_tail(const SysParams& p, const double* mlo, const double* mhi,
                                 const int32_t* klo, const int32_t* W, double4* ot) {
   double smin = 0.0, smax = 0.0, stail = 0.0;
-  for (int i = 0; i < p.d; ++i) {
+  IMPACT_FOR_DIMS(i, p.d) {
     double lb = p.lb[i], ub = p.ub[i], sg = p.sigma[i];
     double qa = exit_prob(lb, ub, mlo[i], sg);
     double qb = exit_prob(lb, ub, mhi[i], sg);

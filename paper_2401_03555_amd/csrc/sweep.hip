@@ -19,366 +19,86 @@
 // inputs, the policy (lowest input on exact ties) and the state's V1 - V0 are
 // then formed in LDS; the sweep's max gap goes to the control block by a
 // 64-bit atomic max (order independent, so results are deterministic).
-#include "impact_internal.hpp"
+#include "sweep_common.hpp"
 
 namespace impact {
 
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
-constexpr int kMaxItems = 256;  // (state, input) rows per workgroup
-
-__device__ __forceinline__ uint64_t dbits(double x) { return (uint64_t)__double_as_longlong(x); }
-__device__ __forceinline__ double bitsd(uint64_t b) { return __longlong_as_double((long long)b); }
-
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-  return x;
-}
-
-__device__ __forceinline__ double wave_max(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off));
-  return x;
-}
-
-// Exclusive prefix sum across the wavefront (lane 0 gets 0).
-__device__ __forceinline__ double wave_excl_scan(double x, int lane) {
-  double incl = x;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    double y = __shfl_up(incl, off);
-    if (lane >= off) incl += y;
-  }
-  double e = __shfl_up(incl, 1);
-  return lane == 0 ? 0.0 : e;
-}
-
-// Reduction / scan over a group of NW wavefronts (NW == 1: one wavefront).
-template <int NW>
-struct Group {
-  double* red;  // 2 * NW doubles of LDS (double-buffered)
-  int tid, lane, wv;
-  int par;
-  __device__ Group(double* r, int t) : red(r), tid(t), lane(t & 63), wv(t >> 6), par(0) {}
-
-  __device__ double sum(double x) {
-    x = wave_sum(x);
-    if (NW == 1) return x;
-    if (lane == 0) red[par * NW + wv] = x;
-    __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) s += red[par * NW + w];
-    par ^= 1;
-    return s;
-  }
-
-  __device__ double excl_scan(double x) {
-    double e = wave_excl_scan(x, lane);
-    if (NW == 1) return e;
-    if (lane == 63) red[par * NW + wv] = e + x;
-    __syncthreads();
-    double pre = 0.0;
-    for (int w = 0; w < wv; ++w) pre += red[par * NW + w];
-    par ^= 1;
-    return pre + e;
-  }
+// Shared memory of the workgroup sweep.
+template <int BLOCK_E>
+struct BlockLds {
+  uint64_t xk[BLOCK_E > 0 ? 64 * kWaves * BLOCK_E : 1];
+  double red[2 * kWaves];
+  double qb0[kMaxItems], qb1[kMaxItems];
+  double gapw[kWaves];
 };
 
-// Compare-exchange of two elements held by one thread.
-template <int E>
-__device__ __forceinline__ void ce_local(uint64_t (&key)[E], double (&val)[E], int e, int e2,
-                                         bool asc) {
-  const bool sw = asc ? (key[e] > key[e2]) : (key[e] < key[e2]);
-  if (sw) {
-    uint64_t tk = key[e];
-    key[e] = key[e2];
-    key[e2] = tk;
-    double tv = val[e];
-    val[e] = val[e2];
-    val[e2] = tv;
-  }
-}
-
-// All stages of merge step k whose stride j < E (both partners in one thread).
-template <int E>
-__device__ __forceinline__ void intra_stages(uint64_t (&key)[E], double (&val)[E], int tid,
-                                             int k) {
-#pragma unroll
-  for (int j = E / 2; j > 0; j >>= 1) {
-    if (j < k) {
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int e2 = e ^ j;
-        if (e2 > e) ce_local<E>(key, val, e, e2, ((tid * E + e) & k) == 0);
-      }
-    }
-  }
-}
-
-// Bitonic sort of P = 64 * NW * E keys, thread t holding positions
-// [t*E, t*E + E) ("blocked" layout), ascending by key; val travels along.
-template <int E, int NW>
-__device__ void bitonic_sort(uint64_t (&key)[E], double (&val)[E], int tid, uint64_t* xk) {
-  constexpr int P = 64 * NW * E;
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int j = k >> 1; j >= E; j >>= 1) {
-      const int tm = j / E;  // partner thread = tid ^ tm
-      const bool lower = (tid & tm) == 0;
-      if (tm < 64) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const bool asc = ((tid * E + e) & k) == 0;
-          const uint64_t pk = (uint64_t)__shfl_xor((long long)key[e], tm);
-          const double pv = __shfl_xor(val[e], tm);
-          const bool take = (asc == lower) ? !(key[e] < pk) : !(key[e] > pk);
-          if (take) {
-            key[e] = pk;
-            val[e] = pv;
-          }
-        }
-      } else {
-        uint64_t pk[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) xk[tid * E + e] = key[e];
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < E; ++e) pk[e] = xk[(tid ^ tm) * E + e];
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < E; ++e) xk[tid * E + e] = dbits(val[e]);
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const bool asc = ((tid * E + e) & k) == 0;
-          const bool take = (asc == lower) ? !(key[e] < pk[e]) : !(key[e] > pk[e]);
-          const double pv = bitsd(xk[(tid ^ tm) * E + e]);
-          if (take) {
-            key[e] = pk[e];
-            val[e] = pv;
-          }
-        }
-        __syncthreads();
-      }
-    }
-    intra_stages<E>(key, val, tid, k);
-  }
-}
-
-// One row's entries as seen by one thread: positions [first, first + E).
-template <int E>
-struct RowSlice {
-  double lo[E], dd[E], v0[E], v1[E];
-  bool pad[E];
-};
-
-template <int E>
-__device__ void load_row(const SweepArgs& a, const SysParams& p, int64_t row, int first,
-                         RowSlice<E>& rs) {
-  const int d = a.d;
-  const int64_t base = a.row_off[row];
-  const int nw = (int)(a.row_off[row + 1] - base);
-  const int32_t* wr = a.win + row * 2 * d;
-  int32_t klo[kMaxDim], W[kMaxDim], j[kMaxDim], fo[kMaxDim];
-  int64_t t = 0;
-  int tot = 0;
-  {
-    int64_t rem = first < nw ? first : 0;
-    for (int i = d - 1; i >= 0; --i) {
-      W[i] = wr[d + i];
-      klo[i] = wr[i];
-      j[i] = nw > 0 ? (int32_t)(rem % W[i]) : 0;
-      rem = nw > 0 ? rem / W[i] : 0;
-    }
-    for (int i = 0; i < d; ++i) {
-      t += ((int64_t)klo[i] + j[i]) * p.stride[i];
-      fo[i] = tot;
-      tot += W[i];
-    }
-  }
-  const double4 o = a.ot[row];
-  const double tail_v = a.maximise ? 1.0 : 0.0;
-  const double2* fr = a.fac ? a.fac + row * (int64_t)a.fs : nullptr;
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int slot = first + e;
-    double lo = 0.0, hi = 0.0, v0 = 0.0, v1 = 0.0;
-    bool pad = false;
-    if (slot < nw) {
-      if (a.storage == IMPACT_STORE_FACTORS) {
-        lo = 1.0;
-        hi = 1.0;
-        for (int i = 0; i < d; ++i) {
-          const double2 fv = fr[fo[i] + j[i]];
-          lo *= fv.x;
-          hi *= fv.y;
-        }
-      } else {
-        const double2 b = a.ent[base + slot];
-        lo = b.x;
-        hi = b.y;
-      }
-      const double2 V = a.vin[t];
-      v0 = V.x;
-      v1 = V.y;
-      // advance the window multi-index by one (last dimension fastest)
-      for (int i = d - 1; i >= 0; --i) {
-        ++j[i];
-        t += p.stride[i];
-        if (j[i] < W[i]) break;
-        j[i] = 0;
-        t -= (int64_t)W[i] * p.stride[i];
-      }
-    } else if (slot == nw) {
-      lo = o.x;
-      hi = o.y;
-      v0 = v1 = a.out_val;
-    } else if (slot == nw + 1 && a.windowed) {
-      lo = o.z;
-      hi = o.w;
-      v0 = v1 = tail_v;
-    } else {
-      pad = true;
-    }
-    rs.lo[e] = lo;
-    rs.dd[e] = pad ? 0.0 : hi - lo;
-    rs.v0[e] = v0;
-    rs.v1[e] = v1;
-    rs.pad[e] = pad;
-  }
-}
-
-// Sorting-method LP value for one value vector (v), given r = 1 - sum(lo).
-template <int E, int NW>
-__device__ double lp_value(const RowSlice<E>& rs, const double (&v)[E], double r, bool maximise,
-                           Group<NW>& g, uint64_t* xk) {
-  double slv = 0.0;
-#pragma unroll
-  for (int e = 0; e < E; ++e) slv += rs.lo[e] * v[e];
-  slv = g.sum(slv);
-  uint64_t key[E];
-  double dk[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const uint64_t b = dbits(v[e] + 0.0);
-    key[e] = rs.pad[e] ? ~0ull : (maximise ? ~b : b);
-    dk[e] = rs.dd[e];
-  }
-  bitonic_sort<E, NW>(key, dk, g.tid, xk);
-  double ls = 0.0;
-#pragma unroll
-  for (int e = 0; e < E; ++e) ls += dk[e];
-  double acc = g.excl_scan(ls);
-  double sdv = 0.0;
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const double room = r - acc;
-    const double delta = room <= 0.0 ? 0.0 : (dk[e] < room ? dk[e] : room);
-    const double val = bitsd(maximise ? ~key[e] : key[e]);
-    if (delta > 0.0) sdv += delta * val;
-    acc += dk[e];
-  }
-  sdv = g.sum(sdv);
-  return slv + sdv;
-}
-
-template <int E, int NW>
-__device__ void solve_row(const SweepArgs& a, const SysParams& p, int64_t row, int tid,
-                          double* red, uint64_t* xk, double& q0, double& q1) {
-  // a single-wavefront group works in lane coordinates; a workgroup group
-  // first waits for every wavefront to leave the previous row's reductions
-  const int gtid = NW == 1 ? (tid & 63) : tid;
-  if (NW > 1) __syncthreads();
-  Group<NW> g(red, gtid);
-  RowSlice<E> rs;
-  load_row<E>(a, p, row, gtid * E, rs);
-  double slo = 0.0;
-#pragma unroll
-  for (int e = 0; e < E; ++e) slo += rs.lo[e];
-  slo = g.sum(slo);
-  double r = 1.0 - slo;
-  if (r < 0.0) r = 0.0;
-  const bool mx = a.maximise != 0;
-  q0 = lp_value<E, NW>(rs, rs.v0, r, mx, g, xk);
-  q1 = lp_value<E, NW>(rs, rs.v1, r, mx, g, xk);
-}
-
-template <int PASS>
-__device__ __forceinline__ int64_t item_row(const SweepArgs& a, int64_t s0, int m, int U) {
-  const int gi = m / U, ui = m - gi * U;
-  const int64_t s = a.safe[s0 + gi];
-  const int u = PASS == 0 ? ui : a.pi[s];
-  return s * a.nu + u;
-}
-
+// Sweep update of nst SAFE states (states[0..nst)) on one workgroup, all
+// their (state, input) rows; returns, on thread t < nst, state t's V1 - V0.
 // WAVE_E: largest per-lane element count of single-wavefront rows (row
 // length <= 64 * WAVE_E); BLOCK_E: largest per-thread count of workgroup rows
 // (row length <= 256 * BLOCK_E), 0 when every row fits one wavefront.
-// PASS 0: all inputs (policy pass); PASS 1: the input fixed by the policy.
-// The two passes are separate kernel symbols so that profiles tell them apart.
 template <int WAVE_E, int BLOCK_E, int PASS>
-__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
-  if (a.ctrl->done) return;
-  __shared__ uint64_t xk[BLOCK_E > 0 ? 64 * kWaves * BLOCK_E : 1];
-  __shared__ double red[2 * kWaves];
-  __shared__ double qb0[kMaxItems], qb1[kMaxItems];
-  __shared__ double gapw[kWaves];
+__device__ double block_sweep_states(const SweepArgs& a, const int32_t* __restrict__ states,
+                                     int nst, BlockLds<BLOCK_E>& L) {
   const SysParams& p = *a.sys;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int G = a.states_per_block, U = a.inputs_per_state;
-  const int64_t s0 = (int64_t)blockIdx.x * G;
-  const int nst = (int)(a.n_safe - s0 < G ? a.n_safe - s0 : G);
+  const int tid = threadIdx.x, lane = tid & 63, wv = uniform_i32(tid >> 6);
+  const int U = PASS == 0 ? a.nu : 1;
   const int items = nst * U;
   const int extra = 1 + a.windowed;
+  auto row_of = [&](int m) -> int64_t {
+    const int gi = m / U, ui = m - gi * U;
+    const int64_t s = states[gi];
+    const int u = PASS == 0 ? ui : a.pi[s];
+    return s * a.nu + u;
+  };
 
   if constexpr (BLOCK_E > 0) {
     // rows longer than one wavefront's capacity: the whole workgroup
     for (int m = 0; m < items; ++m) {
-      const int64_t row = item_row<PASS>(a, s0, m, U);
+      const int64_t row = row_of(m);
       const int n = (int)(a.row_off[row + 1] - a.row_off[row]) + extra;
       if (n <= 64 * WAVE_E) continue;
       double q0, q1;
       if (BLOCK_E <= 4 || n <= 1024)
-        solve_row<4, kWaves>(a, p, row, tid, red, xk, q0, q1);
+        solve_row<4, kWaves>(a, p, row, tid, L.red, L.xk, q0, q1);
       else if (BLOCK_E <= 8 || n <= 2048)
-        solve_row<(BLOCK_E < 8 ? BLOCK_E : 8), kWaves>(a, p, row, tid, red, xk, q0, q1);
+        solve_row<(BLOCK_E < 8 ? BLOCK_E : 8), kWaves>(a, p, row, tid, L.red, L.xk, q0, q1);
       else
-        solve_row<BLOCK_E, kWaves>(a, p, row, tid, red, xk, q0, q1);
+        solve_row<BLOCK_E, kWaves>(a, p, row, tid, L.red, L.xk, q0, q1);
       if (tid == 0) {
-        qb0[m] = q0;
-        qb1[m] = q1;
+        L.qb0[m] = q0;
+        L.qb1[m] = q1;
       }
     }
   }
   // short rows: one wavefront each
   for (int m = wv; m < items; m += kWaves) {
-    const int64_t row = item_row<PASS>(a, s0, m, U);
+    const int64_t row = row_of(m);
     const int n = (int)(a.row_off[row + 1] - a.row_off[row]) + extra;
     if (n > 64 * WAVE_E) continue;
     double q0, q1;
     if (WAVE_E == 1 || n <= 64)
-      solve_row<1, 1>(a, p, row, tid, red, xk, q0, q1);
+      solve_row<1, 1>(a, p, row, tid, L.red, L.xk, q0, q1);
     else if (WAVE_E == 2 || n <= 128)
-      solve_row<(WAVE_E < 2 ? WAVE_E : 2), 1>(a, p, row, tid, red, xk, q0, q1);
+      solve_row<(WAVE_E < 2 ? WAVE_E : 2), 1>(a, p, row, tid, L.red, L.xk, q0, q1);
     else if (WAVE_E == 4 || n <= 256)
-      solve_row<(WAVE_E < 4 ? WAVE_E : 4), 1>(a, p, row, tid, red, xk, q0, q1);
+      solve_row<(WAVE_E < 4 ? WAVE_E : 4), 1>(a, p, row, tid, L.red, L.xk, q0, q1);
     else
-      solve_row<WAVE_E, 1>(a, p, row, tid, red, xk, q0, q1);
+      solve_row<WAVE_E, 1>(a, p, row, tid, L.red, L.xk, q0, q1);
     if (lane == 0) {
-      qb0[m] = q0;
-      qb1[m] = q1;
+      L.qb0[m] = q0;
+      L.qb1[m] = q1;
     }
   }
   __syncthreads();
 
   double gap = 0.0;
   if (tid < nst) {
-    const int64_t s = a.safe[s0 + tid];
-    double b0 = qb0[tid * U], b1 = qb1[tid * U];
+    const int64_t s = states[tid];
+    double b0 = L.qb0[tid * U], b1 = L.qb1[tid * U];
     int arg = 0;
     for (int ui = 1; ui < U; ++ui) {
-      const double q0 = qb0[tid * U + ui], q1 = qb1[tid * U + ui];
+      const double q0 = L.qb0[tid * U + ui], q1 = L.qb1[tid * U + ui];
       if (a.reach ? (q0 > b0) : (q0 < b0)) {
         b0 = q0;
         arg = ui;
@@ -390,24 +110,47 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
     gap = b1 - b0;
     if (!(gap > 0.0)) gap = 0.0;
   }
+  return gap;
+}
+
+// PASS 0: all inputs (policy pass); PASS 1: the input fixed by the policy.
+// The two passes are separate kernel symbols so that profiles tell them apart.
+template <int WAVE_E, int BLOCK_E, int PASS>
+__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
+  if (a.ctrl->done) return;
+  __shared__ BlockLds<BLOCK_E> L;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int G = a.states_per_block;
+  const int64_t s0 = (int64_t)blockIdx.x * G;
+  const int nst = (int)(a.n_safe - s0 < G ? a.n_safe - s0 : G);
+  double gap = block_sweep_states<WAVE_E, BLOCK_E, PASS>(a, a.safe + s0, nst, L);
   gap = wave_max(gap);
-  if (lane == 0) gapw[wv] = gap;
+  if (lane == 0) L.gapw[wv] = gap;
   __syncthreads();
   if (tid == 0) {
-    double gm = gapw[0];
-    for (int w = 1; w < kWaves; ++w) gm = fmax(gm, gapw[w]);
-    atomicMax(&a.ctrl->gap_bits, (unsigned long long)dbits(gm));
+    double gm = L.gapw[0];
+    for (int w = 1; w < kWaves; ++w) gm = fmax(gm, L.gapw[w]);
+    a.gap_part[blockIdx.x] = gm;
   }
 }
 
-// Close one sweep: record its gap, count it, stop on eps or the cap.
-__global__ void k_finish(Ctrl* c) {
-  if (threadIdx.x != 0 || c->done) return;
-  const double gap = bitsd(c->gap_bits);
-  c->gap_bits = 0ull;
+// Close one sweep: reduce the workgroups' gap partials, count the sweep, stop
+// on eps or the cap.
+__global__ __launch_bounds__(1024) void k_finish(Ctrl* c, const double* __restrict__ part,
+                                                 int64_t n_part) {
+  __shared__ double wmax[16];
+  if (c->done) return;
+  double g = 0.0;
+  for (int64_t i = threadIdx.x; i < n_part; i += blockDim.x) g = fmax(g, part[i]);
+  g = wave_max(g);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = g;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) g = fmax(g, wmax[w]);
+  g = fmax(g, wmax[0]);
   c->sweeps += 1;
-  c->gap = gap;
-  if (gap <= c->eps) {
+  c->gap = g;
+  if (g <= c->eps) {
     c->done = 1;
     c->converged = 1;
   } else if (c->sweeps >= c->cap) {
@@ -562,9 +305,14 @@ hipError_t launch_sweep(const SweepArgs& a, int32_t max_row, hipStream_t st) {
   return a.pass == 0 ? launch_sweep_pass<0>(a, max_row, st) : launch_sweep_pass<1>(a, max_row, st);
 }
 
-hipError_t launch_finish(Ctrl* c, hipStream_t st) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, c);
+hipError_t launch_finish(Ctrl* c, const double* part, int64_t n_part, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, st, c, part, n_part);
   return hipGetLastError();
+}
+
+int64_t sweep_blocks(const SweepArgs& a, bool box_path) {
+  if (box_path) return (a.n_safe + kSbWavesPerBlock - 1) / kSbWavesPerBlock;
+  return (a.n_safe + a.states_per_block - 1) / a.states_per_block;
 }
 
 hipError_t launch_finalize(const int8_t* cls, int64_t n, const double2* v, const int32_t* pi,

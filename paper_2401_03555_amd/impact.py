@@ -24,7 +24,9 @@ STORAGE = {"auto": 0, "bounds": 1, "factors": 2}
 # Every function the header declares (checked by the test suite).
 EXPORTS = ["impact_build_imdp", "impact_interval_iterate", "impact_last_iter_info",
            "impact_imdp_get_info", "impact_imdp_export_rows", "impact_set_timing",
-           "impact_imdp_free", "impact_last_error", "impact_version"]
+           "impact_imdp_free", "impact_last_error", "impact_version", "impact_set_sweep_mode",
+           "impact_build_imdp_batch"]
+SWEEP_MODES = {"auto": 0, "per_row": 1, "state_box": 2}
 
 _pd = C.POINTER(C.c_double)
 _pi32 = C.POINTER(C.c_int32)
@@ -78,8 +80,8 @@ class IterInfo(C.Structure):
 class ImdpInfo(C.Structure):
     _fields_ = [("n_states", C.c_int64), ("n_rows", C.c_int64), ("n_entries", C.c_int64),
                 ("dim", C.c_int32), ("n_inputs", C.c_int32), ("windowed", C.c_int32),
-                ("storage", C.c_int32), ("max_row", C.c_int32), ("device_bytes", C.c_int64),
-                ("build_ms", C.c_double)]
+                ("storage", C.c_int32), ("max_row", C.c_int32), ("max_box", C.c_int64),
+                ("device_bytes", C.c_int64), ("build_ms", C.c_double)]
 
 
 class ImpactError(RuntimeError):
@@ -103,6 +105,11 @@ def lib():
         L.impact_build_imdp.argtypes = [C.POINTER(System), C.POINTER(Grid), C.POINTER(Inputs),
                                         C.POINTER(Noise), C.POINTER(Window), C.POINTER(Device),
                                         C.POINTER(C.c_void_p)]
+        L.impact_build_imdp_batch.restype = C.c_int
+        L.impact_build_imdp_batch.argtypes = [C.c_int32, C.POINTER(System), C.POINTER(Grid),
+                                              C.POINTER(Inputs), C.POINTER(Noise),
+                                              C.POINTER(Window), C.POINTER(Device),
+                                              C.POINTER(C.c_void_p)]
         L.impact_interval_iterate.restype = C.c_int
         L.impact_interval_iterate.argtypes = [C.c_void_p, C.POINTER(Spec), C.c_double, _pd, _pd,
                                               _pi32]
@@ -113,6 +120,8 @@ def lib():
         L.impact_imdp_export_rows.restype = C.c_int
         L.impact_imdp_export_rows.argtypes = [C.c_void_p, C.c_int64, C.c_int64, _pi32, _pd,
                                               _pi64, _pd]
+        L.impact_set_sweep_mode.restype = C.c_int
+        L.impact_set_sweep_mode.argtypes = [C.c_void_p, C.c_int32]
         L.impact_set_timing.restype = C.c_int
         L.impact_set_timing.argtypes = [C.c_void_p, C.c_int32]
         L.impact_imdp_free.restype = None
@@ -208,6 +217,9 @@ class Imdp:
         _check(lib().impact_imdp_get_info(self._h, C.byref(i)))
         return {f: getattr(i, f) for f, _ in ImdpInfo._fields_}
 
+    def set_sweep_mode(self, mode):
+        _check(lib().impact_set_sweep_mode(self._h, SWEEP_MODES[mode]))
+
     def set_timing(self, enable=True):
         _check(lib().impact_set_timing(self._h, int(bool(enable))))
 
@@ -276,7 +288,8 @@ class Imdp:
             pass
 
 
-def build_imdp(system, k_sigma=None, storage="bounds", stream=None, timing=False):
+def build_imdp(system, k_sigma=None, storage="bounds", stream=None, timing=False,
+               sweep_mode="auto"):
     """Build the abstraction of ``system`` on the current CUDA(HIP) device."""
     m = _Marshal(system)
     dev = _TorchDevice(stream)
@@ -288,7 +301,29 @@ def build_imdp(system, k_sigma=None, storage="bounds", stream=None, timing=False
     imdp = Imdp(h.value, dev)
     if timing:
         imdp.set_timing(True)
+    if sweep_mode != "auto":
+        imdp.set_sweep_mode(sweep_mode)
     return imdp
+
+
+def build_imdp_batch(systems, storage="bounds", stream=None, sweep_mode="auto"):
+    """Build several abstractions with one launch of each construction kernel."""
+    n = len(systems)
+    ms = [_Marshal(s) for s in systems]
+    dev = _TorchDevice(stream)
+    SysA, GridA, InA, NoiseA, WinA = (System * n), (Grid * n), (Inputs * n), (Noise * n), (Window * n)
+    sa = SysA(*[m.sys for m in ms])
+    ga = GridA(*[m.grid for m in ms])
+    ia = InA(*[m.inp for m in ms])
+    na = NoiseA(*[m.noise for m in ms])
+    wa = WinA(*[Window(float(s.get("k_sigma", 0.0)), STORAGE[storage]) for s in systems])
+    hs = (C.c_void_p * n)()
+    _check(lib().impact_build_imdp_batch(n, sa, ga, ia, na, wa, C.byref(dev.struct), hs))
+    out = [Imdp(h, dev) for h in hs]
+    if sweep_mode != "auto":
+        for m in out:
+            m.set_sweep_mode(sweep_mode)
+    return out
 
 
 def version():

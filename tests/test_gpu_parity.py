@@ -328,3 +328,74 @@ def test_ragged_rows_mix_wave_and_block_paths(I):
     ro = oracle.iterate(o["n_states"], 3, o["row_ptr"], o["target"], o["lo"], o["hi"], cls,
                         "reach_avoid", 1e-8, 40, want_q0=True)
     compare_iter(rg, ro, cls, True, "ragged", q0=ro["q0"])
+
+
+# ---------------------------------------------------------------------------
+# sweep modes: one sort per row vs one sort per state box
+# ---------------------------------------------------------------------------
+
+def _wide_box_system():
+    # rows of <= 400 entries whose inputs shift the mean by +-5 cells, so most
+    # state boxes exceed 512 cells and those states sort per row
+    return dict(kind="affine", A=np.eye(2), B=np.array([[1.0], [0.0]]), c=np.zeros(2),
+                lb=[-10.0, -10.0], ub=[10.0, 10.0], n=[40, 40], inputs=[[-2.5], [0.0], [2.5]],
+                sigma=[0.8, 0.8], k_sigma=6.0)
+
+
+MODE_CASES = {
+    "affine2_window": (SMALL_SYSTEMS["affine2_window"], SPECS["affine2_window"], 3000),
+    "unicycle_small": (SMALL_SYSTEMS["unicycle_small"], SPECS["unicycle_small"], 3000),
+    "affine1_window": (SMALL_SYSTEMS["affine1_window"], SPECS["affine1_window"], 500),
+    "robot2d_K60": (SMALL_SYSTEMS["robot2d"], dict(kind="reach_avoid",
+                                                   target=[[[5.0, 5.0], [8.0, 8.0]]],
+                                                   avoid=[[[-2.0, -2.0], [2.0, 2.0]]]), 60),
+    "wide_box": (_wide_box_system, dict(kind="reach_avoid", target=[[[4.0, 4.0], [8.0, 8.0]]],
+                                        avoid=[[[-3.0, -3.0], [0.0, 0.0]]]), 30),
+}
+
+
+@pytest.mark.parametrize("mode", ["per_row", "state_box"])
+@pytest.mark.parametrize("case", list(MODE_CASES))
+def test_sweep_modes_match_oracle(I, case, mode):
+    make, spec, K = MODE_CASES[case]
+    system = make()
+    spec = dict(spec, eps=1e-8, max_sweeps=K)
+    g = I.build_imdp(system, sweep_mode=mode)
+    info = g.info()
+    say(f"{case} [{mode}]: max_row {info['max_row']} max_box {info['max_box']}")
+    if case == "wide_box":
+        assert info["max_box"] > 512 >= info["max_row"]
+    rg = g.iterate(spec)
+    m = oracle.build(system, system["k_sigma"])
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    ro = oracle.iterate(m["n_states"], m["n_inputs"], m["row_ptr"], m["target"], m["lo"], m["hi"],
+                        cls, spec["kind"], spec["eps"], K, want_q0=True)
+    compare_iter(rg, ro, cls, spec["kind"] != "safety", f"{case}[{mode}]", q0=ro["q0"])
+
+
+# ---------------------------------------------------------------------------
+# batch construction: one launch per kernel over several systems
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("storage", ["bounds", "factors"])
+def test_batch_build_equals_separate_builds(I, storage):
+    systems = [SMALL_SYSTEMS["affine2_window"](), SMALL_SYSTEMS["affine1_window"](),
+               SMALL_SYSTEMS["affine3_window"](), SMALL_SYSTEMS["unicycle_small"](),
+               W.tiny_affine(d=2, n=13, seed=21), _wide_box_system()]
+    views = I.build_imdp_batch(systems, storage=storage)
+    for k, (system, v) in enumerate(zip(systems, views)):
+        single = I.build_imdp(system, storage=storage)
+        a, b = v.info(), single.info()
+        for key in ("n_states", "n_rows", "n_entries", "dim", "n_inputs", "max_row", "max_box"):
+            assert a[key] == b[key], (k, key, a[key], b[key])
+        R = a["n_rows"]
+        ea, eb = v.export_rows(0, R), single.export_rows(0, R)
+        for key in ("win", "ot", "counts", "entries"):
+            assert np.array_equal(ea[key], eb[key]), (k, key)
+    # the views iterate exactly like separately built handles
+    spec = dict(SPECS["affine2_window"], eps=1e-8, max_sweeps=200)
+    r1 = views[0].iterate(spec)
+    r2 = I.build_imdp(systems[0], storage=storage).iterate(spec)
+    for key in ("lo", "hi", "policy"):
+        assert bool((r1[key] == r2[key]).all()), key
+    del views
