@@ -237,7 +237,8 @@ int impact_imdp_export_rows(const impact_imdp *imdp, int64_t row0, int64_t nrows
                             double *entries);
 
 /* How interval iteration orders entries (all give the same LP values).
- *   AUTO       : STATE_BOX when every row has at most 512 entries, else PER_ROW
+ *   AUTO       : the policy pass uses STATE_BOX when every row has at most 512
+ *                entries; the fixed-input pass (one row per state) PER_ROW
  *   PER_ROW    : one bitonic sort per (state, input) row
  *   STATE_BOX  : one bitonic sort per state over the bounding box of its rows'
  *                windows; each row takes its order from it (the order of a
@@ -250,6 +251,51 @@ int impact_set_sweep_mode(impact_imdp *imdp, int32_t mode);
 
 /* Enable (1) / disable (0) per-kernel HIP-event timing on this handle. */
 int impact_set_timing(impact_imdp *imdp, int32_t enable);
+
+/*
+ * Multi-query engine: many interval-iteration queries in flight together
+ * (the batched and served forms).  A query is (abstraction, specification,
+ * eps) with the semantics and outputs of impact_interval_iterate; each runs
+ * its own two passes and stop test, but every step advances all unfinished
+ * queries with one launch per sweep kernel, and chunks of steps are replayed
+ * from a captured HIP graph.  Queries join (submit) and leave (poll) at step
+ * boundaries.  A query's results do not depend on the other queries in
+ * flight.  The engine uses its own HIP stream; calls first wait for the
+ * caller's stream (impact_device.stream) and return with the engine idle.
+ */
+typedef struct impact_mq impact_mq;
+
+/* Create an engine with room for max_queries concurrent queries.  dev: as for
+ * impact_build_imdp (allocator for the engine's and the queries' buffers). */
+int impact_mq_create(const impact_device *dev, int32_t max_queries, impact_mq **out);
+
+/* Add a query.  lo, hi, policy: caller-owned DEVICE buffers of the
+ * abstraction's n_states elements, written as impact_interval_iterate would
+ * once the query finishes (cells outside the SAFE set immediately).  The
+ * abstraction handle may be released after submitting (the engine keeps its
+ * device storage alive until the query is polled).  *id receives the query id.
+ * Errors: E_INVAL (bad spec/eps/buffers), E_UNSUPPORTED (no free slot),
+ * E_NOMEM, E_HIP. */
+int impact_mq_submit(impact_mq *mq, const impact_imdp *imdp, const impact_spec *spec, double eps,
+                     double *lo, double *hi, int32_t *policy, int32_t *id);
+
+/* Run up to `steps` steps (at least 1); returns early once every submitted
+ * query has finished.  *n_active (may be NULL) receives the number of
+ * unfinished queries. */
+int impact_mq_run(impact_mq *mq, int32_t steps, int32_t *n_active);
+
+/* Ids of queries finished since the last poll (up to cap, host array); their
+ * outputs are final and their slots are released.  *n receives the count. */
+int impact_mq_poll(impact_mq *mq, int32_t *ids, int32_t cap, int32_t *n);
+
+/* Sweep counts, gaps and convergence flags of a finished query. */
+int impact_mq_query_info(const impact_mq *mq, int32_t id, impact_iter_info *info);
+
+/* Message for the last failing impact_mq_* call on this thread. */
+const char *impact_mq_last_error(void);
+
+/* Destroy the engine (unfinished queries are dropped).  NULL is a no-op. */
+void impact_mq_free(impact_mq *mq);
 
 /* Release the handle; its device buffers go with the last handle of its build.
  * NULL is a no-op. */

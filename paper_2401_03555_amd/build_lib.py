@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libimpact.so")
-SOURCES = ["abi.hip", "build.hip", "sweep.hip", "sweep_sb.hip"]
+SOURCES = ["abi.hip", "build.hip", "sweep.hip", "sweep_sb.hip", "mq.hip"]
 
 
 def hipcc() -> str:

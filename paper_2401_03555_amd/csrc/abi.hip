@@ -243,6 +243,32 @@ int guarded(F&& f) {
 
 }  // namespace
 
+namespace impact {
+int imdp_view(const impact_imdp* h, ImdpView* v) {
+  if (!h || !v) return IMPACT_E_INVAL;
+  std::memset(&v->a, 0, sizeof(v->a));
+  v->a.row_off = h->row_off;
+  v->a.win = h->win;
+  v->a.ot = h->ot;
+  v->a.ent = h->ent;
+  v->a.fac = h->fac;
+  v->a.sys = h->dp;
+  v->a.fs = h->fs;
+  v->a.nu = h->nu;
+  v->a.d = h->d;
+  v->a.windowed = h->windowed;
+  v->a.storage = h->storage;
+  v->dp = h->dp;
+  v->n_states = h->n_states;
+  v->max_box = h->max_box;
+  v->max_row = h->max_row;
+  v->d = h->d;
+  v->nu = h->nu;
+  v->keep = h->store;
+  return IMPACT_OK;
+}
+}  // namespace impact
+
 extern "C" {
 
 const char* impact_last_error(void) { return g_err.c_str(); }
@@ -566,10 +592,13 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       return e;
     };
     Ctrl hc{};
-    // one sort per state over its rows' window box when every row fits a
-    // wavefront; otherwise one sort per row
-    const bool use_box = h->max_row <= 512 && h->sweep_mode != IMPACT_SWEEP_PER_ROW;
     for (int pass = 0; pass < 2; ++pass) {
+      // policy pass: one sort per state over its rows' window box when every
+      // row fits a wavefront; the fixed-input pass has one row per state and
+      // sorts per row unless the state-box mode is forced
+      const bool use_box = h->max_row <= 512 &&
+                           (pass == 0 ? h->sweep_mode != IMPACT_SWEEP_PER_ROW
+                                      : h->sweep_mode == IMPACT_SWEEP_STATE_BOX);
       SweepArgs a{};
       a.row_off = h->row_off;
       a.win = h->win;

@@ -37,6 +37,50 @@ struct SweepArgs {
   double out_val;          // objective value of OUT
 };
 
+// One interval-iteration query of the multi-query engine (device table).
+// a holds the abstraction's pointers and the query's value buffers; vin,
+// vout, pass and maximise are set per step from the query's control block.
+struct QueryDesc {
+  SweepArgs a;
+  double2* vb0;
+  double2* vb1;
+  double* lo;
+  double* hi;
+  int32_t* pol;
+  int32_t safety;
+  int32_t box_class;        // 1: state-box kernel class, 0: workgroup kernel class
+  double eps;
+  int64_t cap;
+  int64_t work_begin, work_end;  // its items in its class's work list
+};
+
+// Phase machine of one query: 0 policy pass, 1 close pass 1 (write lo and the
+// policy, reset values), 2 fixed-input pass, 3 close pass 2 (write hi), 4 done.
+struct QueryCtrl {
+  int32_t phase, pad;
+  int32_t converged[2];
+  int64_t step;       // value-buffer steps applied (ping-pong parity)
+  int64_t sweeps[2];
+  double gap[2];
+};
+
+}  // namespace impact
+
+#include <memory>
+struct impact_imdp;
+
+namespace impact {
+
+// What the multi-query engine needs of a built abstraction.
+struct ImdpView {
+  SweepArgs a;  // abstraction pointers and sizes (query fields unset)
+  const SysParams* dp;
+  int64_t n_states, max_box;
+  int32_t max_row, d, nu;
+  std::shared_ptr<void> keep;  // the abstraction's device storage
+};
+int imdp_view(const impact_imdp* h, ImdpView* v);
+
 // Scan: out[0..n] = exclusive prefix sums of in[0..n), out[n] = total.
 hipError_t exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp,
                               int64_t tmp_elems, hipStream_t st);
@@ -70,6 +114,14 @@ hipError_t launch_state_box_max(const BuildTable& T, int64_t n_states, const int
 hipError_t launch_finish(Ctrl* c, const double* part, int64_t n_part, hipStream_t st);
 constexpr int kSbWavesPerBlock = 2;  // state-box sweep: wavefronts (= states) per workgroup
 int64_t sweep_blocks(const SweepArgs& a, bool box_path);
+
+// Multi-query engine launchers.
+hipError_t launch_mq_sweep_sb(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
+                              const int32_t* ws, int64_t n_items, double* gap_item,
+                              int64_t max_box, int32_t max_row, hipStream_t st);
+hipError_t launch_mq_sweep_block(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
+                                 const int32_t* ws, int64_t n_items, double* gap_item,
+                                 int32_t max_row, hipStream_t st);
 hipError_t launch_finalize(const int8_t* cls, int64_t n, const double2* v, const int32_t* pi,
                            int32_t pass, int32_t safety, double* out, int32_t* policy,
                            hipStream_t st);

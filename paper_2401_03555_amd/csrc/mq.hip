@@ -1,0 +1,594 @@
+// mq.hip -- many interval-iteration queries in flight on one device.
+//
+// Each query is a (built abstraction, specification, eps) triple with its own
+// labels, SAFE list, (V0, V1) buffers, policy and outputs.  The engine runs
+// all of them together: one step = one launch of each sweep kernel over the
+// (query, SAFE state) items of every unfinished query, followed by one launch
+// of k_mq_finish, which applies each query's own stop test and moves it along
+// its phase machine (policy pass, close, fixed-input pass, close, done).  So
+// queries of very different sizes and convergence speeds share launches, and
+// a query's result does not depend on which others run beside it (every
+// state's update reads only its own query's data).  Chunks of steps are
+// captured once into a HIP graph and replayed; the host polls a done counter
+// between replays, and queries join or leave at those boundaries.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "impact_internal.hpp"
+
+using namespace impact;
+
+namespace impact {
+
+// Per-query stop test and phase machine (one workgroup per query slot).
+__global__ __launch_bounds__(256) void k_mq_finish(const QueryDesc* __restrict__ desc,
+                                                   QueryCtrl* __restrict__ ctrl,
+                                                   const double* __restrict__ gap_sb,
+                                                   const double* __restrict__ gap_blk,
+                                                   int32_t* __restrict__ done_count) {
+  __shared__ double wmax[4];
+  const int q = blockIdx.x;
+  const int phase = ctrl[q].phase;
+  if (phase == 4) return;
+  const QueryDesc& D = desc[q];
+  double g = 0.0;
+  if (phase == 0 || phase == 2) {
+    const double* gp = D.box_class ? gap_sb : gap_blk;
+    for (int64_t i = D.work_begin + threadIdx.x; i < D.work_end; i += blockDim.x)
+      g = fmax(g, gp[i]);
+    for (int off = 32; off > 0; off >>= 1) g = fmax(g, __shfl_xor(g, off));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = g;
+    __syncthreads();
+    g = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+  }
+  if (threadIdx.x != 0) return;
+  QueryCtrl& c = ctrl[q];
+  if (phase == 0 || phase == 2) {
+    const int pass = phase >> 1;
+    c.sweeps[pass] += 1;
+    c.gap[pass] = g;
+    c.step += 1;
+    if (g <= D.eps) {
+      c.converged[pass] = 1;
+      c.phase = phase + 1;
+    } else if (c.sweeps[pass] >= D.cap) {
+      c.phase = phase + 1;
+    }
+  } else if (phase == 1) {
+    c.step += 1;
+    // the fixed-input pass starts from a gap of 1: it runs no sweep if eps >= 1
+    c.phase = 1.0 <= D.eps ? 3 : 2;
+    c.gap[1] = 1.0;
+    c.converged[1] = 1.0 <= D.eps;
+  } else {
+    c.phase = 4;
+    atomicAdd(done_count, 1);
+  }
+}
+
+// Work-list fill: segment k copies its query's SAFE list to [dst, dst + n).
+struct MqSegment {
+  const int32_t* safe;
+  int64_t dst, n;
+  int32_t slot, box_class;
+};
+
+__global__ void k_mq_fill(const MqSegment* __restrict__ seg, int32_t* __restrict__ wq_sb,
+                          int32_t* __restrict__ ws_sb, int32_t* __restrict__ wq_blk,
+                          int32_t* __restrict__ ws_blk) {
+  const MqSegment S = seg[blockIdx.x];
+  int32_t* wq = S.box_class ? wq_sb : wq_blk;
+  int32_t* ws = S.box_class ? ws_sb : ws_blk;
+  for (int64_t i = threadIdx.x; i < S.n; i += blockDim.x) {
+    wq[S.dst + i] = S.slot;
+    ws[S.dst + i] = S.safe[i];
+  }
+}
+
+}  // namespace impact
+
+namespace {
+
+thread_local std::string g_mq_err;
+int mq_fail(int code, const std::string& m) {
+  g_mq_err = m;
+  return code;
+}
+
+struct MqNoMem {};
+
+struct MqQuery {
+  int32_t id = -1;
+  bool active = false;    // occupies its slot
+  bool finished = false;  // reported by a poll
+  int64_t n_safe = 0, n_states = 0;
+  int32_t box_class = 1, max_row = 0, nu = 1;
+  int64_t max_box = 0;
+  std::shared_ptr<void> keep;  // keeps the abstraction's storage alive
+  std::vector<void*> bufs;
+  int32_t* safe = nullptr;
+};
+
+}  // namespace
+
+struct impact_mq {
+  impact_device dev{};
+  hipStream_t user_st = nullptr;  // the caller's stream
+  hipStream_t st = nullptr;       // the engine's own stream (graphs are captured on it)
+  int32_t cap = 0;
+  std::vector<MqQuery> slots;
+  int32_t next_id = 0;
+  std::map<int32_t, impact_iter_info> finished_info;
+  std::vector<int32_t> unreported;
+  QueryDesc* d_desc = nullptr;
+  QueryCtrl* d_ctrl = nullptr;
+  int32_t* d_done = nullptr;
+  std::vector<QueryDesc> h_desc;
+  // work lists
+  int32_t *wq_sb = nullptr, *ws_sb = nullptr, *wq_blk = nullptr, *ws_blk = nullptr;
+  double *gap_sb = nullptr, *gap_blk = nullptr;
+  int64_t cap_sb = 0, cap_blk = 0, n_sb = 0, n_blk = 0;
+  int64_t max_box_sb = 1;
+  int32_t max_row_sb = 1, max_row_blk = 513;
+  int32_t n_slots_used = 0;
+  bool dirty = true;
+  // captured chunk of steps
+  hipGraphExec_t exec = nullptr;
+  int32_t graph_steps = 0;
+  int64_t live_submitted = 0;  // queries with SAFE states ever submitted
+  int64_t steps_run = 0;
+  bool hip_used = false;
+
+  void* alloc(size_t nbytes) {
+    if (nbytes == 0) nbytes = 8;
+    void* p = nullptr;
+    if (dev.alloc) {
+      p = dev.alloc(nbytes, dev.ctx);
+    } else if (hipMalloc(&p, nbytes) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    if (!p) throw MqNoMem{};
+    return p;
+  }
+  void release(void* p) {
+    if (!p) return;
+    if (dev.free)
+      dev.free(p, dev.ctx);
+    else
+      (void)hipFree(p);
+  }
+  void sync() {
+    if (hip_used) (void)hipStreamSynchronize(st);
+  }
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    graph_steps = 0;
+  }
+  // Work submitted by the caller on its stream is complete before ours starts.
+  void join_user() {
+    if (!hip_used) return;
+    (void)hipStreamSynchronize(user_st);
+  }
+  ~impact_mq() {
+    sync();
+    drop_graph();
+    for (auto& q : slots)
+      for (void* p : q.bufs) release(p);
+    for (void* p : {(void*)d_desc, (void*)d_ctrl, (void*)d_done, (void*)wq_sb, (void*)ws_sb,
+                    (void*)wq_blk, (void*)ws_blk, (void*)gap_sb, (void*)gap_blk})
+      release(p);
+    if (st) (void)hipStreamDestroy(st);
+  }
+};
+
+namespace {
+
+struct MqHipError {
+  hipError_t e;
+  const char* what;
+};
+
+#define MQ_TRY(expr)                                   \
+  do {                                                 \
+    hipError_t _e = (expr);                            \
+    if (_e != hipSuccess) throw MqHipError{_e, #expr}; \
+  } while (0)
+
+template <class F>
+int mq_guarded(F&& f) {
+  try {
+    return f();
+  } catch (const MqNoMem&) {
+    return mq_fail(IMPACT_E_NOMEM, "device allocation failed");
+  } catch (const MqHipError& e) {
+    return mq_fail(IMPACT_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  } catch (...) {
+    return mq_fail(IMPACT_E_INVAL, "unknown error");
+  }
+}
+
+// Grow a device array (contents are rebuilt by the caller).
+template <class T>
+void ensure(impact_mq* m, T*& p, int64_t& cap, int64_t need) {
+  if (need <= cap && p) return;
+  const int64_t nc = std::max<int64_t>(need, std::max<int64_t>(1024, cap * 2));
+  if (p) m->release(p);
+  p = nullptr;
+  p = (T*)m->alloc((size_t)nc * sizeof(T));
+  cap = nc;
+}
+
+// Rebuild the work lists from the live (unfinished) queries.
+void rebuild(impact_mq* m) {
+  std::vector<MqSegment> seg;
+  int64_t nsb = 0, nblk = 0;
+  int64_t mbox = 1;
+  int32_t mrow_sb = 1, mrow_blk = 513;
+  for (int32_t k = 0; k < m->n_slots_used; ++k) {
+    MqQuery& q = m->slots[k];
+    QueryDesc& D = m->h_desc[k];
+    if (!q.active || q.finished || q.n_safe == 0) {
+      D.work_begin = D.work_end = 0;
+      continue;
+    }
+    MqSegment S;
+    S.safe = q.safe;
+    S.n = q.n_safe;
+    S.slot = k;
+    S.box_class = q.box_class;
+    if (q.box_class) {
+      S.dst = nsb;
+      nsb += q.n_safe;
+      mbox = std::max(mbox, q.max_box);
+      mrow_sb = std::max(mrow_sb, q.max_row);
+    } else {
+      S.dst = nblk;
+      nblk += q.n_safe;
+      mrow_blk = std::max(mrow_blk, q.max_row);
+    }
+    D.work_begin = S.dst;
+    D.work_end = S.dst + S.n;
+    seg.push_back(S);
+  }
+  int64_t c1 = m->cap_sb, c2 = m->cap_sb, c3 = m->cap_sb;
+  ensure(m, m->wq_sb, c1, nsb);
+  ensure(m, m->ws_sb, c2, nsb);
+  ensure(m, m->gap_sb, c3, nsb);
+  m->cap_sb = std::min({c1, c2, c3});
+  int64_t b1 = m->cap_blk, b2 = m->cap_blk, b3 = m->cap_blk;
+  ensure(m, m->wq_blk, b1, nblk);
+  ensure(m, m->ws_blk, b2, nblk);
+  ensure(m, m->gap_blk, b3, nblk);
+  m->cap_blk = std::min({b1, b2, b3});
+  m->n_sb = nsb;
+  m->n_blk = nblk;
+  m->max_box_sb = mbox;
+  m->max_row_sb = mrow_sb;
+  m->max_row_blk = mrow_blk;
+  if (!seg.empty()) {
+    MqSegment* d_seg = (MqSegment*)m->alloc(sizeof(MqSegment) * seg.size());
+    MQ_TRY(hipMemcpyAsync(d_seg, seg.data(), sizeof(MqSegment) * seg.size(),
+                          hipMemcpyHostToDevice, m->st));
+    hipLaunchKernelGGL(k_mq_fill, dim3((unsigned)seg.size()), dim3(256), 0, m->st, d_seg, m->wq_sb,
+                       m->ws_sb, m->wq_blk, m->ws_blk);
+    MQ_TRY(hipGetLastError());
+    MQ_TRY(hipStreamSynchronize(m->st));
+    m->release(d_seg);
+  }
+  MQ_TRY(hipMemcpyAsync(m->d_desc, m->h_desc.data(), sizeof(QueryDesc) * m->n_slots_used,
+                        hipMemcpyHostToDevice, m->st));
+  m->drop_graph();
+  m->dirty = false;
+}
+
+void enqueue_step(impact_mq* m) {
+  if (m->n_slots_used == 0) return;
+  MQ_TRY(launch_mq_sweep_sb(m->d_desc, m->d_ctrl, m->wq_sb, m->ws_sb, m->n_sb, m->gap_sb,
+                            m->max_box_sb, m->max_row_sb, m->st));
+  MQ_TRY(launch_mq_sweep_block(m->d_desc, m->d_ctrl, m->wq_blk, m->ws_blk, m->n_blk, m->gap_blk,
+                               m->max_row_blk, m->st));
+  hipLaunchKernelGGL(k_mq_finish, dim3((unsigned)m->n_slots_used), dim3(256), 0, m->st,
+                     (const QueryDesc*)m->d_desc, m->d_ctrl, (const double*)m->gap_sb,
+                     (const double*)m->gap_blk, m->d_done);
+  MQ_TRY(hipGetLastError());
+}
+
+// Capture `steps` steps into a graph (replayed until the set of queries changes).
+void capture(impact_mq* m, int32_t steps) {
+  m->drop_graph();
+  hipGraph_t g = nullptr;
+  MQ_TRY(hipStreamBeginCapture(m->st, hipStreamCaptureModeThreadLocal));
+  for (int32_t k = 0; k < steps; ++k) enqueue_step(m);
+  MQ_TRY(hipStreamEndCapture(m->st, &g));
+  MQ_TRY(hipGraphInstantiate(&m->exec, g, nullptr, nullptr, 0));
+  (void)hipGraphDestroy(g);
+  m->graph_steps = steps;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* impact_mq_last_error(void) { return g_mq_err.c_str(); }
+
+int impact_mq_create(const impact_device* dev, int32_t max_queries, impact_mq** out) {
+  g_mq_err.clear();
+  if (!out) return mq_fail(IMPACT_E_INVAL, "out is null");
+  *out = nullptr;
+  if (max_queries < 1 || max_queries > (1 << 20))
+    return mq_fail(IMPACT_E_INVAL, "max_queries must be in [1, 2^20]");
+  impact_mq* m = new impact_mq();
+  if (dev) m->dev = *dev;
+  m->user_st = (hipStream_t)m->dev.stream;
+  m->cap = max_queries;
+  const int rc = mq_guarded([&]() -> int {
+    m->d_desc = (QueryDesc*)m->alloc(sizeof(QueryDesc) * (size_t)max_queries);
+    m->d_ctrl = (QueryCtrl*)m->alloc(sizeof(QueryCtrl) * (size_t)max_queries);
+    m->d_done = (int32_t*)m->alloc(sizeof(int32_t));
+    m->slots.resize(max_queries);
+    m->h_desc.resize(max_queries);
+    m->hip_used = true;
+    MQ_TRY(hipStreamCreateWithFlags(&m->st, hipStreamNonBlocking));
+    std::vector<QueryCtrl> c(max_queries);
+    for (auto& x : c) {
+      std::memset(&x, 0, sizeof(x));
+      x.phase = 4;
+    }
+    MQ_TRY(hipMemcpyAsync(m->d_ctrl, c.data(), sizeof(QueryCtrl) * c.size(),
+                          hipMemcpyHostToDevice, m->st));
+    const int32_t zero = 0;
+    MQ_TRY(hipMemcpyAsync(m->d_done, &zero, sizeof(zero), hipMemcpyHostToDevice, m->st));
+    MQ_TRY(hipStreamSynchronize(m->st));
+    return IMPACT_OK;
+  });
+  if (rc != IMPACT_OK) {
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return IMPACT_OK;
+}
+
+int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec, double eps,
+                     double* lo, double* hi, int32_t* policy, int32_t* id_out) {
+  g_mq_err.clear();
+  if (!m || !h || !spec || !id_out) return mq_fail(IMPACT_E_INVAL, "null argument");
+  if (!lo || !hi || !policy) return mq_fail(IMPACT_E_INVAL, "lo/hi/policy must be device buffers");
+  if (spec->kind < IMPACT_SAFETY || spec->kind > IMPACT_REACH_AVOID)
+    return mq_fail(IMPACT_E_INVAL, "unknown spec kind");
+  if (spec->n_target < 0 || spec->n_avoid < 0) return mq_fail(IMPACT_E_INVAL, "negative box count");
+  if ((spec->n_target > 0 && !spec->target_boxes) || (spec->n_avoid > 0 && !spec->avoid_boxes))
+    return mq_fail(IMPACT_E_INVAL, "box array is null");
+  if (spec->kind == IMPACT_SAFETY && spec->n_target != 0)
+    return mq_fail(IMPACT_E_INVAL, "safety takes no target boxes");
+  if (spec->kind == IMPACT_REACH && spec->n_avoid != 0)
+    return mq_fail(IMPACT_E_INVAL, "reachability takes no avoid boxes (use reach-avoid)");
+  if (spec->pessimistic != 1)
+    return mq_fail(IMPACT_E_UNSUPPORTED, "only the pessimistic policy is implemented");
+  if (spec->max_sweeps < 1) return mq_fail(IMPACT_E_INVAL, "max_sweeps must be >= 1");
+  if (!std::isfinite(eps) || !(eps > 0.0)) return mq_fail(IMPACT_E_INVAL, "eps must be > 0");
+  ImdpView v;
+  if (imdp_view(h, &v) != IMPACT_OK) return mq_fail(IMPACT_E_INVAL, "bad abstraction handle");
+  const int d = v.d;
+  for (int b = 0; b < spec->n_target; ++b)
+    for (int i = 0; i < d; ++i)
+      if (!(spec->target_boxes[b * 2 * d + i] <= spec->target_boxes[b * 2 * d + d + i]))
+        return mq_fail(IMPACT_E_INVAL, "target box with lo > hi");
+  for (int b = 0; b < spec->n_avoid; ++b)
+    for (int i = 0; i < d; ++i)
+      if (!(spec->avoid_boxes[b * 2 * d + i] <= spec->avoid_boxes[b * 2 * d + d + i]))
+        return mq_fail(IMPACT_E_INVAL, "avoid box with lo > hi");
+  if (v.nu > 256) return mq_fail(IMPACT_E_UNSUPPORTED, "more than 256 inputs per state");
+  // a free slot
+  int32_t k = -1;
+  for (int32_t i = 0; i < m->cap; ++i)
+    if (!m->slots[i].active) {
+      k = i;
+      break;
+    }
+  if (k < 0) return mq_fail(IMPACT_E_UNSUPPORTED, "no free query slot (poll finished queries)");
+  return mq_guarded([&]() -> int {
+    m->join_user();
+    MqQuery q;
+    const int64_t N = v.n_states;
+    const bool safety = spec->kind == IMPACT_SAFETY;
+    auto get = [&](size_t bytes) {
+      void* p = m->alloc(bytes);
+      q.bufs.push_back(p);
+      return p;
+    };
+    std::vector<void*> temps;
+    auto tget = [&](size_t bytes) {
+      void* p = m->alloc(bytes);
+      temps.push_back(p);
+      return p;
+    };
+    struct TempFree {
+      impact_mq* m;
+      std::vector<void*>* t;
+      ~TempFree() {
+        m->sync();
+        for (void* p : *t) m->release(p);
+      }
+    } tf{m, &temps};
+    int8_t* cls = (int8_t*)get((size_t)std::max<int64_t>(1, N));
+    int32_t* safe = (int32_t*)get(sizeof(int32_t) * (size_t)std::max<int64_t>(1, N));
+    double2* vb0 = (double2*)get(sizeof(double2) * (size_t)std::max<int64_t>(1, N));
+    double2* vb1 = (double2*)get(sizeof(double2) * (size_t)std::max<int64_t>(1, N));
+    int32_t* pi = (int32_t*)get(sizeof(int32_t) * (size_t)std::max<int64_t>(1, N));
+    double* tb = (double*)tget(sizeof(double) * (size_t)std::max(1, spec->n_target * 2 * d));
+    double* ab = (double*)tget(sizeof(double) * (size_t)std::max(1, spec->n_avoid * 2 * d));
+    int64_t* flag = (int64_t*)tget(sizeof(int64_t) * (size_t)std::max<int64_t>(1, N));
+    int64_t* pos = (int64_t*)tget(sizeof(int64_t) * (size_t)(N + 1));
+    const int64_t te = scan_tmp_elems(N);
+    int64_t* stmp = (int64_t*)tget(sizeof(int64_t) * (size_t)te);
+    if (spec->n_target > 0)
+      MQ_TRY(hipMemcpyAsync(tb, spec->target_boxes, sizeof(double) * spec->n_target * 2 * d,
+                            hipMemcpyHostToDevice, m->st));
+    if (spec->n_avoid > 0)
+      MQ_TRY(hipMemcpyAsync(ab, spec->avoid_boxes, sizeof(double) * spec->n_avoid * 2 * d,
+                            hipMemcpyHostToDevice, m->st));
+    MQ_TRY(launch_label(v.dp, N, tb, spec->n_target, ab, spec->n_avoid, cls, flag, m->st));
+    MQ_TRY(exclusive_scan_i64(flag, pos, N, stmp, te, m->st));
+    int64_t n_safe = 0;
+    MQ_TRY(hipMemcpyAsync(&n_safe, pos + N, sizeof(int64_t), hipMemcpyDeviceToHost, m->st));
+    MQ_TRY(hipStreamSynchronize(m->st));
+    MQ_TRY(launch_compact(cls, pos, N, safe, m->st));
+    MQ_TRY(launch_init_values(cls, N, safety, vb0, vb1, pi, m->st));
+    // outputs of non-SAFE cells now (SAFE cells are written when the passes close)
+    MQ_TRY(launch_finalize(cls, N, vb0, pi, 0, safety, lo, policy, m->st));
+    MQ_TRY(launch_finalize(cls, N, vb0, pi, 1, safety, hi, policy, m->st));
+    QueryDesc D;
+    std::memset(&D, 0, sizeof(D));
+    D.a = v.a;
+    D.a.pi = pi;
+    D.a.n_safe = n_safe;
+    D.a.out_val = safety ? 1.0 : 0.0;
+    D.a.reach = !safety;
+    D.vb0 = vb0;
+    D.vb1 = vb1;
+    D.lo = lo;
+    D.hi = hi;
+    D.pol = policy;
+    D.safety = safety;
+    D.box_class = v.max_row <= 512;
+    D.eps = eps;
+    D.cap = spec->max_sweeps;
+    QueryCtrl c;
+    std::memset(&c, 0, sizeof(c));
+    c.gap[0] = c.gap[1] = n_safe > 0 ? 1.0 : 0.0;
+    if (n_safe == 0) {
+      c.phase = 4;  // nothing to iterate: outputs are final
+      c.converged[0] = c.converged[1] = 1;
+    } else {
+      c.phase = 1.0 <= eps ? 1 : 0;
+      c.converged[0] = 1.0 <= eps;
+    }
+    MQ_TRY(hipMemcpyAsync(m->d_ctrl + k, &c, sizeof(c), hipMemcpyHostToDevice, m->st));
+    MQ_TRY(hipStreamSynchronize(m->st));
+    q.id = m->next_id++;
+    q.active = true;
+    q.finished = false;
+    q.n_safe = n_safe;
+    q.n_states = N;
+    q.box_class = D.box_class;
+    q.max_row = v.max_row;
+    q.max_box = v.max_box;
+    q.nu = v.nu;
+    q.keep = v.keep;
+    q.safe = safe;
+    m->slots[k] = q;
+    m->h_desc[k] = D;
+    m->n_slots_used = std::max(m->n_slots_used, k + 1);
+    m->dirty = true;
+    if (n_safe == 0) {
+      // report at the next poll without running anything
+      m->finished_info[q.id] = impact_iter_info{};
+      m->finished_info[q.id].n_safe = 0;
+      m->finished_info[q.id].converged[0] = m->finished_info[q.id].converged[1] = 1;
+      m->slots[k].finished = true;
+      m->unreported.push_back(q.id);
+    } else {
+      m->live_submitted += 1;
+    }
+    *id_out = q.id;
+    return IMPACT_OK;
+  });
+}
+
+int impact_mq_run(impact_mq* m, int32_t steps, int32_t* n_active) {
+  g_mq_err.clear();
+  if (!m || steps < 1) return mq_fail(IMPACT_E_INVAL, "bad argument");
+  return mq_guarded([&]() -> int {
+    m->join_user();
+    if (m->dirty) rebuild(m);
+    // d_done counts every query that reached the done phase since creation
+    int32_t done = 0;
+    MQ_TRY(hipMemcpyAsync(&done, m->d_done, sizeof(int32_t), hipMemcpyDeviceToHost, m->st));
+    MQ_TRY(hipStreamSynchronize(m->st));
+    int32_t left = steps;
+    const int32_t chunk_max = 16;
+    while (left > 0 && done < m->live_submitted && m->n_sb + m->n_blk > 0) {
+      const int32_t c = std::min(left, chunk_max);
+      if (!m->exec || m->graph_steps != c) capture(m, c);
+      MQ_TRY(hipGraphLaunch(m->exec, m->st));
+      MQ_TRY(hipMemcpyAsync(&done, m->d_done, sizeof(int32_t), hipMemcpyDeviceToHost, m->st));
+      MQ_TRY(hipStreamSynchronize(m->st));
+      m->steps_run += c;
+      left -= c;
+    }
+    if (n_active) *n_active = (int32_t)std::max<int64_t>(0, m->live_submitted - done);
+    return IMPACT_OK;
+  });
+}
+
+int impact_mq_poll(impact_mq* m, int32_t* ids, int32_t cap, int32_t* n_out) {
+  g_mq_err.clear();
+  if (!m || !n_out || cap < 0 || (cap > 0 && !ids)) return mq_fail(IMPACT_E_INVAL, "bad argument");
+  return mq_guarded([&]() -> int {
+    std::vector<QueryCtrl> c(std::max(1, m->n_slots_used));
+    if (m->n_slots_used > 0) {
+      MQ_TRY(hipMemcpyAsync(c.data(), m->d_ctrl, sizeof(QueryCtrl) * m->n_slots_used,
+                            hipMemcpyDeviceToHost, m->st));
+      MQ_TRY(hipStreamSynchronize(m->st));
+    }
+    for (int32_t k = 0; k < m->n_slots_used; ++k) {
+      MqQuery& q = m->slots[k];
+      if (!q.active || q.finished || c[k].phase != 4) continue;
+      impact_iter_info info{};
+      for (int p = 0; p < 2; ++p) {
+        info.sweeps[p] = c[k].sweeps[p];
+        info.gap[p] = c[k].gap[p];
+        info.converged[p] = c[k].converged[p];
+        info.updates[p] = c[k].sweeps[p] * q.n_safe * (p == 0 ? q.nu : 1);
+      }
+      info.n_safe = q.n_safe;
+      m->finished_info[q.id] = info;
+      q.finished = true;
+      m->unreported.push_back(q.id);
+    }
+    int32_t n = 0;
+    std::vector<int32_t> keep;
+    for (int32_t id : m->unreported) {
+      if (n < cap)
+        ids[n++] = id;
+      else
+        keep.push_back(id);
+    }
+    m->unreported = keep;
+    // reported queries give their buffers and slots back
+    for (int32_t k = 0; k < m->n_slots_used; ++k) {
+      MqQuery& q = m->slots[k];
+      if (!q.active || !q.finished) continue;
+      if (std::find(m->unreported.begin(), m->unreported.end(), q.id) != m->unreported.end())
+        continue;
+      for (void* p : q.bufs) m->release(p);
+      q.bufs.clear();
+      q.keep.reset();
+      q.active = false;
+      m->dirty = true;
+    }
+    while (m->n_slots_used > 0 && !m->slots[m->n_slots_used - 1].active) --m->n_slots_used;
+    *n_out = n;
+    return IMPACT_OK;
+  });
+}
+
+int impact_mq_query_info(const impact_mq* m, int32_t id, impact_iter_info* info) {
+  if (!m || !info) return mq_fail(IMPACT_E_INVAL, "null argument");
+  auto it = m->finished_info.find(id);
+  if (it == m->finished_info.end()) return mq_fail(IMPACT_E_INVAL, "query not finished / unknown");
+  *info = it->second;
+  return IMPACT_OK;
+}
+
+void impact_mq_free(impact_mq* m) { delete m; }
+
+}  // extern "C"

@@ -475,6 +475,59 @@ __global__ __launch_bounds__(64 * kSbWaves) void k_sweep_sb(SweepArgs a) {
   }
 }
 
+// Close a pass for one state of a query (phase 1: lo, policy and the reset of
+// the values for pass 2; phase 3: hi).
+__device__ __forceinline__ void mq_close_state(const QueryDesc& D, int64_t step, int phase,
+                                               int64_t s) {
+  const double2* vin = (step & 1) ? D.vb1 : D.vb0;
+  double2* vout = (step & 1) ? D.vb0 : D.vb1;
+  const double2 V = vin[s];
+  if (phase == 1) {
+    D.lo[s] = D.safety ? 1.0 - V.y : V.x;
+    D.pol[s] = D.a.pi[s];
+    vout[s] = make_double2(0.0, 1.0);
+  } else {
+    D.hi[s] = D.safety ? 1.0 - V.x : V.y;
+  }
+}
+
+// Multi-query state-box sweep: one wavefront per (query, SAFE state) item,
+// each query at its own phase and step.
+template <int ESB, int EROW>
+__global__ __launch_bounds__(64 * kSbWaves) void k_mq_sweep_sb(
+    const QueryDesc* __restrict__ desc, const QueryCtrl* __restrict__ ctrl,
+    const int32_t* __restrict__ wq, const int32_t* __restrict__ ws, int64_t n_items,
+    double* __restrict__ gap_item) {
+  __shared__ SbLds<64 * ESB> lds[kSbWaves];
+  const int lane = threadIdx.x & 63, wv = uniform_i32(threadIdx.x >> 6);
+  const int64_t item = (int64_t)blockIdx.x * kSbWaves + wv;
+  if (item >= n_items) return;
+  const int q = uniform_i32(wq[item]);
+  const int64_t s = uniform_i32(ws[item]);
+  const int phase = uniform_i32(ctrl[q].phase);
+  const int64_t step = uniform_i64(ctrl[q].step);
+  const QueryDesc& D = desc[q];
+  double g = 0.0;
+  if (phase == 0 || phase == 2) {
+    SweepArgs a = D.a;
+    a.vin = (step & 1) ? D.vb1 : D.vb0;
+    a.vout = (step & 1) ? D.vb0 : D.vb1;
+    a.reach = !D.safety;
+    if (phase == 0) {
+      a.pass = 0;
+      a.maximise = D.safety;
+      g = sb_sweep_state<ESB, EROW, 0>(a, s, lane, lds[wv]);
+    } else {
+      a.pass = 1;
+      a.maximise = !D.safety;
+      g = sb_sweep_state<ESB, EROW, 1>(a, s, lane, lds[wv]);
+    }
+  } else if ((phase == 1 || phase == 3) && lane == 0) {
+    mq_close_state(D, step, phase, s);
+  }
+  if (lane == 0) gap_item[item] = g;
+}
+
 static inline int lanes_elems(int64_t n) {
   return n <= 64 ? 1 : n <= 128 ? 2 : n <= 256 ? 4 : n <= 512 ? 8 : 0;
 }
@@ -502,6 +555,33 @@ static hipError_t launch_sb_pass(const SweepArgs& a, int64_t max_box, int32_t ma
       }
   }
 #undef SB
+  return hipGetLastError();
+}
+
+hipError_t launch_mq_sweep_sb(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
+                              const int32_t* ws, int64_t n_items, double* gap_item,
+                              int64_t max_box, int32_t max_row, hipStream_t st) {
+  if (n_items == 0) return hipSuccess;
+  const dim3 g((unsigned)((n_items + kSbWaves - 1) / kSbWaves)), bl(64 * kSbWaves);
+  const int er = lanes_elems(max_row);
+  if (er == 0) return hipErrorInvalidValue;
+  const int eb = lanes_elems(max_box);
+#define MQ(E1, E2) \
+  hipLaunchKernelGGL((k_mq_sweep_sb<E1, E2>), g, bl, 0, st, desc, ctrl, wq, ws, n_items, gap_item)
+  switch (eb) {
+    case 1: MQ(1, 0); break;
+    case 2: MQ(2, 0); break;
+    case 4: MQ(4, 0); break;
+    case 8: MQ(8, 0); break;
+    default:
+      switch (er) {
+        case 1: MQ(8, 1); break;
+        case 2: MQ(8, 2); break;
+        case 4: MQ(8, 4); break;
+        default: MQ(8, 8); break;
+      }
+  }
+#undef MQ
   return hipGetLastError();
 }
 

@@ -25,7 +25,8 @@ STORAGE = {"auto": 0, "bounds": 1, "factors": 2}
 EXPORTS = ["impact_build_imdp", "impact_interval_iterate", "impact_last_iter_info",
            "impact_imdp_get_info", "impact_imdp_export_rows", "impact_set_timing",
            "impact_imdp_free", "impact_last_error", "impact_version", "impact_set_sweep_mode",
-           "impact_build_imdp_batch"]
+           "impact_build_imdp_batch", "impact_mq_create", "impact_mq_submit", "impact_mq_run",
+           "impact_mq_poll", "impact_mq_query_info", "impact_mq_last_error", "impact_mq_free"]
 SWEEP_MODES = {"auto": 0, "per_row": 1, "state_box": 2}
 
 _pd = C.POINTER(C.c_double)
@@ -130,6 +131,22 @@ def lib():
         L.impact_last_error.argtypes = []
         L.impact_version.restype = C.c_char_p
         L.impact_version.argtypes = []
+        L.impact_mq_create.restype = C.c_int
+        L.impact_mq_create.argtypes = [C.POINTER(Device), C.c_int32, C.POINTER(C.c_void_p)]
+        L.impact_mq_submit.restype = C.c_int
+        L.impact_mq_submit.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(Spec), C.c_double, _pd,
+                                       _pd, _pi32, C.POINTER(C.c_int32)]
+        L.impact_mq_run.restype = C.c_int
+        L.impact_mq_run.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
+        L.impact_mq_poll.restype = C.c_int
+        L.impact_mq_poll.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.c_int32,
+                                     C.POINTER(C.c_int32)]
+        L.impact_mq_query_info.restype = C.c_int
+        L.impact_mq_query_info.argtypes = [C.c_void_p, C.c_int32, C.POINTER(IterInfo)]
+        L.impact_mq_last_error.restype = C.c_char_p
+        L.impact_mq_last_error.argtypes = []
+        L.impact_mq_free.restype = None
+        L.impact_mq_free.argtypes = [C.c_void_p]
         _lib = L
     return _lib
 
@@ -304,6 +321,97 @@ def build_imdp(system, k_sigma=None, storage="bounds", stream=None, timing=False
     if sweep_mode != "auto":
         imdp.set_sweep_mode(sweep_mode)
     return imdp
+
+
+def _mq_check(rc):
+    if rc < 0:
+        raise ImpactError(rc, lib().impact_mq_last_error().decode())
+    return rc
+
+
+def _spec_struct(spec, d, max_sweeps=None):
+    tb = _f64(np.asarray(spec.get("target") or np.zeros((0, 2, d))).reshape(-1, 2, d))
+    ab = _f64(np.asarray(spec.get("avoid") or np.zeros((0, 2, d))).reshape(-1, 2, d))
+    s = Spec(SPEC_KINDS[spec["kind"]], tb.shape[0], ab.shape[0],
+             _dptr(tb) if tb.size else None, _dptr(ab) if ab.size else None, 1,
+             int(max_sweeps if max_sweeps is not None else spec.get("max_sweeps", 100000)))
+    return s, (tb, ab)
+
+
+class Engine:
+    """Multi-query engine: interval-iteration queries in flight together."""
+
+    def __init__(self, max_queries=1024, stream=None):
+        self._dev = _TorchDevice(stream)
+        h = C.c_void_p()
+        _mq_check(lib().impact_mq_create(C.byref(self._dev.struct), int(max_queries), C.byref(h)))
+        self._h = h.value
+        self._out = {}    # id -> (lo, hi, policy) tensors
+        self._keep = {}   # id -> abstraction (python side)
+
+    def submit(self, imdp, spec, eps=None, max_sweeps=None, out=None):
+        torch = self._dev.torch
+        info = imdp.info()
+        d, n = info["dim"], info["n_states"]
+        s, keep = _spec_struct(spec, d, max_sweeps)
+        dev = f"cuda:{self._dev.device}"
+        if out is None:
+            out = (torch.empty(n, dtype=torch.float64, device=dev),
+                   torch.empty(n, dtype=torch.float64, device=dev),
+                   torch.empty(n, dtype=torch.int32, device=dev))
+        lo, hi, pol = out
+        qid = C.c_int32()
+        _mq_check(lib().impact_mq_submit(
+            self._h, imdp.handle, C.byref(s), float(eps if eps is not None else spec["eps"]),
+            _torch_ptr(lo, C.c_double), _torch_ptr(hi, C.c_double), _torch_ptr(pol, C.c_int32),
+            C.byref(qid)))
+        self._out[qid.value] = out
+        self._keep[qid.value] = imdp
+        return qid.value
+
+    def run(self, steps=16):
+        n = C.c_int32()
+        _mq_check(lib().impact_mq_run(self._h, int(steps), C.byref(n)))
+        return n.value
+
+    def poll(self, cap=4096):
+        ids = (C.c_int32 * cap)()
+        n = C.c_int32()
+        _mq_check(lib().impact_mq_poll(self._h, ids, cap, C.byref(n)))
+        done = []
+        for k in range(n.value):
+            qid = ids[k]
+            i = IterInfo()
+            _mq_check(lib().impact_mq_query_info(self._h, qid, C.byref(i)))
+            lo, hi, pol = self._out.pop(qid)
+            self._keep.pop(qid, None)
+            done.append(dict(id=qid, lo=lo, hi=hi, policy=pol,
+                             status=0 if (i.converged[0] and i.converged[1]) else 1,
+                             info=dict(sweeps=tuple(i.sweeps), gap=tuple(i.gap),
+                                       converged=tuple(i.converged), n_safe=i.n_safe,
+                                       updates=tuple(i.updates))))
+        return done
+
+    def run_all(self, chunk=64):
+        results = {}
+        while True:
+            active = self.run(chunk)
+            for r in self.poll():
+                results[r["id"]] = r
+            if active == 0 and not self._out:
+                break
+        return results
+
+    def free(self):
+        if self._h:
+            lib().impact_mq_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def build_imdp_batch(systems, storage="bounds", stream=None, sweep_mode="auto"):

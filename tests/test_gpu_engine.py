@@ -1,0 +1,161 @@
+"""GPU tests of the multi-query engine (batched and served forms).
+
+A query run by the engine must equal the same query run alone by
+impact_interval_iterate with the same sweep kernels (bitwise), must not depend
+on which other queries share its launches (bitwise), and must match the CPU
+oracle at the parity tolerances.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_03555_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def I():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_03555_amd import impact
+    impact.lib()
+    return impact
+
+
+def _np(r):
+    return r["lo"].cpu().numpy(), r["hi"].cpu().numpy(), r["policy"].cpu().numpy()
+
+
+def _same(a, b, label):
+    for x, y, k in zip(_np(a), _np(b), ("lo", "hi", "policy")):
+        assert np.array_equal(x, y), f"{label}: {k} differs (max {np.abs(x - y).max()})"
+    assert tuple(a["info"]["sweeps"]) == tuple(b["info"]["sweeps"]), label
+
+
+def _affine2():
+    return W.tiny_affine(d=2, n=9, seed=2)
+
+
+def _long_rows():
+    # dense 2D rows of 26 x 26 + 1 = 677 entries: the workgroup kernel class
+    return dict(kind="affine", A=np.eye(2) * 0.8, B=np.eye(2) * 0.5, c=np.zeros(2),
+                lb=[-2.0, -2.0], ub=[2.0, 2.0], n=[26, 26], inputs=[[0.5, 0.0], [0.0, 0.5]],
+                sigma=[0.3, 0.3], k_sigma=0.0)
+
+
+CASES = [
+    ("affine2_ra", _affine2, dict(kind="reach_avoid", target=[[[0.5, 0.5], [1.5, 1.5]]],
+                                  avoid=[[[-1.5, -1.5], [-0.5, -0.5]]], eps=1e-8,
+                                  max_sweeps=400)),
+    ("affine3_reach", lambda: W.tiny_affine(d=3, n=6, seed=3),
+     dict(kind="reach", target=[[[0.0, 0.0, 0.0], [1.3, 1.3, 1.3]]], avoid=[], eps=1e-8,
+          max_sweeps=2000)),
+    ("affine2_safety", lambda: W.tiny_affine(d=2, n=7, seed=8, k_sigma=0.0),
+     dict(kind="safety", target=[], avoid=[[[-0.5, -0.5], [0.5, 0.5]]], eps=1e-8,
+          max_sweeps=300)),
+    ("unicycle", lambda: dict(W.unicycle3d(n=(10, 10, 6))[0], sigma=[0.3, 0.3, 0.2]),
+     dict(kind="reach_avoid", target=[[[2.0, 2.0, -4.0], [5.0, 5.0, 4.0]]],
+          avoid=[[[-1.0, -1.0, -4.0], [1.0, 1.0, 4.0]]], eps=1e-8, max_sweeps=3000)),
+    ("long_rows", _long_rows, dict(kind="reach_avoid", target=[[[1.0, 1.0], [2.0, 2.0]]],
+                                   avoid=[[[-0.5, -0.5], [0.5, 0.5]]], eps=1e-8,
+                                   max_sweeps=60)),
+]
+
+
+@pytest.mark.parametrize("name,make,spec", CASES, ids=[c[0] for c in CASES])
+def test_engine_query_equals_plain_iterate(I, name, make, spec):
+    system = make()
+    imdp = I.build_imdp(system, sweep_mode="state_box")
+    plain = imdp.iterate(spec)
+    eng = I.Engine(max_queries=4)
+    qid = eng.submit(imdp, spec)
+    res = eng.run_all()
+    assert set(res) == {qid}
+    _same(res[qid], plain, name)
+    assert res[qid]["status"] == plain["status"]
+
+
+def test_engine_alone_equals_in_the_mix(I):
+    systems = {name: make() for name, make, _ in CASES}
+    imdps = I.build_imdp_batch([systems[n] for n, _, _ in CASES[:4]])
+    imdps = dict(zip([n for n, _, _ in CASES[:4]], imdps))
+    imdps["long_rows"] = I.build_imdp(systems["long_rows"])
+    alone = {}
+    for name, _, spec in CASES:
+        eng = I.Engine(max_queries=2)
+        q = eng.submit(imdps[name], spec)
+        alone[name] = eng.run_all()[q]
+    # everything at once, plus extra queries on the same abstractions
+    eng = I.Engine(max_queries=16)
+    ids = {}
+    for name, _, spec in CASES:
+        ids[eng.submit(imdps[name], spec)] = name
+    extra = dict(kind="reach", target=[[[-1.0, -1.0], [0.0, 0.0]]], avoid=[], eps=1e-6,
+                 max_sweeps=500)
+    eng.submit(imdps["affine2_ra"], extra)
+    eng.submit(imdps["long_rows"], dict(extra, max_sweeps=20))
+    res = eng.run_all()
+    assert len(res) == len(CASES) + 2
+    for qid, name in ids.items():
+        _same(res[qid], alone[name], f"{name} in the mix")
+
+
+def test_engine_matches_oracle_on_batched_instances(I):
+    import torch
+    rng = np.random.default_rng(7)
+    insts = []
+    while len(insts) < 6:
+        system, spec = W.random_linear(rng, d=2)
+        if np.prod(system["n"]) <= 900:
+            insts.append((system, spec))
+    views = I.build_imdp_batch([s for s, _ in insts], storage="factors")
+    eng = I.Engine(max_queries=8)
+    ids = [eng.submit(v, dict(spec, max_sweeps=400)) for v, (_, spec) in zip(views, insts)]
+    res = eng.run_all()
+    for qid, (system, spec) in zip(ids, insts):
+        ref = oracle.solve(system, system["k_sigma"], spec["kind"], spec["target"], spec["avoid"],
+                           spec["eps"], 400, want_q0=True)
+        lo, hi, pol = _np(res[qid])
+        assert tuple(res[qid]["info"]["sweeps"]) == tuple(ref["sweeps"])
+        assert np.abs(lo - ref["lo"]).max() <= 1e-9 and np.abs(hi - ref["hi"]).max() <= 1e-9
+        safe = ref["cls"] == 0
+        diff = np.where(safe & (pol != ref["policy"]))[0]
+        for s in diff:
+            q = ref["q0"][s]
+            assert q[pol[s]] >= q.max() - 1e-12
+    del torch
+
+
+def test_engine_reuses_slots_and_handles_degenerate_queries(I):
+    system = _affine2()
+    imdp = I.build_imdp(system, sweep_mode="state_box")
+    spec = CASES[0][2]
+    ref = imdp.iterate(spec)
+    eng = I.Engine(max_queries=2)
+    done = {}
+    pending = 0
+    for k in range(5):  # more queries than slots: poll frees them
+        while pending >= 2:
+            eng.run(8)
+            for r in eng.poll():
+                done[r["id"]] = r
+                pending -= 1
+        eng.submit(imdp, spec)
+        pending += 1
+    done.update(eng.run_all())
+    assert len(done) == 5
+    for r in done.values():
+        _same(r, ref, "reused slot")
+    # every cell a target: nothing to iterate
+    q = eng.submit(imdp, dict(kind="reach", target=[[[-2.0, -2.0], [2.0, 2.0]]], avoid=[],
+                              eps=1e-8, max_sweeps=10))
+    r = eng.run_all()[q]
+    assert r["info"]["sweeps"] == (0, 0) and bool((r["lo"] == 1).all())
+    assert bool((r["policy"] == -1).all())
+    # eps >= 1: no sweeps, outputs from the initial brackets
+    q = eng.submit(imdp, dict(spec, eps=2.0))
+    r = eng.run_all()[q]
+    plain = imdp.iterate(dict(spec, eps=2.0))
+    _same(r, plain, "eps >= 1")
