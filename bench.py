@@ -11,7 +11,16 @@ Prints one JSON line.  ``value`` is (state, input)-row LP updates per second
 over the whole timed step (build included); the line also carries the bound
 construction rate, the roofline of the dominant kernel (the policy-pass sweep,
 timed with HIP events on the library's stream) and the CPU oracle timed on a
-bounded sample of the same workload.
+bounded sample of the same workload.  The storage mode and the per-pass entry
+order come from the autotuner unless given.
+
+``--forms`` adds the two systems forms to the same line, each against its
+plain counterpart on the same GPU at the same eps:
+  batched: seeded random 2D/3D linear instances built with one batch build
+           and iterated together by the graph-captured engine, against a
+           loop of plain build + iterate calls, one instance at a time;
+  served : a Poisson request trace over a 64-system pool served by the
+           continuous-batching loop, against serial plain solves.
 """
 import argparse
 import json
@@ -33,9 +42,17 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="unicycle3d",
                     choices=["unicycle3d", "robot2d", "room5d"])
-    ap.add_argument("--storage", default="bounds", choices=["bounds", "factors"])
-    ap.add_argument("--sweep-mode", default="auto", choices=["auto", "per_row", "state_box"])
+    ap.add_argument("--storage", default="tuned", choices=["tuned", "bounds", "factors"])
+    ap.add_argument("--sweep-mode", default="tuned",
+                    choices=["tuned", "auto", "per_row", "state_box"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="", help="comma list of: batched, served")
+    ap.add_argument("--instances", type=int, default=384)
+    ap.add_argument("--batch-max-sweeps", type=int, default=1000)
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-max-sweeps", type=int, default=1000)
+    ap.add_argument("--tune-cache", default=None, help="JSON file for autotuner results")
     return ap.parse_args()
 
 
@@ -54,17 +71,21 @@ def workload(name):
 def algorithmic_bytes(imdp, policy, n_states, d):
     """HBM bytes one policy-pass sweep must move (see the roofline notes).
 
-    Per (SAFE state, input) row: 16 B per window cell (lo, hi) + 32 B OUT/TAIL
-    bounds + 8 B row offset + 8*d B window origin and widths.  Per SAFE state:
-    16 B (V0, V1) written + 4 B policy written + 4 B SAFE-list entry read.
-    Plus one read of the (V0, V1) vector, 16 B per cell; the per-entry value
-    gathers re-read it from cache and are not counted.
+    Per (SAFE state, input) row: the row's bounds -- 16 B per window cell
+    (lo, hi) when stored, or 16 B per per-dimension factor (sum of the window
+    widths) when recomputed -- + 32 B OUT/TAIL bounds + 8 B row offset + 8*d B
+    window origin and widths.  Per SAFE state: 16 B (V0, V1) written + 4 B
+    policy written + 4 B SAFE-list entry read.  Plus one read of the (V0, V1)
+    vector, 16 B per cell; the per-entry value gathers re-read it from cache
+    and are not counted.
     """
-    import numpy as np
     info = imdp.info()
     nu = info["n_inputs"]
-    counts = imdp.export_rows(0, info["n_rows"], entries=False)["counts"].reshape(-1, nu)
+    ex = imdp.export_rows(0, info["n_rows"], entries=False)
     safe = policy >= 0
+    counts = ex["counts"].reshape(-1, nu)
+    if info["storage"] == 2:
+        counts = ex["win"][:, d:].sum(axis=1).reshape(-1, nu)
     cells = int(counts[safe].sum())
     rows = int(safe.sum()) * nu
     per_pass1 = 16 * cells + rows * (32 + 8 + 8 * d) + int(safe.sum()) * 24 + 16 * n_states
@@ -98,24 +119,136 @@ def cpu_baseline(system, spec, budget_s=25.0):
     }
 
 
+def run_batched(args, tuner):
+    """Batched form vs a per-instance plain loop, same instances, eps and sweep cap."""
+    import numpy as np
+    import torch
+    from paper_2401_03555_amd import impact, workloads as W
+    insts = W.batched(count=args.instances)
+    systems = [s for s, _ in insts]
+    specs = [dict(spec, max_sweeps=args.batch_max_sweeps) for _, spec in insts]
+    # schedule choice (untimed): storage of the batch and engine graph chunk
+    probe = impact.build_imdp_batch(systems, storage="factors")
+    infos = [v.info() for v in probe]
+    for v in probe:
+        v.free()
+    choice = tuner.choose_batch(systems, infos=infos)
+    storage, chunk = choice["storage"], choice["chunk"]
+    print(f"# batched: {len(systems)} instances, storage {storage}, chunk {chunk}",
+          file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    views = impact.build_imdp_batch(systems, storage=storage)
+    eng = impact.Engine(max_queries=len(views))
+    ids = [eng.submit(v, sp) for v, sp in zip(views, specs)]
+    res = eng.run_all(chunk=chunk)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    eng.free()
+    print(f"# batched done in {t_batched:.2f} s", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    worst = 0.0
+    plain_updates = 0
+    for k, (system, sp) in enumerate(zip(systems, specs)):
+        im = impact.build_imdp(system, storage=storage)
+        r = im.iterate(sp)
+        plain_updates += sum(r["info"]["updates"])
+        b = res[ids[k]]
+        worst = max(worst, float((r["lo"] - b["lo"]).abs().max()),
+                    float((r["hi"] - b["hi"]).abs().max()))
+        im.free()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    for v in views:
+        v.free()
+    updates = sum(sum(r["info"]["updates"]) for r in res.values())
+    sweeps = np.array([r["info"]["sweeps"] for r in res.values()])
+    return {
+        "workload": (f"{len(systems)} seeded random 2D/3D linear instances, reach-avoid, "
+                     f"eps 1e-8, at most {args.batch_max_sweeps} sweeps per pass"),
+        "instances": len(systems),
+        "n_states": int(sum(i["n_states"] for i in infos)),
+        "n_rows": int(sum(i["n_rows"] for i in infos)),
+        "n_entries": int(sum(i["n_entries"] for i in infos)),
+        "storage": storage, "chunk": chunk, "tuner": choice,
+        "batched_s": t_batched, "plain_loop_s": t_plain,
+        "speedup_vs_plain_loop": t_plain / t_batched,
+        "batched_updates_per_s": updates / t_batched,
+        "plain_updates_per_s": plain_updates / t_plain,
+        "instances_per_s": len(systems) / t_batched,
+        "converged": int(sum(r["status"] == 0 for r in res.values())),
+        "sweeps_p50": [float(x) for x in np.percentile(sweeps, 50, axis=0)],
+        "sweeps_max": [int(x) for x in sweeps.max(axis=0)],
+        "max_abs_diff_vs_plain": worst,
+    }
+
+
+def run_served(args):
+    """Served form vs serial plain solves over the same request trace."""
+    import torch
+    from paper_2401_03555_amd import serve, workloads as W
+    pool = W.served_pool()
+    trace = W.served_trace(pool, rate=args.serve_rate, duration=args.serve_seconds,
+                           max_sweeps=args.serve_max_sweeps)
+    budget = int(torch.cuda.mem_get_info()[0] * 0.5)
+    # both legs start from an empty cache of the same budget
+    cache = serve.AbstractionCache(pool, budget, storage="factors")
+    srv = serve.Server(cache, max_active=64, steps=8)
+    done, st = srv.run(trace)
+    srv.free()
+    served = serve.latency_stats(done, st["makespan"])
+    served.update(peak_active=st["peak_active"], cache=cache.stats())
+    cache.clear()
+    print(f"# served: {served}", file=sys.stderr, flush=True)
+    cache = serve.AbstractionCache(pool, budget, storage="factors")
+    sdone, sst = serve.serve_serial(cache, trace)
+    serial = serve.latency_stats(sdone, sst["makespan"])
+    serial.update(cache=cache.stats())
+    cache.clear()
+    return {
+        "workload": (f"64-system pool (robot2d, unicycle3d, room5d variants, random linear), "
+                     f"Poisson {args.serve_rate:g} req/s for {args.serve_seconds:g} s, "
+                     f"safety/reach/reach-avoid, eps 1e-6/1e-8, at most "
+                     f"{args.serve_max_sweeps} sweeps per pass"),
+        "requests": len(trace),
+        "served": served,
+        "serial_plain": serial,
+        "p99_speedup": serial["p99_ms"] / served["p99_ms"],
+        "qps_ratio": served["qps"] / serial["qps"],
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
               "is a design note, not built", file=sys.stderr)
         return 2
-    import numpy as np
     import torch
     from paper_2401_03555_amd import impact
+    from paper_2401_03555_amd.autotune import Autotuner
 
     assert torch.cuda.is_available(), "no GPU visible"
     impact.lib()
+    tuner = Autotuner(path=args.tune_cache)
     system, spec, desc = workload(args.workload)
     max_sweeps = spec["max_sweeps"]
 
+    # schedule choice (untimed)
+    storage, modes, choice = args.storage, (args.sweep_mode, args.sweep_mode), None
+    if "tuned" in (args.storage, args.sweep_mode):
+        choice = tuner.choose(system)
+        if args.storage == "tuned":
+            storage = choice["storage"]
+        if args.sweep_mode == "tuned":
+            modes = (choice["policy_pass"], choice["fixed_pass"])
+    print(f"# plain: storage {storage}, sweep modes {modes}", file=sys.stderr, flush=True)
+
     def step(timing=False):
-        imdp = impact.build_imdp(system, storage=args.storage, timing=timing,
-                                 sweep_mode=args.sweep_mode)
+        imdp = impact.build_imdp(system, storage=storage, timing=timing)
+        imdp.set_sweep_modes(*modes)
         r = imdp.iterate(spec, max_sweeps=max_sweeps)
         return imdp, r
 
@@ -124,10 +257,8 @@ def main():
         imdp.free()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = []
     for _ in range(args.steps):
         imdp, r = step()
-        infos.append((imdp.info(), r["info"], r["status"]))
         imdp.free()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -144,6 +275,7 @@ def main():
     achieved = bytes_sweep * sweeps0 / max(1, launches0) / (avg_launch_ms * 1e-3) / 1e9
     updates = sum(iinfo["updates"])
     value = updates / (ms_per_step * 1e-3)
+    box = modes[0] in ("state_box", "auto") and binfo["max_row"] <= 512
 
     line = {
         "metric": METRIC,
@@ -160,8 +292,9 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": desc,
-            "storage": args.storage,
-            "sweep_mode": args.sweep_mode,
+            "storage": storage,
+            "sweep_modes": list(modes),
+            "tuner": choice,
             "max_row": binfo["max_row"],
             "max_box": binfo["max_box"],
             "n_states": binfo["n_states"],
@@ -180,8 +313,8 @@ def main():
             "served_p99_ms": None,
         },
         "roofline": {
-            "kernel": ("k_sweep_sb" if (args.sweep_mode != "per_row" and binfo["max_row"] <= 512)
-                       else "k_sweep") + " policy pass (all inputs per SAFE state)",
+            "kernel": ("k_sweep_sb" if box else "k_sweep") +
+                      " policy pass (all inputs per SAFE state)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -195,6 +328,14 @@ def main():
         },
     }
     imdp.free()
+    forms = [f for f in args.forms.split(",") if f]
+    if forms:
+        line["forms"] = {}
+    if "batched" in forms:
+        line["forms"]["batched"] = run_batched(args, tuner)
+    if "served" in forms:
+        line["forms"]["served"] = run_served(args)
+        line["components"]["served_p99_ms"] = line["forms"]["served"]["served"]["p99_ms"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(system, dict(spec))
     print(json.dumps(line), flush=True)

@@ -249,6 +249,13 @@ enum { IMPACT_SWEEP_AUTO = 0, IMPACT_SWEEP_PER_ROW = 1, IMPACT_SWEEP_STATE_BOX =
 
 int impact_set_sweep_mode(impact_imdp *imdp, int32_t mode);
 
+/* The same choice made per pass: policy_pass for pass 1 (optimisation over
+ * inputs), fixed_pass for pass 2 (policy fixed).  AUTO keeps the library's
+ * default for that pass.  Results agree within rounding whatever the modes;
+ * the autotuner picks them by measured sweep time.
+ * Errors: E_INVAL on a null handle or an unknown mode. */
+int impact_set_sweep_modes(impact_imdp *imdp, int32_t policy_pass, int32_t fixed_pass);
+
 /* Enable (1) / disable (0) per-kernel HIP-event timing on this handle. */
 int impact_set_timing(impact_imdp *imdp, int32_t enable);
 

@@ -106,7 +106,7 @@ struct impact_imdp {
   int64_t n_states = 0, n_rows = 0, n_cells = 0;
   int32_t d = 0, nu = 0, windowed = 0, storage = IMPACT_STORE_BOUNDS, max_row = 0, fs = 0;
   int64_t max_box = 0;  // largest bounding box of one state's row windows (cells)
-  int32_t sweep_mode = IMPACT_SWEEP_AUTO;
+  int32_t sweep_mode[2] = {IMPACT_SWEEP_AUTO, IMPACT_SWEEP_AUTO};  // per pass
   impact_iter_info last{};
   bool timing = false;
   double build_ms = 0.0;
@@ -470,12 +470,18 @@ int impact_set_timing(impact_imdp* h, int32_t enable) {
   return IMPACT_OK;
 }
 
-int impact_set_sweep_mode(impact_imdp* h, int32_t mode) {
+int impact_set_sweep_modes(impact_imdp* h, int32_t policy_pass, int32_t fixed_pass) {
   if (!h) return fail(IMPACT_E_INVAL, "null handle");
-  if (mode < IMPACT_SWEEP_AUTO || mode > IMPACT_SWEEP_STATE_BOX)
-    return fail(IMPACT_E_INVAL, "unknown sweep mode");
-  h->sweep_mode = mode;
+  for (int32_t mode : {policy_pass, fixed_pass})
+    if (mode < IMPACT_SWEEP_AUTO || mode > IMPACT_SWEEP_STATE_BOX)
+      return fail(IMPACT_E_INVAL, "unknown sweep mode");
+  h->sweep_mode[0] = policy_pass;
+  h->sweep_mode[1] = fixed_pass;
   return IMPACT_OK;
+}
+
+int impact_set_sweep_mode(impact_imdp* h, int32_t mode) {
+  return impact_set_sweep_modes(h, mode, mode);
 }
 
 int impact_imdp_get_info(const impact_imdp* h, impact_imdp_info* info) {
@@ -596,9 +602,10 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       // policy pass: one sort per state over its rows' window box when every
       // row fits a wavefront; the fixed-input pass has one row per state and
       // sorts per row unless the state-box mode is forced
+      const int32_t mode = h->sweep_mode[pass];
       const bool use_box = h->max_row <= 512 &&
-                           (pass == 0 ? h->sweep_mode != IMPACT_SWEEP_PER_ROW
-                                      : h->sweep_mode == IMPACT_SWEEP_STATE_BOX);
+                           (mode == IMPACT_SWEEP_STATE_BOX ||
+                            (mode == IMPACT_SWEEP_AUTO && pass == 0));
       SweepArgs a{};
       a.row_off = h->row_off;
       a.win = h->win;

@@ -514,7 +514,7 @@ int impact_mq_run(impact_mq* m, int32_t steps, int32_t* n_active) {
     MQ_TRY(hipMemcpyAsync(&done, m->d_done, sizeof(int32_t), hipMemcpyDeviceToHost, m->st));
     MQ_TRY(hipStreamSynchronize(m->st));
     int32_t left = steps;
-    const int32_t chunk_max = 16;
+    const int32_t chunk_max = 64;
     while (left > 0 && done < m->live_submitted && m->n_sb + m->n_blk > 0) {
       const int32_t c = std::min(left, chunk_max);
       if (!m->exec || m->graph_steps != c) capture(m, c);

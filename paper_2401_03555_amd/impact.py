@@ -25,6 +25,7 @@ STORAGE = {"auto": 0, "bounds": 1, "factors": 2}
 EXPORTS = ["impact_build_imdp", "impact_interval_iterate", "impact_last_iter_info",
            "impact_imdp_get_info", "impact_imdp_export_rows", "impact_set_timing",
            "impact_imdp_free", "impact_last_error", "impact_version", "impact_set_sweep_mode",
+           "impact_set_sweep_modes",
            "impact_build_imdp_batch", "impact_mq_create", "impact_mq_submit", "impact_mq_run",
            "impact_mq_poll", "impact_mq_query_info", "impact_mq_last_error", "impact_mq_free"]
 SWEEP_MODES = {"auto": 0, "per_row": 1, "state_box": 2}
@@ -123,6 +124,8 @@ def lib():
                                               _pi64, _pd]
         L.impact_set_sweep_mode.restype = C.c_int
         L.impact_set_sweep_mode.argtypes = [C.c_void_p, C.c_int32]
+        L.impact_set_sweep_modes.restype = C.c_int
+        L.impact_set_sweep_modes.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
         L.impact_set_timing.restype = C.c_int
         L.impact_set_timing.argtypes = [C.c_void_p, C.c_int32]
         L.impact_imdp_free.restype = None
@@ -236,6 +239,10 @@ class Imdp:
 
     def set_sweep_mode(self, mode):
         _check(lib().impact_set_sweep_mode(self._h, SWEEP_MODES[mode]))
+
+    def set_sweep_modes(self, policy_pass, fixed_pass):
+        _check(lib().impact_set_sweep_modes(self._h, SWEEP_MODES[policy_pass],
+                                            SWEEP_MODES[fixed_pass]))
 
     def set_timing(self, enable=True):
         _check(lib().impact_set_timing(self._h, int(bool(enable))))

@@ -24,7 +24,7 @@ def _grid_inputs(*axes):
     return np.array(list(itertools.product(*axes)), dtype=np.float64)
 
 
-def robot2d():
+def robot2d(sigma=0.25):
     """2D robot, reach-avoid, dense rows (stand-in for the paper's 2D robot study).
 
     x+ = x + 0.5 u + w on [-10,10]^2, 20x20 cells of width 1, u in {-1,0,1}^2,
@@ -33,7 +33,7 @@ def robot2d():
     system = dict(kind="affine", A=np.eye(2), B=0.5 * np.eye(2), c=np.zeros(2),
                   lb=[-10.0, -10.0], ub=[10.0, 10.0], n=[20, 20],
                   inputs=_grid_inputs([-1.0, 0.0, 1.0], [-1.0, 0.0, 1.0]),
-                  sigma=[0.25, 0.25], k_sigma=0.0)
+                  sigma=[sigma, sigma], k_sigma=0.0)
     spec = dict(kind="reach_avoid", target=[[[5.0, 5.0], [8.0, 8.0]]],
                 avoid=[[[-2.0, -2.0], [2.0, 2.0]]], eps=1e-8, max_sweeps=100000)
     return system, spec
@@ -135,6 +135,62 @@ def tiny_affine(d=2, n=6, seed=1, k_sigma=6.0, n_inputs=3):
                   inputs=np.linspace(-1.0, 1.0, n_inputs).reshape(-1, 1),
                   sigma=[0.3 * 4.0 / n] * d, k_sigma=k_sigma)
     return system
+
+
+def served_pool(seed=SEED + 1):
+    """The 64 systems a served trace draws from, keyed "<generator>/<k>".
+
+    Every case-study generator contributes its own configuration and seeded
+    variants of it (noise level, grid resolution), and the batched generator
+    the rest: robot2d with sigma U(0.15, 0.5) (4), unicycle3d at 50x50x24 and
+    three coarser grids (4), room5d at 5-8 cells per dimension (4) and 52
+    random linear 2D/3D systems.
+    """
+    rng = np.random.default_rng(seed)
+    pool = {"robot2d/0": robot2d()[0]}
+    for k in range(1, 4):
+        pool[f"robot2d/{k}"] = robot2d(sigma=float(rng.uniform(0.15, 0.5)))[0]
+    pool["unicycle3d/0"] = unicycle3d()[0]
+    for k in range(1, 4):
+        n = (int(rng.integers(16, 41)), int(rng.integers(16, 41)), int(rng.integers(8, 17)))
+        pool[f"unicycle3d/{k}"] = unicycle3d(n=n)[0]
+    for k, cells in enumerate((5, 6, 7, 8)):
+        pool[f"room5d/{k}"] = room5d(cells=cells)[0]
+    for k in range(52):
+        pool[f"linear/{k}"] = random_linear(rng)[0]
+    return pool
+
+
+def _aligned_box(rng, system):
+    lb, ub, n = (np.asarray(system[k], dtype=np.float64) for k in ("lb", "ub", "n"))
+    w = (ub - lb) / n
+    span = [int(rng.integers(1, max(2, int(ni) // 4) + 1)) for ni in n]
+    start = [int(rng.integers(0, int(ni) - sp + 1)) for ni, sp in zip(n, span)]
+    return [[float(lb[i] + start[i] * w[i]) for i in range(len(n))],
+            [float(lb[i] + (start[i] + span[i]) * w[i]) for i in range(len(n))]]
+
+
+def served_trace(pool, rate=200.0, duration=2.0, seed=SEED + 2, max_sweeps=2000):
+    """Poisson arrivals at ``rate`` per second over ``duration`` seconds.
+
+    Each request names a pool system (uniformly), a specification kind in
+    {safety, reach, reach_avoid} (uniformly), grid-aligned random boxes (up to
+    a quarter of the cells per dimension) and eps in {1e-6, 1e-8}.
+    """
+    rng = np.random.default_rng(seed)
+    keys = sorted(pool)
+    t, trace = 0.0, []
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t >= duration:
+            return trace
+        key = keys[int(rng.integers(len(keys)))]
+        kind = ("safety", "reach", "reach_avoid")[int(rng.integers(3))]
+        target = [_aligned_box(rng, pool[key])] if kind != "safety" else []
+        avoid = [_aligned_box(rng, pool[key])] if kind != "reach" else []
+        eps = (1e-6, 1e-8)[int(rng.integers(2))]
+        trace.append(dict(t=t, key=key, spec=dict(kind=kind, target=target, avoid=avoid,
+                                                   eps=eps, max_sweeps=max_sweeps)))
 
 
 CONFIGS = {

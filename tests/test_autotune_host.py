@@ -1,0 +1,56 @@
+"""Host logic of the autotuner: shape keys, result cache, sampling (no GPU)."""
+import json
+
+import numpy as np
+
+from paper_2401_03555_amd import autotune as A, workloads as W
+
+
+def _info(**kw):
+    base = dict(dim=3, n_inputs=20, n_rows=1_000_000, max_row=300, n_entries=60_000_000,
+                windowed=1, n_states=50_000)
+    base.update(kw)
+    return base
+
+
+def test_keys_bucket_by_powers_of_two(monkeypatch):
+    monkeypatch.setattr(A, "_device", lambda: "dev")
+    k = A.imdp_key(_info())
+    assert k == A.imdp_key(_info(n_rows=1_100_000, max_row=290))
+    assert k != A.imdp_key(_info(max_row=600))
+    assert k != A.imdp_key(_info(dim=2))
+    assert k.startswith("dev/")
+    t = A.Autotuner()
+    b = t.batch_key([_info(), _info(dim=2, max_row=50)])
+    assert "d2-3" in b and b.startswith("dev/batch/")
+
+
+def test_cached_choice_skips_measurement(monkeypatch, tmp_path):
+    monkeypatch.setattr(A, "_device", lambda: "dev")
+
+    class Probe:
+        def info(self):
+            return _info()
+
+        def free(self):
+            pass
+
+    monkeypatch.setattr(A.impact, "build_imdp", lambda system, storage="bounds": Probe())
+    path = tmp_path / "tune.json"
+    key = A.imdp_key(_info())
+    path.write_text(json.dumps({key: dict(storage="factors", policy_pass="state_box",
+                                          fixed_pass="per_row", ms_per_sweep_pair=1.0)}))
+    t = A.Autotuner(path=str(path))
+    c = t.choose({"n": [2, 2, 2]})
+    assert c["cached"] and c["storage"] == "factors" and c["fixed_pass"] == "per_row"
+
+
+def test_sample_takes_largest_and_seeded_rest():
+    systems = [s for s, _ in W.batched(count=40, seed=3)]
+    t = A.Autotuner()
+    sub = t._sample(systems, 10)
+    rows = [np.prod(s["n"]) * len(s["inputs"]) for s in systems]
+    top = sorted(rows, reverse=True)[:5]
+    got = [np.prod(s["n"]) * len(s["inputs"]) for s in sub]
+    assert len(sub) == 10 and got[:5] == top
+    assert [id(s) for s in t._sample(systems, 10)] == [id(s) for s in sub]

@@ -1,0 +1,103 @@
+"""GPU tests of the served form: continuous batching must not change results.
+
+A trace of overlapping requests over a small pool is served by the
+continuous-batching loop; every result must equal, bitwise, the same query run
+alone in the engine, and the loop must really have overlapped queries (a
+request admitted while another was on the GPU).  The cache budget is small
+enough to force evictions and admission waits.
+"""
+import numpy as np
+import pytest
+
+from paper_2401_03555_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_03555_amd import impact, serve
+    impact.lib()
+    return impact, serve
+
+
+def _pool():
+    return {
+        "a2": W.tiny_affine(d=2, n=9, seed=2),
+        "a3": W.tiny_affine(d=3, n=6, seed=3),
+        "uni": dict(W.unicycle3d(n=(10, 10, 6))[0], sigma=[0.3, 0.3, 0.2]),
+        "dense": dict(kind="affine", A=np.eye(2) * 0.8, B=np.eye(2) * 0.5, c=np.zeros(2),
+                      lb=[-2.0, -2.0], ub=[2.0, 2.0], n=[26, 26],
+                      inputs=[[0.5, 0.0], [0.0, 0.5]], sigma=[0.3, 0.3], k_sigma=0.0),
+    }
+
+
+def _trace(pool, n=28, seed=5):
+    tr = W.served_trace(pool, rate=2000.0, duration=1.0, seed=seed, max_sweeps=300)
+    return tr[:n]
+
+
+def _np(r):
+    return r["lo"].cpu().numpy(), r["hi"].cpu().numpy(), r["policy"].cpu().numpy()
+
+
+def test_served_results_equal_alone(S):
+    impact, serve = S
+    pool = _pool()
+    trace = _trace(pool)
+    kinds = {r["spec"]["kind"] for r in trace}
+    assert kinds == {"safety", "reach", "reach_avoid"}
+    sizes = {}
+    for k, s in pool.items():
+        im = impact.build_imdp(s)
+        sizes[k] = im.info()["device_bytes"]
+        im.free()
+    # room for the two largest at once: forces evictions and admission waits
+    budget = sorted(sizes.values())[-1] + sorted(sizes.values())[-2]
+    cache = serve.AbstractionCache(pool, budget)
+    srv = serve.Server(cache, max_active=6, steps=4)
+    done, st = srv.run(trace, keep_outputs=True)
+    assert [d["idx"] for d in done] == list(range(len(trace)))
+    assert st["peak_active"] > 1
+    assert cache.evictions > 0 and cache.used <= budget
+    # some request joined while another was running
+    joined = any(a["t_admit"] < b["t_admit"] < a["t_done"] for a in done for b in done
+                 if a is not b)
+    assert joined
+    alone_cache = {}
+    for d, req in zip(done, trace):
+        if req["key"] not in alone_cache:
+            alone_cache[req["key"]] = impact.build_imdp(pool[req["key"]])
+        eng = impact.Engine(max_queries=1)
+        q = eng.submit(alone_cache[req["key"]], req["spec"])
+        ref = eng.run_all()[q]
+        eng.free()
+        for x, y, name in zip(_np(d), _np(ref), ("lo", "hi", "policy")):
+            assert np.array_equal(x, y), f"request {d['idx']} ({req['key']}): {name} differs"
+        assert tuple(d["info"]["sweeps"]) == tuple(ref["info"]["sweeps"])
+        assert d["status"] == ref["status"]
+    srv.free()
+    cache.clear()
+
+
+def test_served_matches_serial_plain_solves(S):
+    impact, serve = S
+    pool = _pool()
+    trace = _trace(pool, n=12, seed=9)
+    cache = serve.AbstractionCache(pool, 1 << 34)
+    srv = serve.Server(cache, max_active=4, steps=8)
+    done, _ = srv.run(trace, keep_outputs=True)
+    ser, _ = serve.serve_serial(cache, trace, keep_outputs=True)
+    assert cache.misses == len({r["key"] for r in trace})
+    for a, b in zip(done, ser):
+        la, ha, pa = _np(a)
+        lb, hb, pb = _np(b)
+        assert np.abs(la - lb).max() <= 1e-9 and np.abs(ha - hb).max() <= 1e-9
+        assert a["status"] == b["status"]
+    st = serve.latency_stats(done, 1.0)
+    assert st["n"] == len(trace) and st["p50_ms"] <= st["p99_ms"]
+    srv.free()
+    cache.clear()
