@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-max-sweeps", type=int, default=1000)
     ap.add_argument("--tune-cache", default=None, help="JSON file for autotuner results")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (a known-size kernel "
+                         "for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -232,6 +235,13 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU visible"
     impact.lib()
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib << 20
+        src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     tuner = Autotuner(path=args.tune_cache)
     system, spec, desc = workload(args.workload)
     max_sweeps = spec["max_sweeps"]

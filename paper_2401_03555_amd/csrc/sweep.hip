@@ -37,7 +37,8 @@ struct BlockLds {
 // WAVE_E: largest per-lane element count of single-wavefront rows (row
 // length <= 64 * WAVE_E); BLOCK_E: largest per-thread count of workgroup rows
 // (row length <= 256 * BLOCK_E), 0 when every row fits one wavefront.
-template <int WAVE_E, int BLOCK_E, int PASS>
+// D > 0: the grid dimension is the compile-time D; D == 0: read at run time.
+template <int WAVE_E, int BLOCK_E, int PASS, int D>
 __device__ double block_sweep_states(const SweepArgs& a, const int32_t* __restrict__ states,
                                      int nst, BlockLds<BLOCK_E>& L) {
   const SysParams& p = *a.sys;
@@ -60,11 +61,11 @@ __device__ double block_sweep_states(const SweepArgs& a, const int32_t* __restri
       if (n <= 64 * WAVE_E) continue;
       double q0, q1;
       if (BLOCK_E <= 4 || n <= 1024)
-        solve_row<4, kWaves>(a, p, row, tid, L.red, L.xk, q0, q1);
+        solve_row<4, kWaves, D>(a, p, row, tid, L.red, L.xk, q0, q1);
       else if (BLOCK_E <= 8 || n <= 2048)
-        solve_row<(BLOCK_E < 8 ? BLOCK_E : 8), kWaves>(a, p, row, tid, L.red, L.xk, q0, q1);
+        solve_row<(BLOCK_E < 8 ? BLOCK_E : 8), kWaves, D>(a, p, row, tid, L.red, L.xk, q0, q1);
       else
-        solve_row<BLOCK_E, kWaves>(a, p, row, tid, L.red, L.xk, q0, q1);
+        solve_row<BLOCK_E, kWaves, D>(a, p, row, tid, L.red, L.xk, q0, q1);
       if (tid == 0) {
         L.qb0[m] = q0;
         L.qb1[m] = q1;
@@ -78,13 +79,13 @@ __device__ double block_sweep_states(const SweepArgs& a, const int32_t* __restri
     if (n > 64 * WAVE_E) continue;
     double q0, q1;
     if (WAVE_E == 1 || n <= 64)
-      solve_row<1, 1>(a, p, row, tid, L.red, L.xk, q0, q1);
+      solve_row<1, 1, D>(a, p, row, tid, L.red, L.xk, q0, q1);
     else if (WAVE_E == 2 || n <= 128)
-      solve_row<(WAVE_E < 2 ? WAVE_E : 2), 1>(a, p, row, tid, L.red, L.xk, q0, q1);
+      solve_row<(WAVE_E < 2 ? WAVE_E : 2), 1, D>(a, p, row, tid, L.red, L.xk, q0, q1);
     else if (WAVE_E == 4 || n <= 256)
-      solve_row<(WAVE_E < 4 ? WAVE_E : 4), 1>(a, p, row, tid, L.red, L.xk, q0, q1);
+      solve_row<(WAVE_E < 4 ? WAVE_E : 4), 1, D>(a, p, row, tid, L.red, L.xk, q0, q1);
     else
-      solve_row<WAVE_E, 1>(a, p, row, tid, L.red, L.xk, q0, q1);
+      solve_row<WAVE_E, 1, D>(a, p, row, tid, L.red, L.xk, q0, q1);
     if (lane == 0) {
       L.qb0[m] = q0;
       L.qb1[m] = q1;
@@ -115,7 +116,7 @@ __device__ double block_sweep_states(const SweepArgs& a, const int32_t* __restri
 
 // PASS 0: all inputs (policy pass); PASS 1: the input fixed by the policy.
 // The two passes are separate kernel symbols so that profiles tell them apart.
-template <int WAVE_E, int BLOCK_E, int PASS>
+template <int WAVE_E, int BLOCK_E, int PASS, int D>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
   if (a.ctrl->done) return;
   __shared__ BlockLds<BLOCK_E> L;
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
   const int G = a.states_per_block;
   const int64_t s0 = (int64_t)blockIdx.x * G;
   const int nst = (int)(a.n_safe - s0 < G ? a.n_safe - s0 : G);
-  double gap = block_sweep_states<WAVE_E, BLOCK_E, PASS>(a, a.safe + s0, nst, L);
+  double gap = block_sweep_states<WAVE_E, BLOCK_E, PASS, D>(a, a.safe + s0, nst, L);
   gap = wave_max(gap);
   if (lane == 0) L.gapw[wv] = gap;
   __syncthreads();
@@ -157,11 +158,11 @@ __global__ __launch_bounds__(kBlock) void k_mq_sweep_block(
     if (phase == 0) {
       a.pass = 0;
       a.maximise = D.safety;
-      g = block_sweep_states<WAVE_E, BLOCK_E, 0>(a, ws + item, 1, L);
+      g = block_sweep_states<WAVE_E, BLOCK_E, 0, 0>(a, ws + item, 1, L);
     } else {
       a.pass = 1;
       a.maximise = !D.safety;
-      g = block_sweep_states<WAVE_E, BLOCK_E, 1>(a, ws + item, 1, L);
+      g = block_sweep_states<WAVE_E, BLOCK_E, 1, 0>(a, ws + item, 1, L);
     }
   } else if ((phase == 1 || phase == 3) && threadIdx.x == 0) {
     const int64_t s = ws[item];
@@ -343,27 +344,38 @@ hipError_t launch_ctrl_init(Ctrl* c, double eps, int64_t cap, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int PASS>
-static hipError_t launch_sweep_pass(const SweepArgs& a, int32_t max_row, hipStream_t st) {
+template <int PASS, int D>
+static hipError_t launch_sweep_pass_d(const SweepArgs& a, int32_t max_row, hipStream_t st) {
   const int64_t blocks = (a.n_safe + a.states_per_block - 1) / a.states_per_block;
   const dim3 g((unsigned)blocks), b(kBlock);
   if (max_row <= 64)
-    hipLaunchKernelGGL((k_sweep<1, 0, PASS>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_sweep<1, 0, PASS, D>), g, b, 0, st, a);
   else if (max_row <= 128)
-    hipLaunchKernelGGL((k_sweep<2, 0, PASS>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_sweep<2, 0, PASS, D>), g, b, 0, st, a);
   else if (max_row <= 256)
-    hipLaunchKernelGGL((k_sweep<4, 0, PASS>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_sweep<4, 0, PASS, D>), g, b, 0, st, a);
   else if (max_row <= 512)
-    hipLaunchKernelGGL((k_sweep<8, 0, PASS>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_sweep<8, 0, PASS, D>), g, b, 0, st, a);
   else if (max_row <= 1024)
-    hipLaunchKernelGGL((k_sweep<8, 4, PASS>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_sweep<8, 4, PASS, D>), g, b, 0, st, a);
   else if (max_row <= 2048)
-    hipLaunchKernelGGL((k_sweep<8, 8, PASS>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_sweep<8, 8, PASS, D>), g, b, 0, st, a);
   else if (max_row <= kMaxRow)
-    hipLaunchKernelGGL((k_sweep<8, 16, PASS>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_sweep<8, 16, PASS, D>), g, b, 0, st, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+// Kernels specialised on the grid dimension for the case-study dimensions.
+template <int PASS>
+static hipError_t launch_sweep_pass(const SweepArgs& a, int32_t max_row, hipStream_t st) {
+  switch (a.d) {
+    case 2: return launch_sweep_pass_d<PASS, 2>(a, max_row, st);
+    case 3: return launch_sweep_pass_d<PASS, 3>(a, max_row, st);
+    case 5: return launch_sweep_pass_d<PASS, 5>(a, max_row, st);
+    default: return launch_sweep_pass_d<PASS, 0>(a, max_row, st);
+  }
 }
 
 hipError_t launch_sweep(const SweepArgs& a, int32_t max_row, hipStream_t st) {

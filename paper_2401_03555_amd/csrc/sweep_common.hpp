@@ -38,11 +38,124 @@ __device__ __forceinline__ int32_t from_bits<int32_t>(uint64_t b) {
   return (int32_t)(uint32_t)b;
 }
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+// ---- cross-lane moves without the LDS address path --------------------------
+// DPP (data-parallel primitives) move a VALU operand between lanes of a
+// 16-lane row (or across rows for the broadcasts) with no LDS traffic;
+// ds_swizzle permutes within 32-lane halves by a fixed bit pattern.  Lanes
+// whose DPP source does not exist keep 0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ int32_t dpp_i32(int32_t x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, ROW_MASK, 0xF, false);
+}
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t x) {
+  const uint32_t lo = (uint32_t)dpp_i32<CTRL, ROW_MASK>((int32_t)(uint32_t)x);
+  const uint32_t hi = (uint32_t)dpp_i32<CTRL, ROW_MASK>((int32_t)(uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_f64(double x) {
+  return __longlong_as_double((long long)dpp_u64<CTRL, ROW_MASK>((uint64_t)__double_as_longlong(x)));
+}
+template <int PATTERN>
+__device__ __forceinline__ uint64_t swz_u64(uint64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_swizzle((int32_t)(uint32_t)x, PATTERN);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_swizzle((int32_t)(uint32_t)(x >> 32), PATTERN);
+  return ((uint64_t)hi << 32) | lo;
+}
+template <int PATTERN>
+__device__ __forceinline__ double swz_f64(double x) {
+  return __longlong_as_double((long long)swz_u64<PATTERN>((uint64_t)__double_as_longlong(x)));
+}
+
+enum : int {
+  kDppXor1 = 0xB1,        // quad_perm [1,0,3,2]
+  kDppXor2 = 0x4E,        // quad_perm [2,3,0,1]
+  kDppRowShr1 = 0x111,    // row_shr:n = 0x110 + n
+  kDppWaveShr1 = 0x138,   // wave_shr:1
+  kDppRowHalfMirror = 0x141,
+  kDppRowMirror = 0x140,
+  kDppBcast15 = 0x142,
+  kDppBcast31 = 0x143,
+};
+// ds_swizzle bit-mask mode: lane' = ((lane & and) | or) ^ xor over 5 bits.
+constexpr int swz_xor(int m) { return 0x1F | (m << 10); }
+constexpr int kSwzLast16 = 0x10 | (0x0F << 5);  // lane 15 of each 16-lane group
+constexpr int kSwzLast32 = 0x1F << 5;           // lane 31 of each 32-lane half
+
+// x of lane (lane ^ m), m a power of two below 64.
+__device__ __forceinline__ uint64_t xor_lane_u64(uint64_t x, int m) {
+  switch (m) {
+    case 1: return dpp_u64<kDppXor1>(x);
+    case 2: return dpp_u64<kDppXor2>(x);
+    case 4: return swz_u64<swz_xor(4)>(x);
+    case 8: return swz_u64<swz_xor(8)>(x);
+    case 16: return swz_u64<swz_xor(16)>(x);
+    default: return (uint64_t)__shfl_xor((long long)x, 32);
+  }
+}
+__device__ __forceinline__ int32_t xor_lane_i32(int32_t x, int m) {
+  switch (m) {
+    case 1: return dpp_i32<kDppXor1>(x);
+    case 2: return dpp_i32<kDppXor2>(x);
+    case 4: return __builtin_amdgcn_ds_swizzle(x, swz_xor(4));
+    case 8: return __builtin_amdgcn_ds_swizzle(x, swz_xor(8));
+    case 16: return __builtin_amdgcn_ds_swizzle(x, swz_xor(16));
+    default: return __shfl_xor(x, 32);
+  }
+}
+
+// Sum over the GW-lane group (GW = 16, 32, 64) of each lane, every lane of the
+// group getting the same value: butterfly over pairs, quads, 8- and 16-lane
+// mirrors, then the halves and the wave.
+template <int GW>
+__device__ __forceinline__ double group_sum_dpp(double x) {
+  x += dpp_f64<kDppXor1>(x);
+  x += dpp_f64<kDppXor2>(x);
+  x += dpp_f64<kDppRowHalfMirror>(x);
+  x += dpp_f64<kDppRowMirror>(x);
+  if (GW >= 32) x += swz_f64<swz_xor(16)>(x);
+  if (GW == 64) x += __shfl_xor(x, 32);
   return x;
 }
+
+// Inclusive prefix sum within GW-lane groups (Hillis-Steele inside 16-lane
+// rows, then the row totals carried across rows).
+template <int GW>
+__device__ __forceinline__ double group_incl_scan_dpp(double x) {
+  x += dpp_f64<kDppRowShr1>(x);
+  x += dpp_f64<kDppRowShr1 + 1>(x);
+  x += dpp_f64<kDppRowShr1 + 3>(x);
+  x += dpp_f64<kDppRowShr1 + 7>(x);
+  if (GW >= 32) x += dpp_f64<kDppBcast15, 0xA>(x);
+  if (GW == 64) x += dpp_f64<kDppBcast31, 0xC>(x);
+  return x;
+}
+
+// Exclusive prefix sum within GW-lane groups (group lane gl) and the group total.
+template <int GW>
+__device__ __forceinline__ double group_excl_scan_dpp(double x, int gl, double& total) {
+  const double incl = group_incl_scan_dpp<GW>(x);
+  if (GW == 16) total = swz_f64<kSwzLast16>(incl);
+  else if (GW == 32) total = swz_f64<kSwzLast32>(incl);
+  else total = __shfl(incl, 63);
+  const double e = dpp_f64<kDppWaveShr1>(incl);
+  return gl == 0 ? 0.0 : e;
+}
+
+template <class V>
+__device__ __forceinline__ V xor_lane(V x, int m);
+template <>
+__device__ __forceinline__ int32_t xor_lane<int32_t>(int32_t x, int m) {
+  return xor_lane_i32(x, m);
+}
+template <>
+__device__ __forceinline__ double xor_lane<double>(double x, int m) {
+  return __longlong_as_double((long long)xor_lane_u64((uint64_t)__double_as_longlong(x), m));
+}
+
+// Every lane of the wavefront active.
+__device__ __forceinline__ double wave_sum(double x) { return group_sum_dpp<64>(x); }
 
 __device__ __forceinline__ double wave_max(double x) {
 #pragma unroll
@@ -50,16 +163,10 @@ __device__ __forceinline__ double wave_max(double x) {
   return x;
 }
 
-// Exclusive prefix sum across the wavefront (lane 0 gets 0).
+// Exclusive prefix sum across the wavefront (lane 0 gets 0); every lane active.
 __device__ __forceinline__ double wave_excl_scan(double x, int lane) {
-  double incl = x;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    double y = __shfl_up(incl, off);
-    if (lane >= off) incl += y;
-  }
-  double e = __shfl_up(incl, 1);
-  return lane == 0 ? 0.0 : e;
+  double total;
+  return group_excl_scan_dpp<64>(x, lane, total);
 }
 
 // Reduction / scan over a group of NW wavefronts (NW == 1: one wavefront).
@@ -137,8 +244,8 @@ __device__ void bitonic_sort(uint64_t (&key)[E], V (&val)[E], int tid, uint64_t*
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           const bool asc = ((tid * E + e) & k) == 0;
-          const uint64_t pk = (uint64_t)__shfl_xor((long long)key[e], tm);
-          const V pv = __shfl_xor(val[e], tm);
+          const uint64_t pk = xor_lane_u64(key[e], tm);
+          const V pv = xor_lane<V>(val[e], tm);
           const bool take = (asc == lower) ? !(key[e] < pk) : !(key[e] > pk);
           if (take) {
             key[e] = pk;
@@ -180,10 +287,11 @@ struct RowSlice {
   bool pad[E];
 };
 
-template <int E>
+// D > 0: the grid dimension is the compile-time D; D == 0: read at run time.
+template <int E, int D>
 __device__ void load_row(const SweepArgs& a, const SysParams& p, int64_t row, int first,
                          RowSlice<E>& rs) {
-  const int d = a.d;
+  const int d = D > 0 ? D : a.d;
   const int64_t base = a.row_off[row];
   const int nw = (int)(a.row_off[row + 1] - base);
   const int32_t* wr = a.win + row * 2 * d;
@@ -290,7 +398,7 @@ __device__ double lp_value(const RowSlice<E>& rs, const double (&v)[E], double r
   return slv + sdv;
 }
 
-template <int E, int NW>
+template <int E, int NW, int D>
 __device__ void solve_row(const SweepArgs& a, const SysParams& p, int64_t row, int tid,
                           double* red, uint64_t* xk, double& q0, double& q1) {
   // a single-wavefront group works in lane coordinates; a workgroup group
@@ -299,7 +407,7 @@ __device__ void solve_row(const SweepArgs& a, const SysParams& p, int64_t row, i
   if (NW > 1) __syncthreads();
   Group<NW> g(red, gtid);
   RowSlice<E> rs;
-  load_row<E>(a, p, row, gtid * E, rs);
+  load_row<E, D>(a, p, row, gtid * E, rs);
   double slo = 0.0;
 #pragma unroll
   for (int e = 0; e < E; ++e) slo += rs.lo[e];

@@ -27,7 +27,7 @@ constexpr int kSbWaves = kSbWavesPerBlock;
 __device__ __forceinline__ int wave_min_i32(int x) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
-    int y = __shfl_xor(x, off);
+    int y = xor_lane_i32(x, off);
     x = y < x ? y : x;
   }
   return x;
@@ -36,7 +36,7 @@ __device__ __forceinline__ int wave_min_i32(int x) {
 __device__ __forceinline__ int wave_max_i32(int x) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
-    int y = __shfl_xor(x, off);
+    int y = xor_lane_i32(x, off);
     x = y > x ? y : x;
   }
   return x;
@@ -61,10 +61,12 @@ __device__ __forceinline__ int row_input(const SweepArgs& a, int64_t s, int ui) 
 }
 
 // Bounding box of the windows of the state's rows (rows whose window is empty
-// in some dimension hold no cells and are ignored).
-template <int PASS>
+// in some dimension hold no cells and are ignored).  D > 0: the grid dimension
+// is the compile-time D (every dimension loop unrolls to straight-line code);
+// D == 0: read at run time.
+template <int PASS, int D>
 __device__ void state_box(const SweepArgs& a, int64_t s, int U, int lane, StateBox& b) {
-  const int d = a.d;
+  const int d = D > 0 ? D : a.d;
   int lo[kMaxDim], hi[kMaxDim];
   IMPACT_FOR_DIMS(i, d) {
     lo[i] = 0x7fffffff;
@@ -107,21 +109,7 @@ __device__ __forceinline__ bool special_front(double v, bool mx) { return mx ? v
 // Reductions over the GW-lane group a lane belongs to (GW = 16, 32 or 64).
 template <int GW>
 __device__ __forceinline__ double group_sum(double x) {
-#pragma unroll
-  for (int off = GW / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, GW);
-  return x;
-}
-
-template <int GW>
-__device__ __forceinline__ double group_excl_scan(double x, int gl) {
-  double incl = x;
-#pragma unroll
-  for (int off = 1; off < GW; off <<= 1) {
-    const double y = __shfl_up(incl, off, GW);
-    if (gl >= off) incl += y;
-  }
-  const double e = __shfl_up(incl, 1, GW);
-  return gl == 0 ? 0.0 : e;
+  return group_sum_dpp<GW>(x);
 }
 
 // Bitonic sort of two key sets at once (same network, independent data),
@@ -137,10 +125,10 @@ __device__ void bitonic_sort2(uint64_t (&ka)[E], int32_t (&pa)[E], uint64_t (&kb
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const bool asc = ((lane * E + e) & k) == 0;
-        const uint64_t qa = (uint64_t)__shfl_xor((long long)ka[e], tm);
-        const uint64_t qb = (uint64_t)__shfl_xor((long long)kb[e], tm);
-        const int32_t ra = __shfl_xor(pa[e], tm);
-        const int32_t rb = __shfl_xor(pb[e], tm);
+        const uint64_t qa = xor_lane_u64(ka[e], tm);
+        const uint64_t qb = xor_lane_u64(kb[e], tm);
+        const int32_t ra = xor_lane_i32(pa[e], tm);
+        const int32_t rb = xor_lane_i32(pb[e], tm);
         const bool keep_min = asc == lower;
         if (keep_min ? !(ka[e] < qa) : !(ka[e] > qa)) {
           ka[e] = qa;
@@ -199,15 +187,16 @@ __device__ double sb_lp_group(const int32_t* __restrict__ ord, const double* __r
     lane_d += dd[k];
   }
   double front = 0.0, q_sp = 0.0;
-  for (int k = 0; k < sp.n; ++k) {
-    if (!special_front(sp.v[k], mx)) continue;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (k >= sp.n || !special_front(sp.v[k], mx)) continue;
     const double room = r - front;
     const double delta = room <= 0.0 ? 0.0 : (sp.dd[k] < room ? sp.dd[k] : room);
     q_sp += (sp.lo[k] + delta) * sp.v[k];
     front += sp.dd[k];
   }
-  const double excl = group_excl_scan<GW>(lane_d, gl);
-  const double total = __shfl(excl + lane_d, GW - 1, GW);
+  double total;
+  const double excl = group_excl_scan_dpp<GW>(lane_d, gl, total);
   double acc = front + excl;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
@@ -217,8 +206,9 @@ __device__ double sb_lp_group(const int32_t* __restrict__ ord, const double* __r
     acc += dd[k];
   }
   double back = front + total;
-  for (int k = 0; k < sp.n; ++k) {
-    if (special_front(sp.v[k], mx)) continue;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (k >= sp.n || special_front(sp.v[k], mx)) continue;
     const double room = r - back;
     const double delta = room <= 0.0 ? 0.0 : (sp.dd[k] < room ? sp.dd[k] : room);
     q_sp += (sp.lo[k] + delta) * sp.v[k];
@@ -229,13 +219,13 @@ __device__ double sb_lp_group(const int32_t* __restrict__ ord, const double* __r
 
 // One SAFE state on one wavefront, box of at most 64*E cells.  The box is
 // sorted with 64 lanes; then the NG lane groups take rows u = g, g+NG, ...
-template <int E, int PASS>
+template <int E, int PASS, int D>
 __device__ void sb_state(const SweepArgs& a, const SysParams& p, int64_t s, int U,
                          const StateBox& b, int lane, SbLds<64 * E>& L, double& best0,
                          double& best1, int& arg) {
   constexpr int P = 64 * E;
   constexpr int NG = SbShape<P>::NG, GW = SbShape<P>::GW, R = SbShape<P>::R;
-  const int d = a.d;
+  const int d = D > 0 ? D : a.d;
   const bool mx = a.maximise != 0;
   const int64_t PB = b.P;
   {
@@ -397,27 +387,27 @@ __device__ void sb_state(const SweepArgs& a, const SysParams& p, int64_t s, int 
 // fallback for states whose box is larger (rows <= 64 * EROW entries).
 // Sweep update of one SAFE state s on one wavefront: writes vout[s] (and
 // pi[s] in the policy pass); returns the state's V1 - V0 (>= 0).
-template <int ESB, int EROW, int PASS>
+template <int ESB, int EROW, int PASS, int D>
 __device__ double sb_sweep_state(const SweepArgs& a, int64_t s, int lane, SbLds<64 * ESB>& L) {
   const SysParams& p = *a.sys;
   const int U = PASS == 0 ? a.nu : 1;
   StateBox b;
-  state_box<PASS>(a, s, U, lane, b);
+  state_box<PASS, D>(a, s, U, lane, b);
   double best0 = 0.0, best1 = 0.0;
   int arg = 0;
   if (b.P <= 64 * ESB) {
     if (ESB == 1 || b.P <= 64)
-      sb_state<1, PASS>(a, p, s, U, b, lane, *(SbLds<64>*)&L, best0, best1, arg);
+      sb_state<1, PASS, D>(a, p, s, U, b, lane, *(SbLds<64>*)&L, best0, best1, arg);
     else if (ESB == 2 || b.P <= 128)
-      sb_state<(ESB < 2 ? ESB : 2), PASS>(a, p, s, U, b, lane,
+      sb_state<(ESB < 2 ? ESB : 2), PASS, D>(a, p, s, U, b, lane,
                                           *(SbLds<64 * (ESB < 2 ? ESB : 2)>*)&L, best0, best1,
                                           arg);
     else if (ESB == 4 || b.P <= 256)
-      sb_state<(ESB < 4 ? ESB : 4), PASS>(a, p, s, U, b, lane,
+      sb_state<(ESB < 4 ? ESB : 4), PASS, D>(a, p, s, U, b, lane,
                                           *(SbLds<64 * (ESB < 4 ? ESB : 4)>*)&L, best0, best1,
                                           arg);
     else
-      sb_state<ESB, PASS>(a, p, s, U, b, lane, L, best0, best1, arg);
+      sb_state<ESB, PASS, D>(a, p, s, U, b, lane, L, best0, best1, arg);
   } else if constexpr (EROW > 0) {
     const int extra = 1 + a.windowed;
     for (int ui = 0; ui < U; ++ui) {
@@ -426,13 +416,13 @@ __device__ double sb_sweep_state(const SweepArgs& a, int64_t s, int lane, SbLds<
       const int n = (int)(a.row_off[row + 1] - a.row_off[row]) + extra;
       double q0, q1;
       if (EROW == 1 || n <= 64)
-        solve_row<1, 1>(a, p, row, lane, nullptr, nullptr, q0, q1);
+        solve_row<1, 1, 0>(a, p, row, lane, nullptr, nullptr, q0, q1);
       else if (EROW == 2 || n <= 128)
-        solve_row<(EROW < 2 ? EROW : 2), 1>(a, p, row, lane, nullptr, nullptr, q0, q1);
+        solve_row<(EROW < 2 ? EROW : 2), 1, 0>(a, p, row, lane, nullptr, nullptr, q0, q1);
       else if (EROW == 4 || n <= 256)
-        solve_row<(EROW < 4 ? EROW : 4), 1>(a, p, row, lane, nullptr, nullptr, q0, q1);
+        solve_row<(EROW < 4 ? EROW : 4), 1, 0>(a, p, row, lane, nullptr, nullptr, q0, q1);
       else
-        solve_row<EROW, 1>(a, p, row, lane, nullptr, nullptr, q0, q1);
+        solve_row<EROW, 1, 0>(a, p, row, lane, nullptr, nullptr, q0, q1);
       if (ui == 0) {
         best0 = q0;
         best1 = q1;
@@ -454,7 +444,7 @@ __device__ double sb_sweep_state(const SweepArgs& a, int64_t s, int lane, SbLds<
   return gap > 0.0 ? gap : 0.0;
 }
 
-template <int ESB, int EROW, int PASS>
+template <int ESB, int EROW, int PASS, int D>
 __global__ __launch_bounds__(64 * kSbWaves) void k_sweep_sb(SweepArgs a) {
   if (a.ctrl->done) return;
   __shared__ SbLds<64 * ESB> lds[kSbWaves];
@@ -464,7 +454,7 @@ __global__ __launch_bounds__(64 * kSbWaves) void k_sweep_sb(SweepArgs a) {
   double gap = 0.0;
   if (si < a.n_safe) {
     const int64_t s = uniform_i64(a.safe[si]);
-    gap = sb_sweep_state<ESB, EROW, PASS>(a, s, lane, lds[wv]);
+    gap = sb_sweep_state<ESB, EROW, PASS, D>(a, s, lane, lds[wv]);
   }
   if (lane == 0) gapw[wv] = gap;
   __syncthreads();
@@ -491,6 +481,30 @@ __device__ __forceinline__ void mq_close_state(const QueryDesc& D, int64_t step,
   }
 }
 
+// The state-box update of one item, specialised on its grid dimension when
+// the kernel has no per-row fallback (EROW == 0).
+template <int ESB, int EROW, int PASS>
+__device__ double mq_sb_pass(const SweepArgs& a, int d, int64_t s, int lane,
+                             SbLds<64 * ESB>& L) {
+  if constexpr (EROW == 0) {
+    switch (d) {
+      case 2: return sb_sweep_state<ESB, 0, PASS, 2>(a, s, lane, L);
+      case 3: return sb_sweep_state<ESB, 0, PASS, 3>(a, s, lane, L);
+      case 5: return sb_sweep_state<ESB, 0, PASS, 5>(a, s, lane, L);
+      default: return sb_sweep_state<ESB, 0, PASS, 0>(a, s, lane, L);
+    }
+  } else {
+    return sb_sweep_state<ESB, EROW, PASS, 0>(a, s, lane, L);
+  }
+}
+
+template <int ESB, int EROW>
+__device__ double mq_sb_dispatch(const SweepArgs& a, int d, bool policy_pass, int64_t s,
+                                 int lane, SbLds<64 * ESB>& L) {
+  return policy_pass ? mq_sb_pass<ESB, EROW, 0>(a, d, s, lane, L)
+                     : mq_sb_pass<ESB, EROW, 1>(a, d, s, lane, L);
+}
+
 // Multi-query state-box sweep: one wavefront per (query, SAFE state) item,
 // each query at its own phase and step.
 template <int ESB, int EROW>
@@ -513,15 +527,9 @@ __global__ __launch_bounds__(64 * kSbWaves) void k_mq_sweep_sb(
     a.vin = (step & 1) ? D.vb1 : D.vb0;
     a.vout = (step & 1) ? D.vb0 : D.vb1;
     a.reach = !D.safety;
-    if (phase == 0) {
-      a.pass = 0;
-      a.maximise = D.safety;
-      g = sb_sweep_state<ESB, EROW, 0>(a, s, lane, lds[wv]);
-    } else {
-      a.pass = 1;
-      a.maximise = !D.safety;
-      g = sb_sweep_state<ESB, EROW, 1>(a, s, lane, lds[wv]);
-    }
+    a.pass = phase == 0 ? 0 : 1;
+    a.maximise = phase == 0 ? D.safety : !D.safety;
+    g = mq_sb_dispatch<ESB, EROW>(a, uniform_i32(a.d), phase == 0, s, lane, lds[wv]);
   } else if ((phase == 1 || phase == 3) && lane == 0) {
     mq_close_state(D, step, phase, s);
   }
@@ -540,20 +548,28 @@ static hipError_t launch_sb_pass(const SweepArgs& a, int64_t max_box, int32_t ma
   const int er = lanes_elems(max_row);
   if (er == 0) return hipErrorInvalidValue;
   const int eb = lanes_elems(max_box);
-#define SB(E1, E2) hipLaunchKernelGGL((k_sweep_sb<E1, E2, PASS>), g, bl, 0, st, a)
+#define SB(E1, E2, D) hipLaunchKernelGGL((k_sweep_sb<E1, E2, PASS, D>), g, bl, 0, st, a)
+#define SBD(E1)                       \
+  switch (a.d) {                      \
+    case 2: SB(E1, 0, 2); break;      \
+    case 3: SB(E1, 0, 3); break;      \
+    case 5: SB(E1, 0, 5); break;      \
+    default: SB(E1, 0, 0); break;     \
+  }
   switch (eb) {
-    case 1: SB(1, 0); break;
-    case 2: SB(2, 0); break;
-    case 4: SB(4, 0); break;
-    case 8: SB(8, 0); break;
+    case 1: SBD(1); break;
+    case 2: SBD(2); break;
+    case 4: SBD(4); break;
+    case 8: SBD(8); break;
     default:  // some boxes exceed 512 cells: per-row sorts for those states
       switch (er) {
-        case 1: SB(8, 1); break;
-        case 2: SB(8, 2); break;
-        case 4: SB(8, 4); break;
-        default: SB(8, 8); break;
+        case 1: SB(8, 1, 0); break;
+        case 2: SB(8, 2, 0); break;
+        case 4: SB(8, 4, 0); break;
+        default: SB(8, 8, 0); break;
       }
   }
+#undef SBD
 #undef SB
   return hipGetLastError();
 }
