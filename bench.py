@@ -95,6 +95,74 @@ def algorithmic_bytes(imdp, policy, n_states, d):
     return per_pass1, cells, rows
 
 
+FP64_PEAK_TFLOPS = 78.6
+
+
+def kernel_source_hash():
+    """Digest of the HIP sources and the C header: identifies the kernels'
+    build for hardware counters recorded under profiles/."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2401_03555_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp")))
+    for f in files + [os.path.join(ROOT, "include", "impact.h")]:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel, storage, workload):
+    """HBM bytes per launch of ``kernel`` from the FETCH_SIZE / WRITE_SIZE
+    summaries under profiles/ (lines ``traffic: key=value ...``), or None when
+    none was recorded for this kernel build."""
+    import glob
+    src = kernel_source_hash()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(f) as fh:
+            for line in fh:
+                if not line.startswith("traffic:"):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:] if "=" in x)
+                if (kv.get("kernel") == kernel and kv.get("storage") == storage
+                        and kv.get("workload") == workload and kv.get("src") == src):
+                    return int(kv["bytes_per_launch"])
+    return None
+
+
+def build_roofline(imdp, d):
+    """Construction against both of its ceilings.
+
+    HBM: bytes the build must write -- per row 8*d B window + 32 B OUT/TAIL +
+    8 B row offset, plus 16 B per entry (bounds storage) or 16 B per factor
+    (sum of the window widths; factor storage).  FP64: the 2(d-1) multiplies
+    that form each entry's (lo, hi) from its factors (the erfc evaluations,
+    ~sum_i (4 W_i + 2) per row, are not counted as flops).  Entries are counted
+    as implied entries whatever the storage.
+    """
+    info = imdp.info()
+    ex = imdp.export_rows(0, info["n_rows"], entries=False)
+    cells = int(ex["counts"].sum())
+    rows = info["n_rows"]
+    fac = int(ex["win"][:, d:].sum())
+    payload = 16 * (fac if info["storage"] == 2 else cells)
+    nbytes = payload + rows * (8 * d + 32 + 8)
+    t = info["build_ms"] * 1e-3
+    muls = 2 * max(0, d - 1) * cells
+    return {
+        "kernels": "k_row_geom + scan + k_expand",
+        "build_ms": info["build_ms"],
+        "entries_per_s": info["n_entries"] / t,
+        "hbm_bytes": nbytes,
+        "hbm_gbs": nbytes / t / 1e9,
+        "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS,
+        "fp64_mul_per_s": muls / t,
+        "fp64_frac": muls / t / (FP64_PEAK_TFLOPS * 1e12),
+        "binding": "hbm" if nbytes / HBM_PEAK_GBS / 1e9 > muls / (FP64_PEAK_TFLOPS * 1e12)
+                   else "fp64",
+    }
+
+
 def cpu_baseline(system, spec, budget_s=25.0):
     """The oracle as it stands, single-threaded, on a bounded sample."""
     import numpy as np
@@ -321,6 +389,7 @@ def main():
             "iter_updates_per_s": updates / (iinfo["iterate_ms"] * 1e-3),
             "iterate_ms": iinfo["iterate_ms"],
             "served_p99_ms": None,
+            "build_roofline": build_roofline(imdp, d),
         },
         "roofline": {
             "kernel": ("k_sweep_sb" if box else "k_sweep") +
@@ -330,7 +399,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": recorded_traffic("k_sweep_sb" if box else "k_sweep", storage,
+                                        args.workload),
             "bytes_per_sweep": bytes_sweep,
             "avg_launch_ms": avg_launch_ms,
             "launches": launches0,

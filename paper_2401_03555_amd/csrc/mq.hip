@@ -28,8 +28,7 @@ namespace impact {
 // Per-query stop test and phase machine (one workgroup per query slot).
 __global__ __launch_bounds__(256) void k_mq_finish(const QueryDesc* __restrict__ desc,
                                                    QueryCtrl* __restrict__ ctrl,
-                                                   const double* __restrict__ gap_sb,
-                                                   const double* __restrict__ gap_blk,
+                                                   const double* __restrict__ gp,
                                                    int32_t* __restrict__ done_count) {
   __shared__ double wmax[4];
   const int q = blockIdx.x;
@@ -38,7 +37,6 @@ __global__ __launch_bounds__(256) void k_mq_finish(const QueryDesc* __restrict__
   const QueryDesc& D = desc[q];
   double g = 0.0;
   if (phase == 0 || phase == 2) {
-    const double* gp = D.box_class ? gap_sb : gap_blk;
     for (int64_t i = D.work_begin + threadIdx.x; i < D.work_end; i += blockDim.x)
       g = fmax(g, gp[i]);
     for (int off = 32; off > 0; off >>= 1) g = fmax(g, __shfl_xor(g, off));
@@ -75,15 +73,12 @@ __global__ __launch_bounds__(256) void k_mq_finish(const QueryDesc* __restrict__
 struct MqSegment {
   const int32_t* safe;
   int64_t dst, n;
-  int32_t slot, box_class;
+  int32_t slot, cls;
 };
 
-__global__ void k_mq_fill(const MqSegment* __restrict__ seg, int32_t* __restrict__ wq_sb,
-                          int32_t* __restrict__ ws_sb, int32_t* __restrict__ wq_blk,
-                          int32_t* __restrict__ ws_blk) {
+__global__ void k_mq_fill(const MqSegment* __restrict__ seg, int32_t* __restrict__ wq,
+                          int32_t* __restrict__ ws) {
   const MqSegment S = seg[blockIdx.x];
-  int32_t* wq = S.box_class ? wq_sb : wq_blk;
-  int32_t* ws = S.box_class ? ws_sb : ws_blk;
   for (int64_t i = threadIdx.x; i < S.n; i += blockDim.x) {
     wq[S.dst + i] = S.slot;
     ws[S.dst + i] = S.safe[i];
@@ -102,12 +97,31 @@ int mq_fail(int code, const std::string& m) {
 
 struct MqNoMem {};
 
+// Kernel classes of the engine: the queries of one class share a launch of
+// the kernel variant sized for them.  State-box classes by grid dimension
+// (2, 3, 5, other) and the per-lane element count of their largest state box
+// (1, 2, 4, 8; boxes beyond 512 cells are split into input groups by the 8
+// classes), and workgroup classes for rows beyond 512 entries (by the longest
+// row).
+constexpr int kMqBoxClasses = 16;
+constexpr int kMqClasses = kMqBoxClasses + 3;
+constexpr int kMqDims[4] = {2, 3, 5, 0};
+
+int elems_for(int64_t n) { return n <= 64 ? 1 : n <= 128 ? 2 : n <= 256 ? 4 : n <= 512 ? 8 : 0; }
+int elems_slot(int e) { return e == 1 ? 0 : e == 2 ? 1 : e == 4 ? 2 : 3; }
+
+struct MqClass {
+  int64_t begin = 0, n = 0, max_box = 1;
+  int32_t max_row = 1;
+  bool box = true;
+};
+
 struct MqQuery {
   int32_t id = -1;
   bool active = false;    // occupies its slot
   bool finished = false;  // reported by a poll
   int64_t n_safe = 0, n_states = 0;
-  int32_t box_class = 1, max_row = 0, nu = 1;
+  int32_t box_class = 1, max_row = 0, nu = 1, d = 0;
   int64_t max_box = 0;
   std::shared_ptr<void> keep;  // keeps the abstraction's storage alive
   std::vector<void*> bufs;
@@ -129,12 +143,11 @@ struct impact_mq {
   QueryCtrl* d_ctrl = nullptr;
   int32_t* d_done = nullptr;
   std::vector<QueryDesc> h_desc;
-  // work lists
-  int32_t *wq_sb = nullptr, *ws_sb = nullptr, *wq_blk = nullptr, *ws_blk = nullptr;
-  double *gap_sb = nullptr, *gap_blk = nullptr;
-  int64_t cap_sb = 0, cap_blk = 0, n_sb = 0, n_blk = 0;
-  int64_t max_box_sb = 1;
-  int32_t max_row_sb = 1, max_row_blk = 513;
+  // one work list of (query slot, state) items, grouped by kernel class
+  int32_t *wq = nullptr, *ws = nullptr;
+  double* gap = nullptr;
+  int64_t cap_items = 0, n_items = 0;
+  MqClass cls[kMqClasses];
   int32_t n_slots_used = 0;
   bool dirty = true;
   // captured chunk of steps
@@ -181,8 +194,8 @@ struct impact_mq {
     drop_graph();
     for (auto& q : slots)
       for (void* p : q.bufs) release(p);
-    for (void* p : {(void*)d_desc, (void*)d_ctrl, (void*)d_done, (void*)wq_sb, (void*)ws_sb,
-                    (void*)wq_blk, (void*)ws_blk, (void*)gap_sb, (void*)gap_blk})
+    for (void* p : {(void*)d_desc, (void*)d_ctrl, (void*)d_done, (void*)wq, (void*)ws,
+                    (void*)gap})
       release(p);
     if (st) (void)hipStreamDestroy(st);
   }
@@ -225,59 +238,61 @@ void ensure(impact_mq* m, T*& p, int64_t& cap, int64_t need) {
   cap = nc;
 }
 
-// Rebuild the work lists from the live (unfinished) queries.
+int class_of(const MqQuery& q) {
+  if (q.box_class) {
+    const int ds = q.d == 2 ? 0 : q.d == 3 ? 1 : q.d == 5 ? 2 : 3;
+    return 4 * ds + elems_slot(elems_for(std::min<int64_t>(q.max_box, 512)));
+  }
+  return kMqBoxClasses + (q.max_row <= 1024 ? 0 : q.max_row <= 2048 ? 1 : 2);
+}
+
+// Rebuild the work list from the live (unfinished) queries, grouped by class.
 void rebuild(impact_mq* m) {
   std::vector<MqSegment> seg;
-  int64_t nsb = 0, nblk = 0;
-  int64_t mbox = 1;
-  int32_t mrow_sb = 1, mrow_blk = 513;
+  MqClass cl[kMqClasses];
+  for (int c = 0; c < kMqClasses; ++c) cl[c].box = c < kMqBoxClasses;
   for (int32_t k = 0; k < m->n_slots_used; ++k) {
     MqQuery& q = m->slots[k];
-    QueryDesc& D = m->h_desc[k];
-    if (!q.active || q.finished || q.n_safe == 0) {
-      D.work_begin = D.work_end = 0;
-      continue;
-    }
+    m->h_desc[k].work_begin = m->h_desc[k].work_end = 0;
+    if (!q.active || q.finished || q.n_safe == 0) continue;
     MqSegment S;
     S.safe = q.safe;
     S.n = q.n_safe;
     S.slot = k;
-    S.box_class = q.box_class;
-    if (q.box_class) {
-      S.dst = nsb;
-      nsb += q.n_safe;
-      mbox = std::max(mbox, q.max_box);
-      mrow_sb = std::max(mrow_sb, q.max_row);
-    } else {
-      S.dst = nblk;
-      nblk += q.n_safe;
-      mrow_blk = std::max(mrow_blk, q.max_row);
-    }
-    D.work_begin = S.dst;
-    D.work_end = S.dst + S.n;
+    S.cls = class_of(q);
+    S.dst = 0;
+    MqClass& c = cl[S.cls];
+    c.n += q.n_safe;
+    c.max_box = std::max(c.max_box, q.max_box);
+    c.max_row = std::max(c.max_row, q.max_row);
     seg.push_back(S);
   }
-  int64_t c1 = m->cap_sb, c2 = m->cap_sb, c3 = m->cap_sb;
-  ensure(m, m->wq_sb, c1, nsb);
-  ensure(m, m->ws_sb, c2, nsb);
-  ensure(m, m->gap_sb, c3, nsb);
-  m->cap_sb = std::min({c1, c2, c3});
-  int64_t b1 = m->cap_blk, b2 = m->cap_blk, b3 = m->cap_blk;
-  ensure(m, m->wq_blk, b1, nblk);
-  ensure(m, m->ws_blk, b2, nblk);
-  ensure(m, m->gap_blk, b3, nblk);
-  m->cap_blk = std::min({b1, b2, b3});
-  m->n_sb = nsb;
-  m->n_blk = nblk;
-  m->max_box_sb = mbox;
-  m->max_row_sb = mrow_sb;
-  m->max_row_blk = mrow_blk;
+  int64_t total = 0;
+  for (int c = 0; c < kMqClasses; ++c) {
+    cl[c].begin = total;
+    total += cl[c].n;
+  }
+  int64_t at[kMqClasses];
+  for (int c = 0; c < kMqClasses; ++c) at[c] = cl[c].begin;
+  for (MqSegment& S : seg) {
+    S.dst = at[S.cls];
+    at[S.cls] += S.n;
+    m->h_desc[S.slot].work_begin = S.dst;
+    m->h_desc[S.slot].work_end = S.dst + S.n;
+  }
+  int64_t c1 = m->cap_items, c2 = m->cap_items, c3 = m->cap_items;
+  ensure(m, m->wq, c1, total);
+  ensure(m, m->ws, c2, total);
+  ensure(m, m->gap, c3, total);
+  m->cap_items = std::min({c1, c2, c3});
+  m->n_items = total;
+  for (int c = 0; c < kMqClasses; ++c) m->cls[c] = cl[c];
   if (!seg.empty()) {
     MqSegment* d_seg = (MqSegment*)m->alloc(sizeof(MqSegment) * seg.size());
     MQ_TRY(hipMemcpyAsync(d_seg, seg.data(), sizeof(MqSegment) * seg.size(),
                           hipMemcpyHostToDevice, m->st));
-    hipLaunchKernelGGL(k_mq_fill, dim3((unsigned)seg.size()), dim3(256), 0, m->st, d_seg, m->wq_sb,
-                       m->ws_sb, m->wq_blk, m->ws_blk);
+    hipLaunchKernelGGL(k_mq_fill, dim3((unsigned)seg.size()), dim3(256), 0, m->st, d_seg, m->wq,
+                       m->ws);
     MQ_TRY(hipGetLastError());
     MQ_TRY(hipStreamSynchronize(m->st));
     m->release(d_seg);
@@ -290,13 +305,18 @@ void rebuild(impact_mq* m) {
 
 void enqueue_step(impact_mq* m) {
   if (m->n_slots_used == 0) return;
-  MQ_TRY(launch_mq_sweep_sb(m->d_desc, m->d_ctrl, m->wq_sb, m->ws_sb, m->n_sb, m->gap_sb,
-                            m->max_box_sb, m->max_row_sb, m->st));
-  MQ_TRY(launch_mq_sweep_block(m->d_desc, m->d_ctrl, m->wq_blk, m->ws_blk, m->n_blk, m->gap_blk,
-                               m->max_row_blk, m->st));
+  for (int c = 0; c < kMqClasses; ++c) {
+    const MqClass& k = m->cls[c];
+    if (k.n == 0) continue;
+    if (k.box)
+      MQ_TRY(launch_mq_sweep_sb(m->d_desc, m->d_ctrl, m->wq + k.begin, m->ws + k.begin, k.n,
+                                m->gap + k.begin, k.max_box, k.max_row, kMqDims[c / 4], m->st));
+    else
+      MQ_TRY(launch_mq_sweep_block(m->d_desc, m->d_ctrl, m->wq + k.begin, m->ws + k.begin, k.n,
+                                   m->gap + k.begin, k.max_row, m->st));
+  }
   hipLaunchKernelGGL(k_mq_finish, dim3((unsigned)m->n_slots_used), dim3(256), 0, m->st,
-                     (const QueryDesc*)m->d_desc, m->d_ctrl, (const double*)m->gap_sb,
-                     (const double*)m->gap_blk, m->d_done);
+                     (const QueryDesc*)m->d_desc, m->d_ctrl, (const double*)m->gap, m->d_done);
   MQ_TRY(hipGetLastError());
 }
 
@@ -482,6 +502,7 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
     q.max_row = v.max_row;
     q.max_box = v.max_box;
     q.nu = v.nu;
+    q.d = v.d;
     q.keep = v.keep;
     q.safe = safe;
     m->slots[k] = q;
@@ -515,7 +536,7 @@ int impact_mq_run(impact_mq* m, int32_t steps, int32_t* n_active) {
     MQ_TRY(hipStreamSynchronize(m->st));
     int32_t left = steps;
     const int32_t chunk_max = 64;
-    while (left > 0 && done < m->live_submitted && m->n_sb + m->n_blk > 0) {
+    while (left > 0 && done < m->live_submitted && m->n_items > 0) {
       const int32_t c = std::min(left, chunk_max);
       if (!m->exec || m->graph_steps != c) capture(m, c);
       MQ_TRY(hipGraphLaunch(m->exec, m->st));

@@ -60,42 +60,78 @@ __device__ __forceinline__ int row_input(const SweepArgs& a, int64_t s, int ui) 
   return PASS == 0 ? ui : a.pi[s];
 }
 
-// Bounding box of the windows of the state's rows (rows whose window is empty
-// in some dimension hold no cells and are ignored).  D > 0: the grid dimension
-// is the compile-time D (every dimension loop unrolls to straight-line code);
-// D == 0: read at run time.
+// Inclusive prefix min / max across the wavefront (lane l: over lanes 0..l).
+__device__ __forceinline__ int wave_prefix_min_i32(int x, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off);
+    if (lane >= off) x = y < x ? y : x;
+  }
+  return x;
+}
+__device__ __forceinline__ int wave_prefix_max_i32(int x, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off);
+    if (lane >= off) x = y > x ? y : x;
+  }
+  return x;
+}
+
+// The next group of consecutive inputs [g0, g1) of state s whose windows'
+// bounding box holds at most cap cells: the longest run from g0 (at most 64
+// inputs) for which it does, or the single input g0 when its own window is
+// larger.  Rows whose window is empty in some dimension hold no cells and do
+// not widen the box.  D > 0: the grid dimension is the compile-time D (every
+// dimension loop unrolls to straight-line code); D == 0: read at run time.
 template <int PASS, int D>
-__device__ void state_box(const SweepArgs& a, int64_t s, int U, int lane, StateBox& b) {
+__device__ __forceinline__ int group_box(const SweepArgs& a, int64_t s, int g0, int U, int64_t cap, int lane,
+                         StateBox& b) {
   const int d = D > 0 ? D : a.d;
   int lo[kMaxDim], hi[kMaxDim];
   IMPACT_FOR_DIMS(i, d) {
     lo[i] = 0x7fffffff;
     hi[i] = -0x7fffffff;
   }
-  for (int ui = lane; ui < U; ui += 64) {
+  const int ui = g0 + lane;
+  if (ui < U) {
     const int64_t row = s * a.nu + row_input<PASS>(a, s, ui);
     const int32_t* wr = a.win + row * 2 * d;
     bool empty = false;
     IMPACT_FOR_DIMS(i, d) empty = empty || wr[d + i] == 0;
     if (!empty)
       IMPACT_FOR_DIMS(i, d) {
-        lo[i] = wr[i] < lo[i] ? wr[i] : lo[i];
-        hi[i] = wr[i] + wr[d + i] > hi[i] ? wr[i] + wr[d + i] : hi[i];
+        lo[i] = wr[i];
+        hi[i] = wr[i] + wr[d + i];
       }
   }
   int64_t P = 1;
   IMPACT_FOR_DIMS(i, d) {
-    const int l = uniform_i32(wave_min_i32(lo[i])), h = uniform_i32(wave_max_i32(hi[i]));
+    lo[i] = wave_prefix_min_i32(lo[i], lane);
+    hi[i] = wave_prefix_max_i32(hi[i], lane);
+    P *= hi[i] > lo[i] ? (int64_t)(hi[i] - lo[i]) : 0;
+  }
+  // first lane whose prefix box is too large ends the group (at least one row)
+  const bool over = ui < U && P > cap;
+  const uint64_t m = (uint64_t)__ballot(over);
+  const int n_in = U - g0 < 64 ? U - g0 : 64;
+  int len = m ? __builtin_ctzll(m) : n_in;
+  if (len == 0) len = 1;
+  const int last = len - 1;
+  int64_t PB = 1;
+  IMPACT_FOR_DIMS(i, d) {
+    const int l = uniform_i32(__shfl(lo[i], last)), h = uniform_i32(__shfl(hi[i], last));
     b.blo[i] = l;
     b.ext[i] = h > l ? h - l : 0;
-    P *= b.ext[i];
+    PB *= b.ext[i];
   }
   int32_t st = 1;
   IMPACT_FOR_DIMS_REV(i, d) {
     b.bstride[i] = st;
     st = (int32_t)((int64_t)st * b.ext[i] > 0x3fffffff ? 0x3fffffff : st * b.ext[i]);
   }
-  b.P = P;
+  b.P = PB;
+  return g0 + len;
 }
 
 // OUT / TAIL: value exactly 0 or 1, so first or last in every sorted order.
@@ -110,6 +146,30 @@ __device__ __forceinline__ bool special_front(double v, bool mx) { return mx ? v
 template <int GW>
 __device__ __forceinline__ double group_sum(double x) {
   return group_sum_dpp<GW>(x);
+}
+
+// Bitonic sort of one key set, 64 lanes x E keys, blocked layout, ascending.
+template <int E>
+__device__ void bitonic_sort1(uint64_t (&ka)[E], int32_t (&pa)[E], int lane) {
+  constexpr int P = 64 * E;
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j >= E; j >>= 1) {
+      const int tm = j / E;
+      const bool lower = (lane & tm) == 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const bool asc = ((lane * E + e) & k) == 0;
+        const uint64_t qa = xor_lane_u64(ka[e], tm);
+        const int32_t ra = xor_lane_i32(pa[e], tm);
+        const bool keep_min = asc == lower;
+        if (keep_min ? !(ka[e] < qa) : !(ka[e] > qa)) {
+          ka[e] = qa;
+          pa[e] = ra;
+        }
+      }
+    }
+    intra_stages<E, int32_t>(ka, pa, lane, k);
+  }
 }
 
 // Bitonic sort of two key sets at once (same network, independent data),
@@ -145,47 +205,87 @@ __device__ void bitonic_sort2(uint64_t (&ka)[E], int32_t (&pa)[E], uint64_t (&kb
   }
 }
 
-// Rows of a state are processed by NG lane groups of GW = 64/NG lanes at a
-// time, each lane holding 8 sorted positions: NG = 4 for boxes of up to 128
-// cells, 2 for 256, 1 for 512.
-template <int P>
-struct SbShape {
-  static constexpr int NG = P <= 128 ? 4 : (P <= 256 ? 2 : 1);
-  static constexpr int GW = 64 / NG;
-  static constexpr int R = P / GW;
-};
-
-// Per-wavefront LDS of the state-box path (P = box capacity).
+// Per-wavefront LDS of the state-box path (P = box capacity): each box cell's
+// (V0, V1) and its position in the two sorted orders.
 template <int P>
 struct SbLds {
-  int32_t ord[2][P];                 // box position of the j-th entry of each order
-  double val[2][P];                  // its value
-  double2 stg[SbShape<P>::NG][P];    // (lo, hi) over the box, one array per lane group
+  double2 vb[P];
+  uint16_t rk[2][P];
 };
 
-// Sorting-method LP of one row along one sorted order, on a GW-lane group:
-// lane gl holds sorted positions [gl*R, gl*R + R).
-template <int R, int GW>
-__device__ double sb_lp_group(const int32_t* __restrict__ ord, const double* __restrict__ val,
-                          const double2* __restrict__ stg, int64_t P, double r, bool mx,
-                          const Specials& sp, int gl) {
-  double dd[R], vv[R];
-  double lane_d = 0.0, lane_q = 0.0;
+// Entries held per lane: a row of up to 8 * GW window cells on a GW-lane group.
+constexpr int kSbEntriesPerLane = 8;
+
+// A row entry held by a lane: its width dd = hi - lo and one packed word with
+// its positions in the two sorted orders (bits 0-9, 10-19) and in the box
+// (bits 20-29); kNoEntry marks an empty slot (positions 1023, beyond any box).
+constexpr uint32_t kNoEntry = 0xFFFFFFFFu;
+__device__ __forceinline__ int entry_pos(uint32_t pk, int order) {
+  return (int)((pk >> (10 * order)) & 1023u);
+}
+__device__ __forceinline__ int entry_box(uint32_t pk) { return (int)((pk >> 20) & 1023u); }
+
+// Sorting-method LP of one row along one order, without walking the order:
+// the greedy gives every entry its full width dd until the budget rb runs
+// out at one critical entry, so the result only needs the critical position
+// j* = max{ j : S(j) <= rb }, with S(j) the row's total dd over order
+// positions below j.  S is monotone, so j* is found by bisection on group
+// sums.  Entries at positions below j* add dd * v, the critical one adds the
+// rest of the budget times its value.  Lane gl of the GW-lane group holds
+// entries k = 0..EL-1; values come from the box's LDS copy.  Returns the group
+// sum of the cells' greedy mass times value, and the cells' total width in
+// `total`.
+template <int EL, int GW, int P>
+__device__ double sb_greedy(const double (&dd)[EL], const uint32_t (&pk)[EL], int order,
+                            const SbLds<P>& L, int PB, double rb, double& total) {
+  double t = 0.0;
 #pragma unroll
-  for (int k = 0; k < R; ++k) {
-    const int j = gl * R + k;
-    const int o = ord[j];
-    if (o < P) {
-      const double2 b = stg[o];
-      dd[k] = b.y - b.x;
-      vv[k] = val[j];
-      lane_q += b.x * vv[k];
-    } else {
-      dd[k] = 0.0;
-      vv[k] = 0.0;
+  for (int k = 0; k < EL; ++k) t += dd[k];
+  total = group_sum_dpp<GW>(t);
+  int lo = 0, hi = PB + 1;  // S(lo) <= rb (or lo == 0), S(hi) > rb (or hi == PB + 1)
+  double s_lo = 0.0;
+  if (total <= rb) {
+    lo = PB;
+    s_lo = total;
+  } else {
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      double x = 0.0;
+#pragma unroll
+      for (int k = 0; k < EL; ++k) x += entry_pos(pk[k], order) < mid ? dd[k] : 0.0;
+      x = group_sum_dpp<GW>(x);
+      if (x <= rb) {
+        lo = mid;
+        s_lo = x;
+      } else {
+        hi = mid;
+      }
     }
-    lane_d += dd[k];
   }
+  const double room = rb - s_lo;
+  double q = 0.0;
+#pragma unroll
+  for (int k = 0; k < EL; ++k) {
+    const int ps = entry_pos(pk[k], order);
+    if (ps <= lo && pk[k] != kNoEntry) {
+      const double2 V = L.vb[entry_box(pk[k])];
+      const double v = order == 0 ? V.x : V.y;
+      if (ps < lo) {
+        q += dd[k] * v;
+      } else {
+        const double delta = room <= 0.0 ? 0.0 : (dd[k] < room ? dd[k] : room);
+        q += delta * v;
+      }
+    }
+  }
+  return group_sum_dpp<GW>(q);
+}
+
+// One row's LP value along one order (specials at the front or the back).
+template <int EL, int GW, int P>
+__device__ double sb_row_lp(const double (&dd)[EL], const uint32_t (&pk)[EL], int order,
+                            const SbLds<P>& L, int PB, double r, double slv, bool mx,
+                            const Specials& sp) {
   double front = 0.0, q_sp = 0.0;
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
@@ -196,15 +296,7 @@ __device__ double sb_lp_group(const int32_t* __restrict__ ord, const double* __r
     front += sp.dd[k];
   }
   double total;
-  const double excl = group_excl_scan_dpp<GW>(lane_d, gl, total);
-  double acc = front + excl;
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    const double room = r - acc;
-    const double delta = room <= 0.0 ? 0.0 : (dd[k] < room ? dd[k] : room);
-    if (delta > 0.0) lane_q += delta * vv[k];
-    acc += dd[k];
-  }
+  const double qc = sb_greedy<EL, GW, P>(dd, pk, order, L, PB, r - front, total);
   double back = front + total;
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
@@ -214,17 +306,20 @@ __device__ double sb_lp_group(const int32_t* __restrict__ ord, const double* __r
     q_sp += (sp.lo[k] + delta) * sp.v[k];
     back += sp.dd[k];
   }
-  return group_sum<GW>(lane_q) + q_sp;
+  return slv + qc + q_sp;
 }
 
-// One SAFE state on one wavefront, box of at most 64*E cells.  The box is
-// sorted with 64 lanes; then the NG lane groups take rows u = g, g+NG, ...
-template <int E, int PASS, int D>
-__device__ void sb_state(const SweepArgs& a, const SysParams& p, int64_t s, int U,
+// One group of inputs [g0, g1) of a SAFE state on one wavefront, box of at
+// most 64*E cells.  The box is sorted with 64 lanes (once per order); then
+// lane groups of GW lanes take rows u = g0 + g, g0 + g + 64/GW, ..., each lane
+// holding up to 8 of the row's window cells with their widths, values and
+// order positions.  The group's best is merged into (best0, best1, arg),
+// which hold the earlier groups' (lower inputs') best.
+template <int E, int GW, int PASS, int D>
+__device__ __forceinline__ void sb_state(const SweepArgs& a, const SysParams& p, int64_t s, int g0, int g1,
                          const StateBox& b, int lane, SbLds<64 * E>& L, double& best0,
                          double& best1, int& arg) {
-  constexpr int P = 64 * E;
-  constexpr int NG = SbShape<P>::NG, GW = SbShape<P>::GW, R = SbShape<P>::R;
+  constexpr int NG = 64 / GW, EL = kSbEntriesPerLane;
   const int d = D > 0 ? D : a.d;
   const bool mx = a.maximise != 0;
   const int64_t PB = b.P;
@@ -247,6 +342,7 @@ __device__ void sb_state(const SweepArgs& a, const SysParams& p, int64_t s, int 
       p1[e] = bi;
       if (bi < PB) {
         const double2 V = a.vin[t];
+        L.vb[bi] = V;
         const uint64_t b0 = dbits(V.x + 0.0), b1 = dbits(V.y + 0.0);
         k0[e] = mx ? ~b0 : b0;
         k1[e] = mx ? ~b1 : b1;
@@ -262,33 +358,40 @@ __device__ void sb_state(const SweepArgs& a, const SysParams& p, int64_t s, int 
         k1[e] = ~0ull;
       }
     }
-    bitonic_sort2<E>(k0, p0, k1, p1, lane);
+    if constexpr (E >= 8) {
+      // one order at a time: half the registers of the paired network
+      bitonic_sort1<E>(k0, p0, lane);
+      bitonic_sort1<E>(k1, p1, lane);
+    } else {
+      bitonic_sort2<E>(k0, p0, k1, p1, lane);
+    }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int j = lane * E + e;
-      L.ord[0][j] = p0[e];
-      L.ord[1][j] = p1[e];
-      L.val[0][j] = p0[e] < PB ? bitsd(mx ? ~k0[e] : k0[e]) : 0.0;
-      L.val[1][j] = p1[e] < PB ? bitsd(mx ? ~k1[e] : k1[e]) : 0.0;
+      if (p0[e] < PB) L.rk[0][p0[e]] = (uint16_t)j;
+      if (p1[e] < PB) L.rk[1][p1[e]] = (uint16_t)j;
     }
   }
   wave_lds_sync();
 
   const int g = lane / GW, gl = lane % GW;
-  double2* stg = L.stg[g];
   const double tail_v = mx ? 1.0 : 0.0;
   const double worst = a.reach ? -1.0 : 2.0;
-  double g0 = worst, g1 = worst;
+  double gb0 = worst, gb1 = worst;
   int garg = 0x7fffffff;
-  for (int ui0 = 0; ui0 < U; ui0 += NG) {
+  for (int ui0 = g0; ui0 < g1; ui0 += NG) {
     const int ui = ui0 + g;
-    const bool act = ui < U;
+    const bool act = ui < g1;
+    double dd[EL];
+    uint32_t pk[EL];
+    double lane_lo = 0.0, lq0 = 0.0, lq1 = 0.0;
 #pragma unroll
-    for (int k = 0; k < R; ++k) stg[gl * R + k] = make_double2(0.0, 0.0);
-    wave_lds_sync();
+    for (int k = 0; k < EL; ++k) {
+      dd[k] = 0.0;
+      pk[k] = kNoEntry;
+    }
     int u = 0;
     int64_t row = 0;
-    double lane_lo = 0.0;
     if (act) {
       u = row_input<PASS>(a, s, ui);
       row = s * a.nu + u;
@@ -304,41 +407,48 @@ __device__ void sb_state(const SweepArgs& a, const SysParams& p, int64_t s, int 
           fo[i] = tot;
           tot += W[i];
         }
-        int64_t r0 = gl, r1 = GW;
+        int64_t q0i = gl, q1i = GW;
         IMPACT_FOR_DIMS_REV(i, d) {
-          j[i] = (int32_t)(r0 % W[i]);
-          r0 /= W[i];
-          inc[i] = (int32_t)(r1 % W[i]);
-          r1 /= W[i];
+          j[i] = (int32_t)(q0i % W[i]);
+          q0i /= W[i];
+          inc[i] = (int32_t)(q1i % W[i]);
+          q1i /= W[i];
         }
         const double2* fr = a.fac ? a.fac + row * (int64_t)a.fs : nullptr;
-        for (int slot = gl; slot < nw; slot += GW) {
-          int bi = 0;
-          IMPACT_FOR_DIMS(i, d) bi += (off[i] + j[i]) * b.bstride[i];
-          double2 e;
-          if (a.storage == IMPACT_STORE_FACTORS) {
-            double lo = 1.0, hi = 1.0;
-            IMPACT_FOR_DIMS(i, d) {
-              const double2 fv = fr[fo[i] + j[i]];
-              lo *= fv.x;
-              hi *= fv.y;
+#pragma unroll
+        for (int k = 0; k < EL; ++k) {
+          const int slot = gl + k * GW;
+          if (slot < nw) {
+            int bi = 0;
+            IMPACT_FOR_DIMS(i, d) bi += (off[i] + j[i]) * b.bstride[i];
+            double2 e;
+            if (a.storage == IMPACT_STORE_FACTORS) {
+              double lo = 1.0, hi = 1.0;
+              IMPACT_FOR_DIMS(i, d) {
+                const double2 fv = fr[fo[i] + j[i]];
+                lo *= fv.x;
+                hi *= fv.y;
+              }
+              e = make_double2(lo, hi);
+            } else {
+              e = a.ent[base + slot];
             }
-            e = make_double2(lo, hi);
-          } else {
-            e = a.ent[base + slot];
-          }
-          stg[bi] = e;
-          lane_lo += e.x;
-          int carry = 0;
-          IMPACT_FOR_DIMS_REV(i, d) {
-            j[i] += inc[i] + carry;
-            carry = j[i] >= W[i];
-            if (carry) j[i] -= W[i];
+            const double2 V = L.vb[bi];
+            dd[k] = e.y - e.x;
+            pk[k] = (uint32_t)L.rk[0][bi] | ((uint32_t)L.rk[1][bi] << 10) | ((uint32_t)bi << 20);
+            lane_lo += e.x;
+            lq0 += e.x * V.x;
+            lq1 += e.x * V.y;
+            int carry = 0;
+            IMPACT_FOR_DIMS_REV(i, d) {
+              j[i] += inc[i] + carry;
+              carry = j[i] >= W[i];
+              if (carry) j[i] -= W[i];
+            }
           }
         }
       }
     }
-    wave_lds_sync();
     if (act) {
       const double4 o = a.ot[row];
       Specials sp;
@@ -353,88 +463,69 @@ __device__ void sb_state(const SweepArgs& a, const SysParams& p, int64_t s, int 
       if (a.windowed) slo += o.z;
       double r = 1.0 - slo;
       if (r < 0.0) r = 0.0;
-      const double q0 = sb_lp_group<R, GW>(L.ord[0], L.val[0], stg, PB, r, mx, sp, gl);
-      const double q1 = sb_lp_group<R, GW>(L.ord[1], L.val[1], stg, PB, r, mx, sp, gl);
+      const double s0 = group_sum<GW>(lq0), s1 = group_sum<GW>(lq1);
+      const double q0 = sb_row_lp<EL, GW, 64 * E>(dd, pk, 0, L, (int)PB, r, s0, mx, sp);
+      const double q1 = sb_row_lp<EL, GW, 64 * E>(dd, pk, 1, L, (int)PB, r, s1, mx, sp);
       // rows of a group come in increasing u: a strict improvement keeps the lowest u
-      if (a.reach ? (q0 > g0) : (q0 < g0)) {
-        g0 = q0;
+      if (a.reach ? (q0 > gb0) : (q0 < gb0)) {
+        gb0 = q0;
         garg = u;
       }
-      if (a.reach ? (q1 > g1) : (q1 < g1)) g1 = q1;
+      if (a.reach ? (q1 > gb1) : (q1 < gb1)) gb1 = q1;
     }
-    wave_lds_sync();
   }
   // combine the lane groups: best value, lowest input on exact ties
 #pragma unroll
   for (int off = GW; off < 64; off <<= 1) {
-    const double o0 = __shfl_xor(g0, off), o1 = __shfl_xor(g1, off);
+    const double o0 = __shfl_xor(gb0, off), o1 = __shfl_xor(gb1, off);
     const int oa = __shfl_xor(garg, off);
-    const bool better = a.reach ? (o0 > g0 || (o0 == g0 && oa < garg))
-                                : (o0 < g0 || (o0 == g0 && oa < garg));
+    const bool better = a.reach ? (o0 > gb0 || (o0 == gb0 && oa < garg))
+                                : (o0 < gb0 || (o0 == gb0 && oa < garg));
     if (better) {
-      g0 = o0;
+      gb0 = o0;
       garg = oa;
     }
-    g1 = a.reach ? fmax(g1, o1) : fmin(g1, o1);
+    gb1 = a.reach ? fmax(gb1, o1) : fmin(gb1, o1);
   }
-  best0 = g0;
-  best1 = g1;
-  arg = garg;
+  // earlier groups hold lower inputs: a strict improvement is needed to replace them
+  if (a.reach ? (gb0 > best0) : (gb0 < best0)) {
+    best0 = gb0;
+    arg = garg;
+  }
+  best1 = a.reach ? fmax(best1, gb1) : fmin(best1, gb1);
 }
 
-// ESB: per-lane element count of the largest state box handled by the box
-// path (box <= 64 * ESB cells); EROW > 0: per-lane count of the per-row
-// fallback for states whose box is larger (rows <= 64 * EROW entries).
 // Sweep update of one SAFE state s on one wavefront: writes vout[s] (and
-// pi[s] in the policy pass); returns the state's V1 - V0 (>= 0).
-template <int ESB, int EROW, int PASS, int D>
-__device__ double sb_sweep_state(const SweepArgs& a, int64_t s, int lane, SbLds<64 * ESB>& L) {
+// pi[s] in the policy pass); returns the state's V1 - V0 (>= 0).  The inputs
+// are taken in consecutive groups whose windows' box holds at most 64 * ESB
+// cells (one sort per group); a single row always fits, because the state-box
+// kernels run only on abstractions whose rows have at most 512 entries and
+// ESB is 8 unless every state's whole box fits.
+template <int ESB, int GW, int PASS, int D>
+__device__ __forceinline__ double sb_sweep_state(const SweepArgs& a, int64_t s, int lane,
+                                                SbLds<64 * ESB>& L) {
   const SysParams& p = *a.sys;
   const int U = PASS == 0 ? a.nu : 1;
-  StateBox b;
-  state_box<PASS, D>(a, s, U, lane, b);
-  double best0 = 0.0, best1 = 0.0;
-  int arg = 0;
-  if (b.P <= 64 * ESB) {
+  const double worst = a.reach ? -1.0 : 2.0;
+  double best0 = worst, best1 = worst;
+  int arg = 0x7fffffff;
+  for (int g0 = 0; g0 < U;) {
+    StateBox b;
+    const int g1 = uniform_i32(group_box<PASS, D>(a, s, g0, U, 64 * ESB, lane, b));
     if (ESB == 1 || b.P <= 64)
-      sb_state<1, PASS, D>(a, p, s, U, b, lane, *(SbLds<64>*)&L, best0, best1, arg);
+      sb_state<1, GW, PASS, D>(a, p, s, g0, g1, b, lane, *(SbLds<64>*)&L, best0, best1, arg);
     else if (ESB == 2 || b.P <= 128)
-      sb_state<(ESB < 2 ? ESB : 2), PASS, D>(a, p, s, U, b, lane,
-                                          *(SbLds<64 * (ESB < 2 ? ESB : 2)>*)&L, best0, best1,
-                                          arg);
+      sb_state<(ESB < 2 ? ESB : 2), GW, PASS, D>(a, p, s, g0, g1, b, lane,
+                                              *(SbLds<64 * (ESB < 2 ? ESB : 2)>*)&L, best0,
+                                              best1, arg);
     else if (ESB == 4 || b.P <= 256)
-      sb_state<(ESB < 4 ? ESB : 4), PASS, D>(a, p, s, U, b, lane,
-                                          *(SbLds<64 * (ESB < 4 ? ESB : 4)>*)&L, best0, best1,
-                                          arg);
+      sb_state<(ESB < 4 ? ESB : 4), GW, PASS, D>(a, p, s, g0, g1, b, lane,
+                                              *(SbLds<64 * (ESB < 4 ? ESB : 4)>*)&L, best0,
+                                              best1, arg);
     else
-      sb_state<ESB, PASS, D>(a, p, s, U, b, lane, L, best0, best1, arg);
-  } else if constexpr (EROW > 0) {
-    const int extra = 1 + a.windowed;
-    for (int ui = 0; ui < U; ++ui) {
-      const int u = row_input<PASS>(a, s, ui);
-      const int64_t row = s * a.nu + u;
-      const int n = (int)(a.row_off[row + 1] - a.row_off[row]) + extra;
-      double q0, q1;
-      if (EROW == 1 || n <= 64)
-        solve_row<1, 1, 0>(a, p, row, lane, nullptr, nullptr, q0, q1);
-      else if (EROW == 2 || n <= 128)
-        solve_row<(EROW < 2 ? EROW : 2), 1, 0>(a, p, row, lane, nullptr, nullptr, q0, q1);
-      else if (EROW == 4 || n <= 256)
-        solve_row<(EROW < 4 ? EROW : 4), 1, 0>(a, p, row, lane, nullptr, nullptr, q0, q1);
-      else
-        solve_row<EROW, 1, 0>(a, p, row, lane, nullptr, nullptr, q0, q1);
-      if (ui == 0) {
-        best0 = q0;
-        best1 = q1;
-        arg = u;
-      } else {
-        if (a.reach ? (q0 > best0) : (q0 < best0)) {
-          best0 = q0;
-          arg = u;
-        }
-        if (a.reach ? (q1 > best1) : (q1 < best1)) best1 = q1;
-      }
-    }
+      sb_state<ESB, GW, PASS, D>(a, p, s, g0, g1, b, lane, L, best0, best1, arg);
+    g0 = g1;
+    wave_lds_sync();
   }
   if (lane == 0) {
     a.vout[s] = make_double2(best0, best1);
@@ -444,7 +535,7 @@ __device__ double sb_sweep_state(const SweepArgs& a, int64_t s, int lane, SbLds<
   return gap > 0.0 ? gap : 0.0;
 }
 
-template <int ESB, int EROW, int PASS, int D>
+template <int ESB, int GW, int PASS, int D>
 __global__ __launch_bounds__(64 * kSbWaves) void k_sweep_sb(SweepArgs a) {
   if (a.ctrl->done) return;
   __shared__ SbLds<64 * ESB> lds[kSbWaves];
@@ -454,7 +545,7 @@ __global__ __launch_bounds__(64 * kSbWaves) void k_sweep_sb(SweepArgs a) {
   double gap = 0.0;
   if (si < a.n_safe) {
     const int64_t s = uniform_i64(a.safe[si]);
-    gap = sb_sweep_state<ESB, EROW, PASS, D>(a, s, lane, lds[wv]);
+    gap = sb_sweep_state<ESB, GW, PASS, D>(a, s, lane, lds[wv]);
   }
   if (lane == 0) gapw[wv] = gap;
   __syncthreads();
@@ -481,33 +572,9 @@ __device__ __forceinline__ void mq_close_state(const QueryDesc& D, int64_t step,
   }
 }
 
-// The state-box update of one item, specialised on its grid dimension when
-// the kernel has no per-row fallback (EROW == 0).
-template <int ESB, int EROW, int PASS>
-__device__ double mq_sb_pass(const SweepArgs& a, int d, int64_t s, int lane,
-                             SbLds<64 * ESB>& L) {
-  if constexpr (EROW == 0) {
-    switch (d) {
-      case 2: return sb_sweep_state<ESB, 0, PASS, 2>(a, s, lane, L);
-      case 3: return sb_sweep_state<ESB, 0, PASS, 3>(a, s, lane, L);
-      case 5: return sb_sweep_state<ESB, 0, PASS, 5>(a, s, lane, L);
-      default: return sb_sweep_state<ESB, 0, PASS, 0>(a, s, lane, L);
-    }
-  } else {
-    return sb_sweep_state<ESB, EROW, PASS, 0>(a, s, lane, L);
-  }
-}
-
-template <int ESB, int EROW>
-__device__ double mq_sb_dispatch(const SweepArgs& a, int d, bool policy_pass, int64_t s,
-                                 int lane, SbLds<64 * ESB>& L) {
-  return policy_pass ? mq_sb_pass<ESB, EROW, 0>(a, d, s, lane, L)
-                     : mq_sb_pass<ESB, EROW, 1>(a, d, s, lane, L);
-}
-
 // Multi-query state-box sweep: one wavefront per (query, SAFE state) item,
 // each query at its own phase and step.
-template <int ESB, int EROW>
+template <int ESB, int GW, int DIM>
 __global__ __launch_bounds__(64 * kSbWaves) void k_mq_sweep_sb(
     const QueryDesc* __restrict__ desc, const QueryCtrl* __restrict__ ctrl,
     const int32_t* __restrict__ wq, const int32_t* __restrict__ ws, int64_t n_items,
@@ -529,7 +596,8 @@ __global__ __launch_bounds__(64 * kSbWaves) void k_mq_sweep_sb(
     a.reach = !D.safety;
     a.pass = phase == 0 ? 0 : 1;
     a.maximise = phase == 0 ? D.safety : !D.safety;
-    g = mq_sb_dispatch<ESB, EROW>(a, uniform_i32(a.d), phase == 0, s, lane, lds[wv]);
+    g = phase == 0 ? sb_sweep_state<ESB, GW, 0, DIM>(a, s, lane, lds[wv])
+                   : sb_sweep_state<ESB, GW, 1, DIM>(a, s, lane, lds[wv]);
   } else if ((phase == 1 || phase == 3) && lane == 0) {
     mq_close_state(D, step, phase, s);
   }
@@ -540,66 +608,79 @@ static inline int lanes_elems(int64_t n) {
   return n <= 64 ? 1 : n <= 128 ? 2 : n <= 256 ? 4 : n <= 512 ? 8 : 0;
 }
 
+// Kernel variant for a largest state box of max_box cells (boxes beyond 512
+// cells are split into input groups by the 512-cell variants) and rows of at
+// most max_row entries (at most 512; a row's cells go to 16, 32 or 64 lanes,
+// 8 per lane).  Returns the element count and lane-group width through eb/gw.
+static inline bool sb_variant(int64_t max_box, int32_t max_row, int& eb, int& gw) {
+  if (max_row > 512) return false;
+  gw = max_row <= 128 ? 16 : max_row <= 256 ? 32 : 64;
+  eb = lanes_elems(max_box < 512 ? max_box : 512);
+  const int need = gw == 16 ? 1 : gw == 32 ? 2 : 4;  // the box holds a whole row
+  if (eb < need) eb = need;
+  return true;
+}
+
+#define IMPACT_SB_SWITCH(LAUNCH)                    \
+  switch (gw * 16 + eb) {                           \
+    case 16 * 16 + 1: LAUNCH(1, 16); break;         \
+    case 16 * 16 + 2: LAUNCH(2, 16); break;         \
+    case 16 * 16 + 4: LAUNCH(4, 16); break;         \
+    case 16 * 16 + 8: LAUNCH(8, 16); break;         \
+    case 32 * 16 + 2: LAUNCH(2, 32); break;         \
+    case 32 * 16 + 4: LAUNCH(4, 32); break;         \
+    case 32 * 16 + 8: LAUNCH(8, 32); break;         \
+    case 64 * 16 + 4: LAUNCH(4, 64); break;         \
+    default: LAUNCH(8, 64); break;                  \
+  }
+
 template <int PASS>
 static hipError_t launch_sb_pass(const SweepArgs& a, int64_t max_box, int32_t max_row,
                                  hipStream_t st) {
+  int eb = 0, gw = 0;
+  if (!sb_variant(max_box, max_row, eb, gw)) return hipErrorInvalidValue;
   const int64_t blocks = (a.n_safe + kSbWaves - 1) / kSbWaves;
   const dim3 g((unsigned)blocks), bl(64 * kSbWaves);
-  const int er = lanes_elems(max_row);
-  if (er == 0) return hipErrorInvalidValue;
-  const int eb = lanes_elems(max_box);
-#define SB(E1, E2, D) hipLaunchKernelGGL((k_sweep_sb<E1, E2, PASS, D>), g, bl, 0, st, a)
-#define SBD(E1)                       \
-  switch (a.d) {                      \
-    case 2: SB(E1, 0, 2); break;      \
-    case 3: SB(E1, 0, 3); break;      \
-    case 5: SB(E1, 0, 5); break;      \
-    default: SB(E1, 0, 0); break;     \
+#define SB(E1, G1, D) hipLaunchKernelGGL((k_sweep_sb<E1, G1, PASS, D>), g, bl, 0, st, a)
+#define SBD(E1, G1)                \
+  switch (a.d) {                   \
+    case 2: SB(E1, G1, 2); break;  \
+    case 3: SB(E1, G1, 3); break;  \
+    case 5: SB(E1, G1, 5); break;  \
+    default: SB(E1, G1, 0); break; \
   }
-  switch (eb) {
-    case 1: SBD(1); break;
-    case 2: SBD(2); break;
-    case 4: SBD(4); break;
-    case 8: SBD(8); break;
-    default:  // some boxes exceed 512 cells: per-row sorts for those states
-      switch (er) {
-        case 1: SB(8, 1, 0); break;
-        case 2: SB(8, 2, 0); break;
-        case 4: SB(8, 4, 0); break;
-        default: SB(8, 8, 0); break;
-      }
-  }
+  IMPACT_SB_SWITCH(SBD)
 #undef SBD
 #undef SB
   return hipGetLastError();
 }
 
+// Every item's query has grid dimension d when d is 2, 3 or 5 (kernels
+// specialised on it); any other d runs the generic variant.
 hipError_t launch_mq_sweep_sb(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
                               const int32_t* ws, int64_t n_items, double* gap_item,
-                              int64_t max_box, int32_t max_row, hipStream_t st) {
+                              int64_t max_box, int32_t max_row, int32_t d, hipStream_t st) {
   if (n_items == 0) return hipSuccess;
+  int eb = 0, gw = 0;
+  if (!sb_variant(max_box, max_row, eb, gw)) return hipErrorInvalidValue;
   const dim3 g((unsigned)((n_items + kSbWaves - 1) / kSbWaves)), bl(64 * kSbWaves);
-  const int er = lanes_elems(max_row);
-  if (er == 0) return hipErrorInvalidValue;
-  const int eb = lanes_elems(max_box);
-#define MQ(E1, E2) \
-  hipLaunchKernelGGL((k_mq_sweep_sb<E1, E2>), g, bl, 0, st, desc, ctrl, wq, ws, n_items, gap_item)
-  switch (eb) {
-    case 1: MQ(1, 0); break;
-    case 2: MQ(2, 0); break;
-    case 4: MQ(4, 0); break;
-    case 8: MQ(8, 0); break;
-    default:
-      switch (er) {
-        case 1: MQ(8, 1); break;
-        case 2: MQ(8, 2); break;
-        case 4: MQ(8, 4); break;
-        default: MQ(8, 8); break;
-      }
+#define MQ(E1, G1, D)                                                                \
+  hipLaunchKernelGGL((k_mq_sweep_sb<E1, G1, D>), g, bl, 0, st, desc, ctrl, wq, ws, \
+                     n_items, gap_item)
+#define MQD(E1, G1)                \
+  switch (d) {                     \
+    case 2: MQ(E1, G1, 2); break;  \
+    case 3: MQ(E1, G1, 3); break;  \
+    case 5: MQ(E1, G1, 5); break;  \
+    default: MQ(E1, G1, 0); break; \
   }
+  IMPACT_SB_SWITCH(MQD)
+#undef MQD
 #undef MQ
   return hipGetLastError();
 }
+
+#undef IMPACT_SB_SWITCH
 
 hipError_t launch_sweep_sb(const SweepArgs& a, int64_t max_box, int32_t max_row, hipStream_t st) {
   if (a.n_safe == 0) return hipSuccess;
