@@ -190,6 +190,16 @@ def cpu_baseline(system, spec, budget_s=25.0):
     }
 
 
+def _progress(label, every):
+    state = {"last": 0}
+
+    def cb(n, total):
+        if n - state["last"] >= every or n == total:
+            state["last"] = n
+            print(f"# {label}: {n}/{total}", file=sys.stderr, flush=True)
+    return cb
+
+
 def run_batched(args, tuner):
     """Batched form vs a per-instance plain loop, same instances, eps and sweep cap."""
     import numpy as np
@@ -213,7 +223,15 @@ def run_batched(args, tuner):
     views = impact.build_imdp_batch(systems, storage=storage)
     eng = impact.Engine(max_queries=len(views))
     ids = [eng.submit(v, sp) for v, sp in zip(views, specs)]
-    res = eng.run_all(chunk=chunk)
+    res = {}
+    t_print = time.perf_counter()
+    while len(res) < len(ids):
+        eng.run(chunk)
+        for r in eng.poll():
+            res[r["id"]] = r
+        if time.perf_counter() - t_print > 15:
+            t_print = time.perf_counter()
+            print(f"# batched engine: {len(res)}/{len(ids)} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
     eng.free()
@@ -222,9 +240,11 @@ def run_batched(args, tuner):
     t0 = time.perf_counter()
     worst = 0.0
     plain_updates = 0
+    prog = _progress("plain loop", 32)
     for k, (system, sp) in enumerate(zip(systems, specs)):
         im = impact.build_imdp(system, storage=storage)
         r = im.iterate(sp)
+        prog(k + 1, len(systems))
         plain_updates += sum(r["info"]["updates"])
         b = res[ids[k]]
         worst = max(worst, float((r["lo"] - b["lo"]).abs().max()),
@@ -267,14 +287,14 @@ def run_served(args):
     # both legs start from an empty cache of the same budget
     cache = serve.AbstractionCache(pool, budget, storage="factors")
     srv = serve.Server(cache, max_active=64, steps=8)
-    done, st = srv.run(trace)
+    done, st = srv.run(trace, progress=_progress("served", 25))
     srv.free()
     served = serve.latency_stats(done, st["makespan"])
     served.update(peak_active=st["peak_active"], cache=cache.stats())
     cache.clear()
     print(f"# served: {served}", file=sys.stderr, flush=True)
     cache = serve.AbstractionCache(pool, budget, storage="factors")
-    sdone, sst = serve.serve_serial(cache, trace)
+    sdone, sst = serve.serve_serial(cache, trace, progress=_progress("serial", 25))
     serial = serve.latency_stats(sdone, sst["makespan"])
     serial.update(cache=cache.stats())
     cache.clear()

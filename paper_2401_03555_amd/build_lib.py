@@ -13,7 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libimpact.so")
-SOURCES = ["abi.hip", "build.hip", "sweep.hip", "sweep_sb.hip", "mq.hip"]
+SOURCES = ["sweep_sb_d3.hip", "sweep_sb_d2.hip", "sweep_sb_d5.hip", "sweep_sb_d0.hip",
+           "sweep.hip", "abi.hip", "build.hip", "sweep_sb.hip", "mq.hip"]
 
 
 def hipcc() -> str:

@@ -98,12 +98,14 @@ int mq_fail(int code, const std::string& m) {
 struct MqNoMem {};
 
 // Kernel classes of the engine: the queries of one class share a launch of
-// the kernel variant sized for them.  State-box classes by grid dimension
-// (2, 3, 5, other) and the per-lane element count of their largest state box
-// (1, 2, 4, 8; boxes beyond 512 cells are split into input groups by the 8
-// classes), and workgroup classes for rows beyond 512 entries (by the longest
-// row).
-constexpr int kMqBoxClasses = 16;
+// the kernel variant sized for them, the same variant a single query of that
+// abstraction runs.  Wavefront classes by grid dimension (2, 3, 5, other),
+// the per-lane element count of the largest state box (1, 2, 4, 8; boxes
+// beyond 512 cells are split into input groups) and the lane-group width of
+// the longest row (16, 32, 64): the policy pass runs the state-box kernel,
+// the fixed-input pass the per-row kernel.  Workgroup classes for rows beyond
+// 512 entries (by the longest row).
+constexpr int kMqBoxClasses = 4 * 4 * 3;
 constexpr int kMqClasses = kMqBoxClasses + 3;
 constexpr int kMqDims[4] = {2, 3, 5, 0};
 
@@ -241,7 +243,10 @@ void ensure(impact_mq* m, T*& p, int64_t& cap, int64_t need) {
 int class_of(const MqQuery& q) {
   if (q.box_class) {
     const int ds = q.d == 2 ? 0 : q.d == 3 ? 1 : q.d == 5 ? 2 : 3;
-    return 4 * ds + elems_slot(elems_for(std::min<int64_t>(q.max_box, 512)));
+    const int gs = q.max_row <= 128 ? 0 : q.max_row <= 256 ? 1 : 2;
+    int eb = elems_for(std::min<int64_t>(q.max_box, 512));
+    eb = std::max(eb, gs == 0 ? 1 : gs == 1 ? 2 : 4);  // the box holds a whole row
+    return (ds * 4 + elems_slot(eb)) * 3 + gs;
   }
   return kMqBoxClasses + (q.max_row <= 1024 ? 0 : q.max_row <= 2048 ? 1 : 2);
 }
@@ -308,10 +313,13 @@ void enqueue_step(impact_mq* m) {
   for (int c = 0; c < kMqClasses; ++c) {
     const MqClass& k = m->cls[c];
     if (k.n == 0) continue;
-    if (k.box)
+    if (k.box) {
+      const int d = kMqDims[c / 12];
       MQ_TRY(launch_mq_sweep_sb(m->d_desc, m->d_ctrl, m->wq + k.begin, m->ws + k.begin, k.n,
-                                m->gap + k.begin, k.max_box, k.max_row, kMqDims[c / 4], m->st));
-    else
+                                m->gap + k.begin, k.max_box, k.max_row, d, m->st));
+      MQ_TRY(launch_mq_sweep_row(m->d_desc, m->d_ctrl, m->wq + k.begin, m->ws + k.begin, k.n,
+                                 m->gap + k.begin, k.max_row, d, m->st));
+    } else
       MQ_TRY(launch_mq_sweep_block(m->d_desc, m->d_ctrl, m->wq + k.begin, m->ws + k.begin, k.n,
                                    m->gap + k.begin, k.max_row, m->st));
   }

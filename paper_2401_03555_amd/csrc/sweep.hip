@@ -135,6 +135,79 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
   }
 }
 
+// Multi-query fixed-input pass for queries whose rows fit a wavefront: one
+// wavefront per (query, SAFE state) item in the fixed-input phase (others are
+// left to k_mq_sweep_sb), the row of the policy's input solved like the
+// single-query per-row sweep does (element count by the row's own length, up
+// to WAVE_E).
+template <int WAVE_E, int DIM>
+__global__ __launch_bounds__(kBlock) void k_mq_sweep_row(
+    const QueryDesc* __restrict__ desc, const QueryCtrl* __restrict__ ctrl,
+    const int32_t* __restrict__ wq, const int32_t* __restrict__ ws, int64_t n_items,
+    double* __restrict__ gap_item) {
+  const int lane = threadIdx.x & 63, wv = uniform_i32(threadIdx.x >> 6);
+  const int64_t item = (int64_t)blockIdx.x * kWaves + wv;
+  if (item >= n_items) return;
+  const int q = uniform_i32(wq[item]);
+  if (uniform_i32(ctrl[q].phase) != 2) return;
+  const int64_t s = uniform_i32(ws[item]);
+  const int64_t step = uniform_i64(ctrl[q].step);
+  const QueryDesc& D = desc[q];
+  SweepArgs a = D.a;
+  a.vin = (step & 1) ? D.vb1 : D.vb0;
+  a.vout = (step & 1) ? D.vb0 : D.vb1;
+  a.reach = !D.safety;
+  a.pass = 1;
+  a.maximise = !D.safety;
+  const SysParams& p = *a.sys;
+  const int64_t row = s * a.nu + a.pi[s];
+  const int n = (int)(a.row_off[row + 1] - a.row_off[row]) + 1 + a.windowed;
+  double q0, q1;
+  if (WAVE_E == 1 || n <= 64)
+    solve_row<1, 1, DIM>(a, p, row, lane, nullptr, nullptr, q0, q1);
+  else if (WAVE_E == 2 || n <= 128)
+    solve_row<(WAVE_E < 2 ? WAVE_E : 2), 1, DIM>(a, p, row, lane, nullptr, nullptr, q0, q1);
+  else if (WAVE_E == 4 || n <= 256)
+    solve_row<(WAVE_E < 4 ? WAVE_E : 4), 1, DIM>(a, p, row, lane, nullptr, nullptr, q0, q1);
+  else
+    solve_row<WAVE_E, 1, DIM>(a, p, row, lane, nullptr, nullptr, q0, q1);
+  if (lane == 0) {
+    a.vout[s] = make_double2(q0, q1);
+    const double g = q1 - q0;
+    gap_item[item] = g > 0.0 ? g : 0.0;
+  }
+}
+
+hipError_t launch_mq_sweep_row(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
+                               const int32_t* ws, int64_t n_items, double* gap_item,
+                               int32_t max_row, int32_t d, hipStream_t st) {
+  if (n_items == 0) return hipSuccess;
+  if (max_row > 512) return hipErrorInvalidValue;
+  const dim3 g((unsigned)((n_items + kWaves - 1) / kWaves)), b(kBlock);
+#define MR(E1, D)                                                                           \
+  hipLaunchKernelGGL((k_mq_sweep_row<E1, D>), g, b, 0, st, desc, ctrl, wq, ws, n_items, \
+                     gap_item)
+#define MRD(E1)                \
+  switch (d) {                 \
+    case 2: MR(E1, 2); break;  \
+    case 3: MR(E1, 3); break;  \
+    case 5: MR(E1, 5); break;  \
+    default: MR(E1, 0); break; \
+  }
+  if (max_row <= 64) {
+    MRD(1)
+  } else if (max_row <= 128) {
+    MRD(2)
+  } else if (max_row <= 256) {
+    MRD(4)
+  } else {
+    MRD(8)
+  }
+#undef MRD
+#undef MR
+  return hipGetLastError();
+}
+
 // Multi-query workgroup sweep for long rows: one workgroup per (query, SAFE
 // state) item, each query at its own phase and step.
 template <int WAVE_E, int BLOCK_E>

@@ -236,7 +236,9 @@ __device__ __forceinline__ void intra_stages(uint64_t (&key)[E], V (&val)[E], in
 template <int E, int NW, class V>
 __device__ void bitonic_sort(uint64_t (&key)[E], V (&val)[E], int tid, uint64_t* xk) {
   constexpr int P = 64 * NW * E;
+#pragma unroll
   for (int k = 2; k <= P; k <<= 1) {
+#pragma unroll
     for (int j = k >> 1; j >= E; j >>= 1) {
       const int tm = j / E;  // partner thread = tid ^ tm
       const bool lower = (tid & tm) == 0;

@@ -114,8 +114,11 @@ class Server:
         self.steps = steps
         self.engine = impact.Engine(max_queries=max_active)
 
-    def run(self, trace, keep_outputs=False):
-        """Serve ``trace`` (dicts with arrival ``t`` in seconds, ``key``, ``spec``)."""
+    def run(self, trace, keep_outputs=False, progress=None):
+        """Serve ``trace`` (dicts with arrival ``t`` in seconds, ``key``, ``spec``).
+
+        ``progress(n_done, n_total)`` is called after every engine run that
+        completes requests."""
         t0 = time.perf_counter()
         i, queue, active, done = 0, collections.deque(), {}, []
         query_bytes = 0
@@ -151,6 +154,8 @@ class Server:
                     if keep_outputs:
                         rec.update(lo=r["lo"], hi=r["hi"], policy=r["policy"])
                     done.append(rec)
+                    if progress:
+                        progress(len(done), len(trace))
             elif i < len(trace):
                 time.sleep(max(0.0, trace[i]["t"] - (time.perf_counter() - t0)))
         makespan = time.perf_counter() - t0
@@ -161,7 +166,7 @@ class Server:
         self.engine.free()
 
 
-def serve_serial(cache, trace, keep_outputs=False):
+def serve_serial(cache, trace, keep_outputs=False, progress=None):
     """Baseline: one request at a time with the plain single-query call."""
     t0 = time.perf_counter()
     done = []
@@ -179,6 +184,8 @@ def serve_serial(cache, trace, keep_outputs=False):
         if keep_outputs:
             rec.update(lo=r["lo"], hi=r["hi"], policy=r["policy"])
         done.append(rec)
+        if progress:
+            progress(len(done), len(trace))
     return done, dict(makespan=time.perf_counter() - t0)
 
 

@@ -1,9 +1,10 @@
 """GPU tests of the multi-query engine (batched and served forms).
 
 A query run by the engine must equal the same query run alone by
-impact_interval_iterate with the same sweep kernels (bitwise), must not depend
-on which other queries share its launches (bitwise), and must match the CPU
-oracle at the parity tolerances.
+impact_interval_iterate with the same sweep kernels (bitwise: the engine runs
+the state-box kernel for the policy pass and the per-row kernel for the
+fixed-input pass), must not depend on which other queries share its launches
+(bitwise), and must match the CPU oracle at the parity tolerances.
 """
 import numpy as np
 import pytest
@@ -22,6 +23,11 @@ def I():
     from paper_2401_03555_amd import impact
     impact.lib()
     return impact
+
+
+def _engine_modes(imdp):
+    imdp.set_sweep_modes("state_box", "per_row")
+    return imdp
 
 
 def _np(r):
@@ -67,7 +73,7 @@ CASES = [
 @pytest.mark.parametrize("name,make,spec", CASES, ids=[c[0] for c in CASES])
 def test_engine_query_equals_plain_iterate(I, name, make, spec):
     system = make()
-    imdp = I.build_imdp(system, sweep_mode="state_box")
+    imdp = _engine_modes(I.build_imdp(system))
     plain = imdp.iterate(spec)
     eng = I.Engine(max_queries=4)
     qid = eng.submit(imdp, spec)
@@ -130,7 +136,7 @@ def test_engine_matches_oracle_on_batched_instances(I):
 
 def test_engine_reuses_slots_and_handles_degenerate_queries(I):
     system = _affine2()
-    imdp = I.build_imdp(system, sweep_mode="state_box")
+    imdp = _engine_modes(I.build_imdp(system))
     spec = CASES[0][2]
     ref = imdp.iterate(spec)
     eng = I.Engine(max_queries=2)
