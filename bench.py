@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--forms", default="", help="comma list of: batched, served")
     ap.add_argument("--instances", type=int, default=384)
     ap.add_argument("--batch-max-sweeps", type=int, default=1000)
+    ap.add_argument("--batch-dims", default="2,3",
+                    help="keep only the seeded instances of these dimensions")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-max-sweeps", type=int, default=1000)
@@ -205,7 +207,8 @@ def run_batched(args, tuner):
     import numpy as np
     import torch
     from paper_2401_03555_amd import impact, workloads as W
-    insts = W.batched(count=args.instances)
+    dims = {int(x) for x in args.batch_dims.split(",")}
+    insts = [x for x in W.batched(count=args.instances) if len(x[0]["n"]) in dims]
     systems = [s for s, _ in insts]
     specs = [dict(spec, max_sweeps=args.batch_max_sweeps) for _, spec in insts]
     # schedule choice (untimed): storage of the batch and engine graph chunk
@@ -257,8 +260,9 @@ def run_batched(args, tuner):
     updates = sum(sum(r["info"]["updates"]) for r in res.values())
     sweeps = np.array([r["info"]["sweeps"] for r in res.values()])
     return {
-        "workload": (f"{len(systems)} seeded random 2D/3D linear instances, reach-avoid, "
-                     f"eps 1e-8, at most {args.batch_max_sweeps} sweeps per pass"),
+        "workload": (f"{len(systems)} of {args.instances} seeded random linear instances "
+                     f"(dimensions {args.batch_dims}), reach-avoid, eps 1e-8, at most "
+                     f"{args.batch_max_sweeps} sweeps per pass"),
         "instances": len(systems),
         "n_states": int(sum(i["n_states"] for i in infos)),
         "n_rows": int(sum(i["n_rows"] for i in infos)),

@@ -11,7 +11,7 @@ class _Stub:
         self.nbytes, self.log, self.freed = nbytes, log, False
 
     def info(self):
-        return dict(device_bytes=self.nbytes, n_states=10)
+        return dict(device_bytes=self.nbytes, n_states=10, n_entries=self.nbytes * 4)
 
     def free(self):
         self.freed = True
@@ -62,6 +62,18 @@ def test_expected_size_of_unbuilt_systems(cache):
     cache.acquire("b")
     assert not cache.fits("c", extra=200)        # 200 pinned + 200 + 125 > 450
     assert cache.fits("c", extra=100)
+
+
+def test_cache_records_entries_and_lanes(cache):
+    cache.acquire("c")
+    cache.release("c")
+    assert cache.entries_of == {"c": 1200}
+    # lane choice by entries per sweep (no GPU: the class method only)
+    lane_of = serve.Server.lane_of
+    fake = type("S", (), {"BOUNDS": serve.Server.BOUNDS, "lanes": [0, 1, 2]})()
+    assert lane_of(fake, 1000) == 0
+    assert lane_of(fake, (1 << 22) + 1) == 1
+    assert lane_of(fake, 1 << 30) == 2
 
 
 def test_served_trace_shape():
