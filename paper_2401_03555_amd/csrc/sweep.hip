@@ -46,6 +46,7 @@ __device__ double block_sweep_states(const SweepArgs& a, const int32_t* __restri
   const int U = PASS == 0 ? a.nu : 1;
   const int items = nst * U;
   const int extra = 1 + a.windowed;
+  constexpr bool UN = WAVE_E < 8 && BLOCK_E == 0;
   auto row_of = [&](int m) -> int64_t {
     const int gi = m / U, ui = m - gi * U;
     const int64_t s = states[gi];
@@ -61,11 +62,11 @@ __device__ double block_sweep_states(const SweepArgs& a, const int32_t* __restri
       if (n <= 64 * WAVE_E) continue;
       double q0, q1;
       if (BLOCK_E <= 4 || n <= 1024)
-        solve_row<4, kWaves, D>(a, p, row, tid, L.red, L.xk, q0, q1);
+        solve_row<4, kWaves, D, false>(a, p, row, tid, L.red, L.xk, q0, q1);
       else if (BLOCK_E <= 8 || n <= 2048)
-        solve_row<(BLOCK_E < 8 ? BLOCK_E : 8), kWaves, D>(a, p, row, tid, L.red, L.xk, q0, q1);
+        solve_row<(BLOCK_E < 8 ? BLOCK_E : 8), kWaves, D, false>(a, p, row, tid, L.red, L.xk, q0, q1);
       else
-        solve_row<BLOCK_E, kWaves, D>(a, p, row, tid, L.red, L.xk, q0, q1);
+        solve_row<BLOCK_E, kWaves, D, false>(a, p, row, tid, L.red, L.xk, q0, q1);
       if (tid == 0) {
         L.qb0[m] = q0;
         L.qb1[m] = q1;
@@ -79,13 +80,13 @@ __device__ double block_sweep_states(const SweepArgs& a, const int32_t* __restri
     if (n > 64 * WAVE_E) continue;
     double q0, q1;
     if (WAVE_E == 1 || n <= 64)
-      solve_row<1, 1, D>(a, p, row, tid, L.red, L.xk, q0, q1);
+      solve_row<1, 1, D, UN>(a, p, row, tid, L.red, L.xk, q0, q1);
     else if (WAVE_E == 2 || n <= 128)
-      solve_row<(WAVE_E < 2 ? WAVE_E : 2), 1, D>(a, p, row, tid, L.red, L.xk, q0, q1);
+      solve_row<(WAVE_E < 2 ? WAVE_E : 2), 1, D, UN>(a, p, row, tid, L.red, L.xk, q0, q1);
     else if (WAVE_E == 4 || n <= 256)
-      solve_row<(WAVE_E < 4 ? WAVE_E : 4), 1, D>(a, p, row, tid, L.red, L.xk, q0, q1);
+      solve_row<(WAVE_E < 4 ? WAVE_E : 4), 1, D, UN>(a, p, row, tid, L.red, L.xk, q0, q1);
     else
-      solve_row<WAVE_E, 1, D>(a, p, row, tid, L.red, L.xk, q0, q1);
+      solve_row<WAVE_E, 1, D, UN>(a, p, row, tid, L.red, L.xk, q0, q1);
     if (lane == 0) {
       L.qb0[m] = q0;
       L.qb1[m] = q1;
@@ -164,13 +165,13 @@ __global__ __launch_bounds__(kBlock) void k_mq_sweep_row(
   const int n = (int)(a.row_off[row + 1] - a.row_off[row]) + 1 + a.windowed;
   double q0, q1;
   if (WAVE_E == 1 || n <= 64)
-    solve_row<1, 1, DIM>(a, p, row, lane, nullptr, nullptr, q0, q1);
+    solve_row<1, 1, DIM, (WAVE_E < 8)>(a, p, row, lane, nullptr, nullptr, q0, q1);
   else if (WAVE_E == 2 || n <= 128)
-    solve_row<(WAVE_E < 2 ? WAVE_E : 2), 1, DIM>(a, p, row, lane, nullptr, nullptr, q0, q1);
+    solve_row<(WAVE_E < 2 ? WAVE_E : 2), 1, DIM, (WAVE_E < 8)>(a, p, row, lane, nullptr, nullptr, q0, q1);
   else if (WAVE_E == 4 || n <= 256)
-    solve_row<(WAVE_E < 4 ? WAVE_E : 4), 1, DIM>(a, p, row, lane, nullptr, nullptr, q0, q1);
+    solve_row<(WAVE_E < 4 ? WAVE_E : 4), 1, DIM, (WAVE_E < 8)>(a, p, row, lane, nullptr, nullptr, q0, q1);
   else
-    solve_row<WAVE_E, 1, DIM>(a, p, row, lane, nullptr, nullptr, q0, q1);
+    solve_row<WAVE_E, 1, DIM, (WAVE_E < 8)>(a, p, row, lane, nullptr, nullptr, q0, q1);
   if (lane == 0) {
     a.vout[s] = make_double2(q0, q1);
     const double g = q1 - q0;

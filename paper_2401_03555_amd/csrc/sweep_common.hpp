@@ -233,12 +233,16 @@ __device__ __forceinline__ void intra_stages(uint64_t (&key)[E], V (&val)[E], in
 
 // Bitonic sort of P = 64 * NW * E keys, thread t holding positions
 // [t*E, t*E + E) ("blocked" layout), ascending by key; val travels along.
-template <int E, int NW, class V>
+template <int E, int NW, class V, bool UNROLL = true>
 __device__ void bitonic_sort(uint64_t (&key)[E], V (&val)[E], int tid, uint64_t* xk) {
   constexpr int P = 64 * NW * E;
-#pragma unroll
+  // fully unrolled (compile-time partner distances) up to 4 keys per thread;
+  // larger networks, and every network of a kernel that also holds the large
+  // ones (UNROLL false), keep their loops, which holds the register footprint
+  constexpr int kUnroll = (E >= 8 || !UNROLL) ? 1 : 16;
+#pragma unroll kUnroll
   for (int k = 2; k <= P; k <<= 1) {
-#pragma unroll
+#pragma unroll kUnroll
     for (int j = k >> 1; j >= E; j >>= 1) {
       const int tm = j / E;  // partner thread = tid ^ tm
       const bool lower = (tid & tm) == 0;
@@ -367,7 +371,7 @@ __device__ void load_row(const SweepArgs& a, const SysParams& p, int64_t row, in
 }
 
 // Sorting-method LP value for one value vector (v), given r = 1 - sum(lo).
-template <int E, int NW>
+template <int E, int NW, bool UNROLL = true>
 __device__ double lp_value(const RowSlice<E>& rs, const double (&v)[E], double r, bool maximise,
                            Group<NW>& g, uint64_t* xk) {
   double slv = 0.0;
@@ -382,7 +386,7 @@ __device__ double lp_value(const RowSlice<E>& rs, const double (&v)[E], double r
     key[e] = rs.pad[e] ? ~0ull : (maximise ? ~b : b);
     dk[e] = rs.dd[e];
   }
-  bitonic_sort<E, NW, double>(key, dk, g.tid, xk);
+  bitonic_sort<E, NW, double, UNROLL>(key, dk, g.tid, xk);
   double ls = 0.0;
 #pragma unroll
   for (int e = 0; e < E; ++e) ls += dk[e];
@@ -400,7 +404,7 @@ __device__ double lp_value(const RowSlice<E>& rs, const double (&v)[E], double r
   return slv + sdv;
 }
 
-template <int E, int NW, int D>
+template <int E, int NW, int D, bool UNROLL = true>
 __device__ void solve_row(const SweepArgs& a, const SysParams& p, int64_t row, int tid,
                           double* red, uint64_t* xk, double& q0, double& q1) {
   // a single-wavefront group works in lane coordinates; a workgroup group
@@ -417,8 +421,8 @@ __device__ void solve_row(const SweepArgs& a, const SysParams& p, int64_t row, i
   double r = 1.0 - slo;
   if (r < 0.0) r = 0.0;
   const bool mx = a.maximise != 0;
-  q0 = lp_value<E, NW>(rs, rs.v0, r, mx, g, xk);
-  q1 = lp_value<E, NW>(rs, rs.v1, r, mx, g, xk);
+  q0 = lp_value<E, NW, UNROLL>(rs, rs.v0, r, mx, g, xk);
+  q1 = lp_value<E, NW, UNROLL>(rs, rs.v1, r, mx, g, xk);
 }
 
 template <int PASS>

@@ -157,9 +157,12 @@ __device__ __forceinline__ double group_sum(double x) {
 template <int E>
 __device__ void bitonic_sort1(uint64_t (&ka)[E], int32_t (&pa)[E], int lane) {
   constexpr int P = 64 * E;
-#pragma unroll
+  // fully unrolled (compile-time partner distances) up to 256 keys; the
+  // 512-key network keeps its loops, which holds its register footprint
+  constexpr int kUnroll = E >= 8 ? 1 : 16;
+#pragma unroll kUnroll
   for (int k = 2; k <= P; k <<= 1) {
-#pragma unroll
+#pragma unroll kUnroll
     for (int j = k >> 1; j >= E; j >>= 1) {
       const int tm = j / E;
       const bool lower = (lane & tm) == 0;
@@ -185,9 +188,12 @@ template <int E>
 __device__ void bitonic_sort2(uint64_t (&ka)[E], int32_t (&pa)[E], uint64_t (&kb)[E],
                               int32_t (&pb)[E], int lane) {
   constexpr int P = 64 * E;
-#pragma unroll
+  // fully unrolled (compile-time partner distances) up to 256 keys; the
+  // 512-key network keeps its loops, which holds its register footprint
+  constexpr int kUnroll = E >= 8 ? 1 : 16;
+#pragma unroll kUnroll
   for (int k = 2; k <= P; k <<= 1) {
-#pragma unroll
+#pragma unroll kUnroll
     for (int j = k >> 1; j >= E; j >>= 1) {
       const int tm = j / E;
       const bool lower = (lane & tm) == 0;
@@ -215,12 +221,23 @@ __device__ void bitonic_sort2(uint64_t (&ka)[E], int32_t (&pa)[E], uint64_t (&kb
 }
 
 // Per-wavefront LDS of the state-box path (P = box capacity): each box cell's
-// (V0, V1) and its position in the two sorted orders.
+// (V0, V1) and its position in the two sorted orders; capacities of at most
+// 128 cells also get one staging array of P (width, value) pairs per lane
+// group for the scan form of the greedy (kernels of larger capacity use the
+// bisection form for every group, so their smaller groups need no staging).
 template <int P>
-struct SbLds {
+struct SbLdsCore {
   double2 vb[P];
   uint16_t rk[2][P];
+  double2 stg[P <= 128 ? 4 : 1][P <= 128 ? P + P / 8 : 1];
 };
+
+// Staging slot of order position j: one pad slot after every 8 positions, so
+// that lanes reading 8 consecutive positions each do not all start on the
+// same LDS bank.
+__device__ __forceinline__ int stg_slot(int j) { return j + (j >> 3); }
+template <int P>
+struct SbLds : SbLdsCore<P> {};
 
 // Entries held per lane: a row of up to 8 * GW window cells on a GW-lane group.
 constexpr int kSbEntriesPerLane = 8;
@@ -318,13 +335,73 @@ __device__ double sb_row_lp(const double (&dd)[EL], const uint32_t (&pk)[EL], in
   return slv + qc + q_sp;
 }
 
+// One row's LP value along one order in scan form (boxes of at most 128
+// cells): the row's cells are placed at their order positions in the lane
+// group's staging array (width, value; zero elsewhere), and the group walks
+// the order once, R = 64E / GW positions per lane, with an exclusive prefix
+// sum of the widths -- the sorting method's greedy as written.  Cheaper in
+// VALU than the bisection when the box is small.
+template <int EL, int GW, int E>
+__device__ double sb_row_scan(const double (&dd)[EL], const uint32_t (&pk)[EL], int order,
+                              const SbLds<64 * E>& L, double2* __restrict__ stg, int gl,
+                              double r, double slv, bool mx, const Specials& sp) {
+  constexpr int R = 64 * E / GW;
+#pragma unroll
+  for (int k = 0; k < R; ++k) stg[stg_slot(gl * R + k)] = make_double2(0.0, 0.0);
+  wave_lds_sync();
+#pragma unroll
+  for (int k = 0; k < EL; ++k) {
+    if (pk[k] != kNoEntry) {
+      const double2 V = L.vb[entry_box(pk[k])];
+      stg[stg_slot(entry_pos(pk[k], order))] = make_double2(dd[k], order == 0 ? V.x : V.y);
+    }
+  }
+  wave_lds_sync();
+  // two passes over the lane's positions (widths, then widths and values):
+  // re-reading LDS is cheaper than holding 2R doubles in registers
+  double lane_d = 0.0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) lane_d += stg[stg_slot(gl * R + k)].x;
+  double front = 0.0, q_sp = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (k >= sp.n || !special_front(sp.v[k], mx)) continue;
+    const double room = r - front;
+    const double delta = room <= 0.0 ? 0.0 : (sp.dd[k] < room ? sp.dd[k] : room);
+    q_sp += (sp.lo[k] + delta) * sp.v[k];
+    front += sp.dd[k];
+  }
+  double total;
+  const double excl = group_excl_scan_dpp<GW>(lane_d, gl, total);
+  double acc = front + excl, lane_q = 0.0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const double2 x = stg[stg_slot(gl * R + k)];
+    const double room = r - acc;
+    const double delta = room <= 0.0 ? 0.0 : (x.x < room ? x.x : room);
+    lane_q += delta * x.y;
+    acc += x.x;
+  }
+  wave_lds_sync();
+  double back = front + total;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (k >= sp.n || special_front(sp.v[k], mx)) continue;
+    const double room = r - back;
+    const double delta = room <= 0.0 ? 0.0 : (sp.dd[k] < room ? sp.dd[k] : room);
+    q_sp += (sp.lo[k] + delta) * sp.v[k];
+    back += sp.dd[k];
+  }
+  return slv + group_sum_dpp<GW>(lane_q) + q_sp;
+}
+
 // One group of inputs [g0, g1) of a SAFE state on one wavefront, box of at
 // most 64*E cells.  The box is sorted with 64 lanes (once per order); then
 // lane groups of GW lanes take rows u = g0 + g, g0 + g + 64/GW, ..., each lane
 // holding up to 8 of the row's window cells with their widths, values and
 // order positions.  The group's best is merged into (best0, best1, arg),
 // which hold the earlier groups' (lower inputs') best.
-template <int E, int GW, int PASS, int D>
+template <int E, int GW, int PASS, int D, bool SCAN>
 __device__ __forceinline__ void sb_state(const SweepArgs& a, const SysParams& p, int64_t s, int g0, int g1,
                          const StateBox& b, int lane, SbLds<64 * E>& L, double& best0,
                          double& best1, int& arg) {
@@ -473,8 +550,14 @@ __device__ __forceinline__ void sb_state(const SweepArgs& a, const SysParams& p,
       double r = 1.0 - slo;
       if (r < 0.0) r = 0.0;
       const double s0 = group_sum<GW>(lq0), s1 = group_sum<GW>(lq1);
-      const double q0 = sb_row_lp<EL, GW, 64 * E>(dd, pk, 0, L, (int)PB, r, s0, mx, sp);
-      const double q1 = sb_row_lp<EL, GW, 64 * E>(dd, pk, 1, L, (int)PB, r, s1, mx, sp);
+      double q0, q1;
+      if constexpr (SCAN && E <= 2) {
+        q0 = sb_row_scan<EL, GW, E>(dd, pk, 0, L, L.stg[g], gl, r, s0, mx, sp);
+        q1 = sb_row_scan<EL, GW, E>(dd, pk, 1, L, L.stg[g], gl, r, s1, mx, sp);
+      } else {
+        q0 = sb_row_lp<EL, GW, 64 * E>(dd, pk, 0, L, (int)PB, r, s0, mx, sp);
+        q1 = sb_row_lp<EL, GW, 64 * E>(dd, pk, 1, L, (int)PB, r, s1, mx, sp);
+      }
       // rows of a group come in increasing u: a strict improvement keeps the lowest u
       if (a.reach ? (q0 > gb0) : (q0 < gb0)) {
         gb0 = q0;
@@ -522,17 +605,17 @@ __device__ __forceinline__ double sb_sweep_state(const SweepArgs& a, int64_t s, 
     StateBox b;
     const int g1 = uniform_i32(group_box<PASS, D>(a, s, g0, U, 64 * ESB, lane, b));
     if (ESB == 1 || b.P <= 64)
-      sb_state<1, GW, PASS, D>(a, p, s, g0, g1, b, lane, *(SbLds<64>*)&L, best0, best1, arg);
+      sb_state<1, GW, PASS, D, (ESB <= 2)>(a, p, s, g0, g1, b, lane, *(SbLds<64>*)&L, best0, best1, arg);
     else if (ESB == 2 || b.P <= 128)
-      sb_state<(ESB < 2 ? ESB : 2), GW, PASS, D>(a, p, s, g0, g1, b, lane,
+      sb_state<(ESB < 2 ? ESB : 2), GW, PASS, D, (ESB <= 2)>(a, p, s, g0, g1, b, lane,
                                               *(SbLds<64 * (ESB < 2 ? ESB : 2)>*)&L, best0,
                                               best1, arg);
     else if (ESB == 4 || b.P <= 256)
-      sb_state<(ESB < 4 ? ESB : 4), GW, PASS, D>(a, p, s, g0, g1, b, lane,
+      sb_state<(ESB < 4 ? ESB : 4), GW, PASS, D, (ESB <= 2)>(a, p, s, g0, g1, b, lane,
                                               *(SbLds<64 * (ESB < 4 ? ESB : 4)>*)&L, best0,
                                               best1, arg);
     else
-      sb_state<ESB, GW, PASS, D>(a, p, s, g0, g1, b, lane, L, best0, best1, arg);
+      sb_state<ESB, GW, PASS, D, (ESB <= 2)>(a, p, s, g0, g1, b, lane, L, best0, best1, arg);
     g0 = g1;
     wave_lds_sync();
   }
