@@ -633,6 +633,9 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       while (G > 1 && G * a.inputs_per_state > 256) --G;
       if (a.inputs_per_state > 256)
         return fail(IMPACT_E_UNSUPPORTED, "more than 256 inputs per state");
+      // the fixed-input pass sorting per row runs several rows per wavefront
+      if (pass == 1 && !use_box && rows_g_states_per_block(h->max_row) > 0)
+        G = rows_g_states_per_block(h->max_row);
       a.states_per_block = G;
 
       HIP_TRY(launch_init_values(cls, N, safety, vb[0], vb[1], pass == 0 ? pi : nullptr, h->st));

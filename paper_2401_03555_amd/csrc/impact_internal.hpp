@@ -119,6 +119,7 @@ int64_t sweep_blocks(const SweepArgs& a, bool box_path);
 hipError_t launch_mq_sweep_sb(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
                               const int32_t* ws, int64_t n_items, double* gap_item,
                               int64_t max_box, int32_t max_row, int32_t d, hipStream_t st);
+int rows_g_states_per_block(int32_t max_row);
 hipError_t launch_mq_sweep_row(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
                                const int32_t* ws, int64_t n_items, double* gap_item,
                                int32_t max_row, int32_t d, hipStream_t st);

@@ -136,6 +136,44 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
   }
 }
 
+// Fixed-input pass with short rows: each GW-lane group of the workgroup
+// solves one SAFE state's row (the policy's input), GW = 16 or 32 lanes with
+// E keys each, so a wavefront carries 64 / GW rows at once.
+template <int E, int GW, int D>
+__global__ __launch_bounds__(kBlock) void k_sweep_rows_g(SweepArgs a) {
+  if (a.ctrl->done) return;
+  __shared__ double gapw[kWaves];
+  constexpr int G = kBlock / GW;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int grp = tid / GW, gl = tid % GW;
+  const int64_t si = (int64_t)blockIdx.x * G + grp;
+  double gap = 0.0;
+  if (si < a.n_safe) {
+    const int64_t s = a.safe[si];
+    const int64_t row = s * a.nu + a.pi[s];
+    double q0, q1;
+    solve_row_g<E, GW, D>(a, *a.sys, row, gl, q0, q1);
+    if (gl == 0) {
+      a.vout[s] = make_double2(q0, q1);
+      gap = q1 - q0 > 0.0 ? q1 - q0 : 0.0;
+    }
+  }
+  gap = wave_max(gap);
+  if (lane == 0) gapw[wv] = gap;
+  __syncthreads();
+  if (tid == 0) {
+    double gm = gapw[0];
+    for (int w = 1; w < kWaves; ++w) gm = fmax(gm, gapw[w]);
+    a.gap_part[blockIdx.x] = gm;
+  }
+}
+
+// States per workgroup of k_sweep_rows_g for rows of at most max_row entries,
+// or 0 when the rows are too long for it.
+int rows_g_states_per_block(int32_t max_row) {
+  return max_row <= 128 ? kBlock / 16 : max_row <= 256 ? kBlock / 32 : 0;
+}
+
 // Multi-query fixed-input pass for queries whose rows fit a wavefront: one
 // wavefront per (query, SAFE state) item in the fixed-input phase (others are
 // left to k_mq_sweep_sb), the row of the policy's input solved like the
@@ -179,11 +217,65 @@ __global__ __launch_bounds__(kBlock) void k_mq_sweep_row(
   }
 }
 
+// The engine's fixed-input pass for rows of at most 256 entries: one
+// (query, SAFE state) item per GW-lane group, as k_sweep_rows_g.
+template <int E, int GW, int DIM>
+__global__ __launch_bounds__(kBlock) void k_mq_sweep_rows_g(
+    const QueryDesc* __restrict__ desc, const QueryCtrl* __restrict__ ctrl,
+    const int32_t* __restrict__ wq, const int32_t* __restrict__ ws, int64_t n_items,
+    double* __restrict__ gap_item) {
+  constexpr int G = kBlock / GW;
+  const int grp = threadIdx.x / GW, gl = threadIdx.x % GW;
+  const int64_t item = (int64_t)blockIdx.x * G + grp;
+  if (item >= n_items) return;
+  const int q = wq[item];
+  if (ctrl[q].phase != 2) return;
+  const int64_t s = ws[item];
+  const int64_t step = ctrl[q].step;
+  const QueryDesc& D = desc[q];
+  SweepArgs a = D.a;
+  a.vin = (step & 1) ? D.vb1 : D.vb0;
+  a.vout = (step & 1) ? D.vb0 : D.vb1;
+  a.reach = !D.safety;
+  a.pass = 1;
+  a.maximise = !D.safety;
+  const int64_t row = s * a.nu + a.pi[s];
+  double q0, q1;
+  solve_row_g<E, GW, DIM>(a, *a.sys, row, gl, q0, q1);
+  if (gl == 0) {
+    a.vout[s] = make_double2(q0, q1);
+    const double g = q1 - q0;
+    gap_item[item] = g > 0.0 ? g : 0.0;
+  }
+}
+
 hipError_t launch_mq_sweep_row(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
                                const int32_t* ws, int64_t n_items, double* gap_item,
                                int32_t max_row, int32_t d, hipStream_t st) {
   if (n_items == 0) return hipSuccess;
   if (max_row > 512) return hipErrorInvalidValue;
+  if (max_row <= 256) {
+    const int gw = max_row <= 128 ? 16 : 32;
+    const dim3 gg((unsigned)((n_items + kBlock / gw - 1) / (kBlock / gw))), bb(kBlock);
+#define MG(GW1, D)                                                                            \
+  hipLaunchKernelGGL((k_mq_sweep_rows_g<8, GW1, D>), gg, bb, 0, st, desc, ctrl, wq, ws, \
+                     n_items, gap_item)
+#define MGD(GW1)                \
+  switch (d) {                  \
+    case 2: MG(GW1, 2); break;  \
+    case 3: MG(GW1, 3); break;  \
+    case 5: MG(GW1, 5); break;  \
+    default: MG(GW1, 0); break; \
+  }
+    if (gw == 16) {
+      MGD(16)
+    } else {
+      MGD(32)
+    }
+#undef MGD
+#undef MG
+    return hipGetLastError();
+  }
   const dim3 g((unsigned)((n_items + kWaves - 1) / kWaves)), b(kBlock);
 #define MR(E1, D)                                                                           \
   hipLaunchKernelGGL((k_mq_sweep_row<E1, D>), g, b, 0, st, desc, ctrl, wq, ws, n_items, \
@@ -422,6 +514,14 @@ template <int PASS, int D>
 static hipError_t launch_sweep_pass_d(const SweepArgs& a, int32_t max_row, hipStream_t st) {
   const int64_t blocks = (a.n_safe + a.states_per_block - 1) / a.states_per_block;
   const dim3 g((unsigned)blocks), b(kBlock);
+  if (PASS == 1 && a.states_per_block == rows_g_states_per_block(max_row)) {
+    // one row per state: several rows per wavefront
+    if (max_row <= 128)
+      hipLaunchKernelGGL((k_sweep_rows_g<8, 16, D>), g, b, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_sweep_rows_g<8, 32, D>), g, b, 0, st, a);
+    return hipGetLastError();
+  }
   if (max_row <= 64)
     hipLaunchKernelGGL((k_sweep<1, 0, PASS, D>), g, b, 0, st, a);
   else if (max_row <= 128)

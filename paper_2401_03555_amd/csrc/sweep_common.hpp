@@ -286,6 +286,34 @@ __device__ void bitonic_sort(uint64_t (&key)[E], V (&val)[E], int tid, uint64_t*
   }
 }
 
+// Bitonic sort of GW * E keys held by a GW-lane group (GW <= 64, groups
+// aligned within the wavefront), lane gl holding positions [gl*E, gl*E + E);
+// every partner is in the same group.
+template <int E, int GW, class V>
+__device__ void bitonic_sort_g(uint64_t (&key)[E], V (&val)[E], int gl) {
+  constexpr int P = GW * E;
+#pragma unroll
+  for (int k = 2; k <= P; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j >= E; j >>= 1) {
+      const int tm = j / E;
+      const bool lower = (gl & tm) == 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const bool asc = ((gl * E + e) & k) == 0;
+        const uint64_t pk = xor_lane_u64(key[e], tm);
+        const V pv = xor_lane<V>(val[e], tm);
+        const bool take = (asc == lower) ? !(key[e] < pk) : !(key[e] > pk);
+        if (take) {
+          key[e] = pk;
+          val[e] = pv;
+        }
+      }
+    }
+    intra_stages<E, V>(key, val, gl, k);
+  }
+}
+
 // One row's entries as seen by one thread: positions [first, first + E).
 template <int E>
 struct RowSlice {
@@ -431,6 +459,58 @@ __device__ __forceinline__ int64_t item_row(const SweepArgs& a, int64_t s0, int 
   const int64_t s = a.safe[s0 + gi];
   const int u = PASS == 0 ? ui : a.pi[s];
   return s * a.nu + u;
+}
+
+// The same LP on a GW-lane group (several rows per wavefront, one per group;
+// group sums and scans by DPP within the group).
+template <int E, int GW>
+__device__ double lp_value_g(const RowSlice<E>& rs, const double (&v)[E], double r,
+                             bool maximise, int gl) {
+  double slv = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) slv += rs.lo[e] * v[e];
+  slv = group_sum_dpp<GW>(slv);
+  uint64_t key[E];
+  double dk[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint64_t b = dbits(v[e] + 0.0);
+    key[e] = rs.pad[e] ? ~0ull : (maximise ? ~b : b);
+    dk[e] = rs.dd[e];
+  }
+  bitonic_sort_g<E, GW, double>(key, dk, gl);
+  double ls = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) ls += dk[e];
+  double total;
+  double acc = group_excl_scan_dpp<GW>(ls, gl, total);
+  double sdv = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const double room = r - acc;
+    const double delta = room <= 0.0 ? 0.0 : (dk[e] < room ? dk[e] : room);
+    const double val = bitsd(maximise ? ~key[e] : key[e]);
+    if (delta > 0.0) sdv += delta * val;
+    acc += dk[e];
+  }
+  return slv + group_sum_dpp<GW>(sdv);
+}
+
+// One row (at most GW * E entries) on a GW-lane group: both LP values.
+template <int E, int GW, int D>
+__device__ void solve_row_g(const SweepArgs& a, const SysParams& p, int64_t row, int gl,
+                            double& q0, double& q1) {
+  RowSlice<E> rs;
+  load_row<E, D>(a, p, row, gl * E, rs);
+  double slo = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) slo += rs.lo[e];
+  slo = group_sum_dpp<GW>(slo);
+  double r = 1.0 - slo;
+  if (r < 0.0) r = 0.0;
+  const bool mx = a.maximise != 0;
+  q0 = lp_value_g<E, GW>(rs, rs.v0, r, mx, gl);
+  q1 = lp_value_g<E, GW>(rs, rs.v1, r, mx, gl);
 }
 
 }  // namespace impact
