@@ -598,7 +598,8 @@ int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
                 const int8_t *cls, int32_t spec_kind, double eps,
                 int64_t max_sweeps, double *out_lo, double *out_hi,
                 int32_t *policy, orc_iter_info *info, double *q0_last,
-                int64_t hist_cap, double *hist_v0, double *hist_v1) {
+                int64_t hist_cap, double *hist_v0, double *hist_v1,
+                int32_t optimistic) {
   if (n_inputs < 1 || max_sweeps < 1 || !(eps > 0.0)) return -1;
   int64_t n_safe = 0, max_len = 1;
   for (int64_t s = 0; s < n_states; ++s) {
@@ -619,9 +620,13 @@ int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
   int capped = 0;
   for (int pass = 0; pass < 2; ++pass) {
     int reach = spec_kind != ORC_SAFETY;
-    /* pass 1: reach -> min LP / max over u; safety -> max LP / min over u.
-       pass 2: the LP direction flips and u is fixed by pi. */
-    int maximise = pass == 0 ? !reach : reach;
+    /* pessimistic policy (Sec. 5, IMDP_lower = true): pass 1 takes the
+       adversarial LP -- reach: min LP, max over u; safety (probability of
+       the bad set): max LP, min over u -- and pass 2 the other direction
+       with u fixed by pi.  optimistic policy: the passes' LP directions are
+       swapped, the policy comes from the favourable LP. */
+    int adverse = pass == 0 ? !optimistic : optimistic;
+    int maximise = adverse ? !reach : reach;
     for (int64_t s = 0; s < n_states; ++s) {
       V0[s] = 0.0;
       V1[s] = 1.0;
@@ -688,20 +693,22 @@ int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
       info->converged[pass] = converged;
       info->n_safe = n_safe;
     }
+    /* the adversarial pass bounds the satisfaction probability from below
+       (reach: its V0; safety: 1 - V1 of the bad set), the favourable pass
+       from above (reach: V1; safety: 1 - V0) */
     for (int64_t s = 0; s < n_states; ++s) {
       double v;
       if (cls[s] == ORC_SAFE)
-        v = pass == 0 ? (reach ? V0[s] : 1.0 - V1[s]) : (reach ? V1[s] : 1.0 - V0[s]);
+        v = adverse ? (reach ? V0[s] : 1.0 - V1[s]) : (reach ? V1[s] : 1.0 - V0[s]);
       else if (cls[s] == ORC_TARGET)
         v = 1.0;
       else
         v = 0.0;
-      if (pass == 0) {
+      if (adverse)
         out_lo[s] = v;
-        policy[s] = cls[s] == ORC_SAFE ? pi[s] : -1;
-      } else {
+      else
         out_hi[s] = v;
-      }
+      if (pass == 0) policy[s] = cls[s] == ORC_SAFE ? pi[s] : -1;
     }
   }
   free(V0);

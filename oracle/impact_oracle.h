@@ -106,12 +106,15 @@ double orc_lp_sorted(int64_t n, const double *lo, const double *hi,
                      const double *val, int32_t maximise, double *p_out);
 
 /* ---- interval iteration ---- */
+/* optimistic = 0: pessimistic policy (the paper's IMDP_lower = true);
+   optimistic = 1: optimistic policy (IMDP_lower = false). */
 int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
                 const int32_t *target, const double *lo, const double *hi,
                 const int8_t *cls, int32_t spec_kind, double eps,
                 int64_t max_sweeps, double *out_lo, double *out_hi,
                 int32_t *policy, orc_iter_info *info, double *q0_last,
-                int64_t hist_cap, double *hist_v0, double *hist_v1);
+                int64_t hist_cap, double *hist_v0, double *hist_v1,
+                int32_t optimistic);
 
 #ifdef __cplusplus
 }

@@ -524,6 +524,73 @@ def test_imc_has_trivial_policy(orc):
 
 
 # --------------------------------------------------------------------------
+# Optimistic policy (IMDP_lower = false, Sec. 5): the policy is optimised on
+# the favourable LP and fixed for the adversarial one
+# --------------------------------------------------------------------------
+
+def _two_input_choice():
+    # state 0 SAFE, 1 TARGET, 2 AVOID; input 0: target and avoid in [.4, .6];
+    # input 1: target and avoid in [.1, .9].  Rows of the non-SAFE states are empty.
+    row_ptr = [0, 2, 4, 4, 4, 4, 4]
+    target = [1, 2, 1, 2]
+    lo = [.4, .4, .1, .1]
+    hi = [.6, .6, .9, .9]
+    return row_ptr, target, lo, hi, np.array([0, 1, 2], np.int8)
+
+
+def test_worked_pessimistic_and_optimistic_policies(orc):
+    # Pessimistic: the adversary puts the free mass on AVOID, so input 0 is
+    # worth .4 and input 1 only .1 -> pi = 0, lo = .4; with pi fixed the
+    # favourable LP gives hi = .6.  Optimistic: the favourable LP gives .6 vs
+    # .9 -> pi = 1, hi = .9; fixed, the adversarial LP gives lo = .1.
+    # Every LP here is exact after one sweep (no self loop).
+    row_ptr, target, lo, hi, cls = _two_input_choice()
+    p = orc.iterate(3, 2, row_ptr, target, lo, hi, cls, "reach_avoid", 1e-8, 100)
+    o = orc.iterate(3, 2, row_ptr, target, lo, hi, cls, "reach_avoid", 1e-8, 100,
+                    optimistic=True)
+    assert p["policy"][0] == 0 and o["policy"][0] == 1
+    assert (p["lo"][0], p["hi"][0]) == (pytest.approx(0.4, abs=1e-15), pytest.approx(0.6, abs=1e-15))
+    assert (o["lo"][0], o["hi"][0]) == (pytest.approx(0.1, abs=1e-15), pytest.approx(0.9, abs=1e-15))
+    assert p["status"] == 0 and o["status"] == 0
+
+
+def test_optimistic_equals_pessimistic_without_choice(orc):
+    # one input: no policy to choose, the two passes swap places only
+    system = W.tiny_affine(d=2, n=6, seed=14, n_inputs=1)
+    m = orc.build(system, system["k_sigma"])
+    cls = orc.label(system, [[[0.0, 0.0], [1.0, 1.0]]], [[[-1.0, -1.0], [-0.4, -0.4]]])
+    for kind in ("reach_avoid", "safety"):
+        c = cls.copy()
+        if kind == "safety":
+            c[c == 1] = 0
+        args = (m["n_states"], 1, m["row_ptr"], m["target"], m["lo"], m["hi"], c, kind, 1e-8, 5000)
+        p = orc.iterate(*args)
+        o = orc.iterate(*args, optimistic=True)
+        assert np.array_equal(p["lo"], o["lo"]) and np.array_equal(p["hi"], o["hi"])
+        assert p["sweeps"] == o["sweeps"][::-1]
+
+
+@pytest.mark.parametrize("seed", [12, 21, 24])
+def test_optimistic_policy_orders_the_bounds(orc, seed):
+    # hi_opt bounds max over policies of P_max from above; lo_opt is a lower
+    # bound of P_min under one policy, at most max over policies of P_min,
+    # which lo_pess approximates from below within eps (and vice versa).
+    system = W.tiny_affine(d=2, n=7, seed=seed, n_inputs=4)
+    m = orc.build(system, system["k_sigma"])
+    cls = orc.label(system, [[[0.5, 0.5], [2.0, 2.0]]], [[[-2.0, -2.0], [-1.0, -1.0]]])
+    eps = 1e-9
+    args = (m["n_states"], 4, m["row_ptr"], m["target"], m["lo"], m["hi"], cls, "reach_avoid",
+            eps, 20000)
+    p = orc.iterate(*args)
+    o = orc.iterate(*args, optimistic=True)
+    assert p["status"] == 0 and o["status"] == 0
+    assert np.all(p["hi"] <= o["hi"] + eps)
+    assert np.all(o["lo"] <= p["lo"] + eps)
+    assert np.all(o["lo"] <= o["hi"] + eps)
+    assert (o["hi"] - p["hi"]).max() > 1e-3  # the optimistic policy does raise the upper bound
+
+
+# --------------------------------------------------------------------------
 # Soundness against the concrete system (Monte Carlo under the synthesized policy)
 # --------------------------------------------------------------------------
 
