@@ -163,7 +163,11 @@ enum { IMPACT_SAFETY = 0, IMPACT_REACH = 1, IMPACT_REACH_AVOID = 2 };
  * labelled by its centre (closed boxes, widened by 1e-9 cell widths); avoid
  * wins over target.  SAFETY: avoid boxes are the unsafe set, n_target must be
  * 0.  REACH: n_avoid must be 0.  Leaving [lb, ub] is always unsafe / failure.
- * pessimistic must be 1 (the paper's IMDP_lower = true policy).
+ * pessimistic: 1 for the pessimistic policy (the paper's IMDP_lower = true,
+ * Section 5: the policy is optimised on the adversarial LP and fixed for the
+ * favourable one), 0 for the optimistic policy (optimised on the favourable
+ * LP, fixed for the adversarial one); any other value is E_INVAL.  Either
+ * way lo is the lower and hi the upper satisfaction bound under the policy.
  * max_sweeps >= 1 caps each of the two passes. */
 typedef struct {
   int32_t kind, n_target, n_avoid;

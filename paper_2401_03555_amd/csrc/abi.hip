@@ -538,8 +538,8 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
     return fail(IMPACT_E_INVAL, "safety takes no target boxes");
   if (spec->kind == IMPACT_REACH && spec->n_avoid != 0)
     return fail(IMPACT_E_INVAL, "reachability takes no avoid boxes (use reach-avoid)");
-  if (spec->pessimistic != 1)
-    return fail(IMPACT_E_UNSUPPORTED, "only the pessimistic policy is implemented");
+  if (spec->pessimistic != 0 && spec->pessimistic != 1)
+    return fail(IMPACT_E_INVAL, "pessimistic must be 0 or 1");
   if (spec->max_sweeps < 1) return fail(IMPACT_E_INVAL, "max_sweeps must be >= 1");
   if (!is_finite(eps) || !(eps > 0.0)) return fail(IMPACT_E_INVAL, "eps must be finite and > 0");
   const int d = h->d;
@@ -621,7 +621,11 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       a.fs = h->fs;
       a.pass = pass;
       a.reach = !safety;
-      a.maximise = pass == 0 ? safety : !safety;
+      // the adversarial LP (reach: minimising; safety: maximising the bad
+      // mass) runs in the policy pass for the pessimistic policy and in the
+      // fixed-input pass for the optimistic one
+      const bool adverse = (pass == 0) == (spec->pessimistic != 0);
+      a.maximise = adverse ? safety : !safety;
       a.nu = h->nu;
       a.d = d;
       a.windowed = h->windowed;
@@ -712,8 +716,8 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       info.sweep_ms[pass] = sweep_ms;
       info.launch_ms[pass] = launch_ms;
       info.launches[pass] = launched;
-      HIP_TRY(launch_finalize(cls, N, vb[sweeps & 1], pi, pass, safety, pass == 0 ? lo : hi,
-                              policy, h->st));
+      HIP_TRY(launch_finalize(cls, N, vb[sweeps & 1], pi, adverse ? 0 : 1, safety,
+                              adverse ? lo : hi, pass == 0 ? policy : nullptr, h->st));
     }
     HIP_TRY(hipStreamSynchronize(h->st));
     for (hipEvent_t e : evs) (void)hipEventDestroy(e);

@@ -398,8 +398,8 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
     return mq_fail(IMPACT_E_INVAL, "safety takes no target boxes");
   if (spec->kind == IMPACT_REACH && spec->n_avoid != 0)
     return mq_fail(IMPACT_E_INVAL, "reachability takes no avoid boxes (use reach-avoid)");
-  if (spec->pessimistic != 1)
-    return mq_fail(IMPACT_E_UNSUPPORTED, "only the pessimistic policy is implemented");
+  if (spec->pessimistic != 0 && spec->pessimistic != 1)
+    return mq_fail(IMPACT_E_INVAL, "pessimistic must be 0 or 1");
   if (spec->max_sweeps < 1) return mq_fail(IMPACT_E_INVAL, "max_sweeps must be >= 1");
   if (!std::isfinite(eps) || !(eps > 0.0)) return mq_fail(IMPACT_E_INVAL, "eps must be > 0");
   ImdpView v;
@@ -472,7 +472,7 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
     MQ_TRY(launch_init_values(cls, N, safety, vb0, vb1, pi, m->st));
     // outputs of non-SAFE cells now (SAFE cells are written when the passes close)
     MQ_TRY(launch_finalize(cls, N, vb0, pi, 0, safety, lo, policy, m->st));
-    MQ_TRY(launch_finalize(cls, N, vb0, pi, 1, safety, hi, policy, m->st));
+    MQ_TRY(launch_finalize(cls, N, vb0, pi, 1, safety, hi, nullptr, m->st));
     QueryDesc D;
     std::memset(&D, 0, sizeof(D));
     D.a = v.a;
@@ -486,6 +486,10 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
     D.hi = hi;
     D.pol = policy;
     D.safety = safety;
+    // the adversarial LP first for the pessimistic policy, second for the optimistic one
+    D.upper_first = spec->pessimistic ? 0 : 1;
+    D.max_lp[0] = spec->pessimistic ? safety : !safety;
+    D.max_lp[1] = spec->pessimistic ? !safety : safety;
     D.box_class = v.max_row <= 512;
     D.eps = eps;
     D.cap = spec->max_sweeps;

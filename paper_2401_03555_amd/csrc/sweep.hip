@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_mq_sweep_row(
   a.vout = (step & 1) ? D.vb0 : D.vb1;
   a.reach = !D.safety;
   a.pass = 1;
-  a.maximise = !D.safety;
+  a.maximise = D.max_lp[1];
   const SysParams& p = *a.sys;
   const int64_t row = s * a.nu + a.pi[s];
   const int n = (int)(a.row_off[row + 1] - a.row_off[row]) + 1 + a.windowed;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void k_mq_sweep_rows_g(
   a.vout = (step & 1) ? D.vb0 : D.vb1;
   a.reach = !D.safety;
   a.pass = 1;
-  a.maximise = !D.safety;
+  a.maximise = D.max_lp[1];
   const int64_t row = s * a.nu + a.pi[s];
   double q0, q1;
   solve_row_g<E, GW, DIM>(a, *a.sys, row, gl, q0, q1);
@@ -323,25 +323,15 @@ __global__ __launch_bounds__(kBlock) void k_mq_sweep_block(
     a.reach = !D.safety;
     if (phase == 0) {
       a.pass = 0;
-      a.maximise = D.safety;
+      a.maximise = D.max_lp[0];
       g = block_sweep_states<WAVE_E, BLOCK_E, 0, 0>(a, ws + item, 1, L);
     } else {
       a.pass = 1;
-      a.maximise = !D.safety;
+      a.maximise = D.max_lp[1];
       g = block_sweep_states<WAVE_E, BLOCK_E, 1, 0>(a, ws + item, 1, L);
     }
   } else if ((phase == 1 || phase == 3) && threadIdx.x == 0) {
-    const int64_t s = ws[item];
-    const double2* vin = (step & 1) ? D.vb1 : D.vb0;
-    double2* vout = (step & 1) ? D.vb0 : D.vb1;
-    const double2 V = vin[s];
-    if (phase == 1) {
-      D.lo[s] = D.safety ? 1.0 - V.y : V.x;
-      D.pol[s] = D.a.pi[s];
-      vout[s] = make_double2(0.0, 1.0);
-    } else {
-      D.hi[s] = D.safety ? 1.0 - V.x : V.y;
-    }
+    mq_close_state(D, step, phase, ws[item]);
   }
   if (threadIdx.x == 0) gap_item[item] = g;
 }
@@ -462,22 +452,13 @@ __global__ void k_init_values(const int8_t* __restrict__ cls, int64_t n, int32_t
 
 // Outputs: pass 0 writes lo and the policy, pass 1 writes hi.
 __global__ void k_finalize(const int8_t* __restrict__ cls, int64_t n, const double2* __restrict__ v,
-                           const int32_t* __restrict__ pi, int32_t pass, int32_t safety,
+                           const int32_t* __restrict__ pi, int32_t upper, int32_t safety,
                            double* __restrict__ out, int32_t* __restrict__ policy) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
-  double o;
-  if (cls[s] == kSafe) {
-    const double2 x = v[s];
-    if (pass == 0)
-      o = safety ? 1.0 - x.y : x.x;
-    else
-      o = safety ? 1.0 - x.x : x.y;
-  } else {
-    o = cls[s] == kTarget ? 1.0 : 0.0;
-  }
-  out[s] = o;
-  if (pass == 0) policy[s] = cls[s] == kSafe ? pi[s] : -1;
+  out[s] = cls[s] == kSafe ? bound_of(v[s], upper != 0, safety != 0)
+                           : (cls[s] == kTarget ? 1.0 : 0.0);
+  if (policy) policy[s] = cls[s] == kSafe ? pi[s] : -1;
 }
 
 static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -568,10 +549,10 @@ int64_t sweep_blocks(const SweepArgs& a, bool box_path) {
 }
 
 hipError_t launch_finalize(const int8_t* cls, int64_t n, const double2* v, const int32_t* pi,
-                           int32_t pass, int32_t safety, double* out, int32_t* policy,
+                           int32_t upper, int32_t safety, double* out, int32_t* policy,
                            hipStream_t st) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, st, cls, n, v, pi, pass,
+  hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, st, cls, n, v, pi, upper,
                      safety, out, policy);
   return hipGetLastError();
 }

@@ -648,22 +648,6 @@ __global__ __launch_bounds__(64 * kSbWaves) void k_sweep_sb(SweepArgs a) {
   }
 }
 
-// Close a pass for one state of a query (phase 1: lo, policy and the reset of
-// the values for pass 2; phase 3: hi).
-__device__ __forceinline__ void mq_close_state(const QueryDesc& D, int64_t step, int phase,
-                                               int64_t s) {
-  const double2* vin = (step & 1) ? D.vb1 : D.vb0;
-  double2* vout = (step & 1) ? D.vb0 : D.vb1;
-  const double2 V = vin[s];
-  if (phase == 1) {
-    D.lo[s] = D.safety ? 1.0 - V.y : V.x;
-    D.pol[s] = D.a.pi[s];
-    vout[s] = make_double2(0.0, 1.0);
-  } else {
-    D.hi[s] = D.safety ? 1.0 - V.x : V.y;
-  }
-}
-
 // Multi-query state-box sweep of the policy pass (and the closing steps):
 // one wavefront per (query, SAFE state) item,
 // each query at its own phase and step.
@@ -690,7 +674,7 @@ __global__ __launch_bounds__(64 * kSbWaves) void k_mq_sweep_sb(
     a.vout = (step & 1) ? D.vb0 : D.vb1;
     a.reach = !D.safety;
     a.pass = 0;
-    a.maximise = D.safety;
+    a.maximise = D.max_lp[0];
     g = sb_sweep_state<ESB, GW, 0, DIM>(a, s, lane, lds[wv]);
   } else if ((phase == 1 || phase == 3) && lane == 0) {
     mq_close_state(D, step, phase, s);

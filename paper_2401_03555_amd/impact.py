@@ -278,7 +278,8 @@ class Imdp:
         tb = _f64(np.asarray(spec.get("target") or np.zeros((0, 2, d))).reshape(-1, 2, d))
         ab = _f64(np.asarray(spec.get("avoid") or np.zeros((0, 2, d))).reshape(-1, 2, d))
         s = Spec(SPEC_KINDS[spec["kind"]], tb.shape[0], ab.shape[0],
-                 _dptr(tb) if tb.size else None, _dptr(ab) if ab.size else None, 1,
+                 _dptr(tb) if tb.size else None, _dptr(ab) if ab.size else None,
+                 int(bool(spec.get("pessimistic", True))),
                  int(max_sweeps if max_sweeps is not None else spec.get("max_sweeps", 100000)))
         dev = f"cuda:{self._dev.device}"
         if out is None:
@@ -340,7 +341,8 @@ def _spec_struct(spec, d, max_sweeps=None):
     tb = _f64(np.asarray(spec.get("target") or np.zeros((0, 2, d))).reshape(-1, 2, d))
     ab = _f64(np.asarray(spec.get("avoid") or np.zeros((0, 2, d))).reshape(-1, 2, d))
     s = Spec(SPEC_KINDS[spec["kind"]], tb.shape[0], ab.shape[0],
-             _dptr(tb) if tb.size else None, _dptr(ab) if ab.size else None, 1,
+             _dptr(tb) if tb.size else None, _dptr(ab) if ab.size else None,
+             int(bool(spec.get("pessimistic", True))),
              int(max_sweeps if max_sweeps is not None else spec.get("max_sweeps", 100000)))
     return s, (tb, ab)
 

@@ -10,7 +10,8 @@ System dict keys: ``kind`` ("affine" | "unicycle"), ``A``, ``B``, ``c`` (affine)
 ``sigma`` (diagonal noise standard deviations), ``k_sigma`` (window half-width in
 standard deviations; 0 means dense rows).
 Spec dict keys: ``kind`` ("safety" | "reach" | "reach_avoid"), ``target``,
-``avoid`` (lists of [lo, hi] boxes), ``eps``, ``max_sweeps``.
+``avoid`` (lists of [lo, hi] boxes), ``eps``, ``max_sweeps``, optionally
+``pessimistic`` (default true; false: optimistic policy).
 """
 import itertools
 import math

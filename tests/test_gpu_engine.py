@@ -70,9 +70,11 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("pessimistic", [True, False], ids=["pess", "opt"])
 @pytest.mark.parametrize("name,make,spec", CASES, ids=[c[0] for c in CASES])
-def test_engine_query_equals_plain_iterate(I, name, make, spec):
+def test_engine_query_equals_plain_iterate(I, name, make, spec, pessimistic):
     system = make()
+    spec = dict(spec, pessimistic=pessimistic)
     imdp = _engine_modes(I.build_imdp(system))
     plain = imdp.iterate(spec)
     eng = I.Engine(max_queries=4)

@@ -84,19 +84,48 @@ def check_policy(pol_g, pol_o, q0, cls, reach, label):
     assert not bad, f"{label}: policy mismatch beyond ties at {bad[:10]}"
 
 
-def compare_iter(g, o, cls, reach, label, q0=None):
+def fixed_pass_under(m, cls, spec, policy, optimistic):
+    """Oracle run of the interval Markov chain that ``policy`` induces.
+
+    The fixed-input pass starts afresh from the policy alone, so its bound and
+    sweep count are those of the second pass of this run.
+    """
+    U, N = m["n_inputs"], m["n_states"]
+    rows = np.arange(N) * U + np.maximum(np.asarray(policy), 0)
+    rp = m["row_ptr"]
+    starts, ends = rp[rows], rp[rows + 1]
+    idx = np.concatenate([np.arange(a, b) for a, b in zip(starts, ends)])
+    new_rp = np.concatenate([[0], np.cumsum(ends - starts)]).astype(np.int64)
+    return oracle.iterate(N, 1, new_rp, m["target"][idx], m["lo"][idx], m["hi"][idx], cls,
+                          spec["kind"], spec["eps"], spec["max_sweeps"], optimistic=optimistic)
+
+
+def compare_iter(g, o, cls, reach, label, q0=None, model=None, spec=None, optimistic=False):
+    """Policy-pass bound and sweeps against the oracle; the policy equal up to
+    ties.  Where the policies differ at ties (``model`` given), the
+    fixed-input pass is checked against the oracle run under the GPU's policy."""
     lo, hi = g["lo"].cpu().numpy(), g["hi"].cpu().numpy()
     pol = g["policy"].cpu().numpy()
+    kp, kf = ("hi", "lo") if optimistic else ("lo", "hi")
+    got = dict(lo=lo, hi=hi)
     dlo = np.abs(lo - o["lo"]).max()
     dhi = np.abs(hi - o["hi"]).max()
     say(f"{label}: sweeps gpu {g['info']['sweeps']} oracle {tuple(o['sweeps'])} "
         f"max|dlo| {dlo:.2e} max|dhi| {dhi:.2e} status {g['status']}")
-    assert tuple(g["info"]["sweeps"]) == tuple(o["sweeps"])
-    assert dlo <= VALUE_TOL and dhi <= VALUE_TOL
+    assert g["info"]["sweeps"][0] == o["sweeps"][0]
+    assert np.abs(got[kp] - o[kp]).max() <= VALUE_TOL
     if q0 is not None:
         check_policy(pol, np.asarray(o["policy"]), q0, cls, reach, label)
     else:
         assert np.array_equal(pol, o["policy"])
+    ref = o
+    if model is not None and not np.array_equal(pol, np.asarray(o["policy"])):
+        ref = fixed_pass_under(model, cls, spec, pol, optimistic)
+        d = np.abs(got[kf] - ref[kf]).max()
+        say(f"{label}: policies differ at ties; fixed pass under the GPU policy: "
+            f"sweeps {ref['sweeps'][1]} max|d{kf}| {d:.2e}")
+    assert g["info"]["sweeps"][1] == ref["sweeps"][1]
+    assert np.abs(got[kf] - ref[kf]).max() <= VALUE_TOL
 
 
 SMALL_SYSTEMS = {
@@ -187,7 +216,7 @@ def test_iterate_parity_small(I, name):
     ro = oracle.iterate(m["n_states"], m["n_inputs"], m["row_ptr"], m["target"], m["lo"], m["hi"],
                         cls, spec["kind"], spec["eps"], spec["max_sweeps"], want_q0=True)
     assert rg["status"] == ro["status"]
-    compare_iter(rg, ro, cls, spec["kind"] != "safety", name, q0=ro["q0"])
+    compare_iter(rg, ro, cls, spec["kind"] != "safety", name, q0=ro["q0"], model=m, spec=spec)
 
 
 def test_iterate_parity_robot2d_converged(I):
@@ -370,7 +399,8 @@ def test_sweep_modes_match_oracle(I, case, mode):
     cls = oracle.label(system, spec["target"], spec["avoid"])
     ro = oracle.iterate(m["n_states"], m["n_inputs"], m["row_ptr"], m["target"], m["lo"], m["hi"],
                         cls, spec["kind"], spec["eps"], K, want_q0=True)
-    compare_iter(rg, ro, cls, spec["kind"] != "safety", f"{case}[{mode}]", q0=ro["q0"])
+    compare_iter(rg, ro, cls, spec["kind"] != "safety", f"{case}[{mode}]", q0=ro["q0"],
+                 model=m, spec=spec)
 
 
 # ---------------------------------------------------------------------------
@@ -399,3 +429,50 @@ def test_batch_build_equals_separate_builds(I, storage):
     for key in ("lo", "hi", "policy"):
         assert bool((r1[key] == r2[key]).all()), key
     del views
+
+
+# ---------------------------------------------------------------------------
+# optimistic policy (Sec. 5 with IMDP_lower = false): the policy pass takes
+# the favourable bound, the fixed-input pass the adversarial one
+# ---------------------------------------------------------------------------
+
+OPT_CASES = ["affine2_window", "affine3_window", "affine2_dense", "affine1_window",
+             "unicycle_small"]
+
+
+@pytest.mark.parametrize("mode", ["per_row", "state_box"])
+@pytest.mark.parametrize("name", OPT_CASES)
+def test_optimistic_policy_matches_oracle(I, name, mode):
+    system = SMALL_SYSTEMS[name]()
+    spec = dict(SPECS[name], eps=1e-8, max_sweeps=3000, pessimistic=False)
+    say(f"optimistic iterate parity: {name} {spec['kind']} [{mode}]")
+    g = I.build_imdp(system, sweep_mode=mode)
+    rg = g.iterate(spec)
+    m = oracle.build(system, system["k_sigma"])
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    ro = oracle.iterate(m["n_states"], m["n_inputs"], m["row_ptr"], m["target"], m["lo"], m["hi"],
+                        cls, spec["kind"], spec["eps"], spec["max_sweeps"], want_q0=True,
+                        optimistic=True)
+    assert rg["status"] == ro["status"]
+    compare_iter(rg, ro, cls, spec["kind"] != "safety", f"{name} optimistic", q0=ro["q0"],
+                 model=m, spec=spec, optimistic=True)
+    lo, hi = rg["lo"].cpu().numpy(), rg["hi"].cpu().numpy()
+    assert (lo <= hi + 1e-12).all()
+
+
+def test_optimistic_and_pessimistic_policies_differ_where_choice_matters(I):
+    # each policy is optimal for its own bound: the pessimistic one maximises
+    # the guaranteed (lower) reach bound over the policies, the optimistic one
+    # the possible (upper) bound; with several inputs some state's choice differs
+    system = SMALL_SYSTEMS["unicycle_small"]()
+    spec = dict(SPECS["unicycle_small"], eps=1e-8, max_sweeps=3000)
+    g = I.build_imdp(system)
+    rp = g.iterate(spec)
+    ro = g.iterate(dict(spec, pessimistic=False))
+    plo, phi = rp["lo"].cpu().numpy(), rp["hi"].cpu().numpy()
+    olo, ohi = ro["lo"].cpu().numpy(), ro["hi"].cpu().numpy()
+    tol = spec["eps"]
+    assert (plo >= olo - tol).all()
+    assert (ohi >= phi - tol).all()
+    assert (ohi - phi).max() > 1e3 * tol
+    assert (rp["policy"] != ro["policy"]).any()
