@@ -88,7 +88,7 @@ def lib():
         L.orc_iterate.restype = C.c_int
         L.orc_iterate.argtypes = [i64, i32, C.POINTER(C.c_int64), C.POINTER(C.c_int32), pd, pd,
                                   C.POINTER(C.c_int8), i32, d, i64, pd, pd,
-                                  C.POINTER(C.c_int32), C.POINTER(_IterInfo), pd, i64, pd, pd, i32]
+                                  C.POINTER(C.c_int32), C.POINTER(_IterInfo), pd, i64, pd, pd, i32, i64]
         _lib = L
     return _lib
 
@@ -235,9 +235,10 @@ def lp_sorted(lo, hi, val, maximise):
 
 
 def iterate(n_states_, n_inputs, row_ptr, target, lo, hi, cls, spec_kind, eps, max_sweeps,
-            want_q0=False, hist_cap=0, optimistic=False):
+            want_q0=False, hist_cap=0, optimistic=False, horizon=0):
     """Interval iteration (Alg. 3 / Alg. 4 with the sorting method); the
     policy is pessimistic (IMDP_lower = true, Sec. 5) unless ``optimistic``.
+    ``horizon`` T > 0: finite horizon, T sweeps per pass (Remark 5.1).
 
     Returns dict(lo, hi, policy, status, sweeps, gap, converged, n_safe[, q0][, hist_v0, hist_v1]).
     """
@@ -259,7 +260,7 @@ def iterate(n_states_, n_inputs, row_ptr, target, lo, hi, cls, spec_kind, eps, m
         cls.ctypes.data_as(C.POINTER(C.c_int8)), spec_kind, float(eps), int(max_sweeps),
         _dptr(out_lo), _dptr(out_hi), pol.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(info),
         _dptr(q0) if want_q0 else None, hist_cap, _dptr(h0) if hist_cap else None,
-        _dptr(h1) if hist_cap else None, int(bool(optimistic)))
+        _dptr(h1) if hist_cap else None, int(bool(optimistic)), int(horizon))
     if rc < 0:
         raise ValueError(f"oracle iterate rejected its input ({rc})")
     res = dict(lo=out_lo, hi=out_hi, policy=pol, status=rc, sweeps=tuple(info.sweeps),

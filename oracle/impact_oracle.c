@@ -591,7 +591,16 @@ static double max_gap(int64_t n, const int8_t *cls, const double *V0, const doub
  *   reach, reach-avoid: lo = V0 of pass 1, hi = V1 of pass 2;
  *   safety: lo = 1 - V1 of pass 1, hi = 1 - V0 of pass 2;
  *   TARGET cells lo = hi = 1; AVOID cells lo = hi = 0; policy -1 off S.
- * Returns 0 if both passes met eps, 1 if a cap fired, < 0 on bad input.
+ * Finite horizon (Remark 5.1, horizon = T > 0): the while loops become for
+ * loops, so each pass runs exactly T sweeps with no stop test (none without
+ * SAFE states), and interval iteration reduces to value iteration: both
+ * bounds come from the V0 iterate, which after k sweeps is the k-step value
+ * from V0 = 0 (reach: lo = V0 of the adversarial pass, hi = V0 of the
+ * favourable one; safety: 1 - V0 of each).  The policy is the optimising
+ * input of the last pass-1 sweep (the first decision of the T-step game),
+ * held fixed for pass 2, as above.
+ * Returns 0 if both passes met eps (or ran their T sweeps), 1 if a cap
+ * fired, < 0 on bad input.
  */
 int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
                 const int32_t *target, const double *lo, const double *hi,
@@ -599,8 +608,8 @@ int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
                 int64_t max_sweeps, double *out_lo, double *out_hi,
                 int32_t *policy, orc_iter_info *info, double *q0_last,
                 int64_t hist_cap, double *hist_v0, double *hist_v1,
-                int32_t optimistic) {
-  if (n_inputs < 1 || max_sweeps < 1 || !(eps > 0.0)) return -1;
+                int32_t optimistic, int64_t horizon) {
+  if (n_inputs < 1 || max_sweeps < 1 || !(eps > 0.0) || horizon < 0) return -1;
   int64_t n_safe = 0, max_len = 1;
   for (int64_t s = 0; s < n_states; ++s) {
     if (spec_kind == ORC_SAFETY && cls[s] == ORC_TARGET) return -1;
@@ -636,11 +645,15 @@ int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
     int converged;
     for (;;) {
       gap = n_safe > 0 ? max_gap(n_states, cls, V0, V1) : 0.0;
-      if (gap <= eps) {
+      if (horizon > 0) {
+        if (n_safe == 0 || sweeps >= horizon) {
+          converged = 1;
+          break;
+        }
+      } else if (gap <= eps) {
         converged = 1;
         break;
-      }
-      if (sweeps >= max_sweeps) {
+      } else if (sweeps >= max_sweeps) {
         converged = 0;
         break;
       }
@@ -698,7 +711,9 @@ int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
        from above (reach: V1; safety: 1 - V0) */
     for (int64_t s = 0; s < n_states; ++s) {
       double v;
-      if (cls[s] == ORC_SAFE)
+      if (cls[s] == ORC_SAFE && horizon > 0)
+        v = reach ? V0[s] : 1.0 - V0[s]; /* value iteration: both from V0 = 0 */
+      else if (cls[s] == ORC_SAFE)
         v = adverse ? (reach ? V0[s] : 1.0 - V1[s]) : (reach ? V1[s] : 1.0 - V0[s]);
       else if (cls[s] == ORC_TARGET)
         v = 1.0;

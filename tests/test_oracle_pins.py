@@ -641,3 +641,169 @@ def test_label_counts(orc):
     sysd, spec = W.unicycle3d()
     cls = orc.label(sysd, spec["target"], spec["avoid"])
     assert list(np.bincount(cls, minlength=3)) == [53664, 1536, 4800]
+
+
+@pytest.mark.parametrize("optimistic", [False, True])
+def test_fixed_input_pass_depends_on_the_policy_alone(orc, optimistic):
+    # Alg. 3/4: the second pass restarts from the initial vectors with u fixed
+    # by the first pass's policy, so it equals the run of the induced IMC
+    system = W.tiny_affine(d=2, n=7, seed=12, n_inputs=4)
+    m = orc.build(system, system["k_sigma"])
+    cls = orc.label(system, [[[0.5, 0.5], [2.0, 2.0]]], [[[-2.0, -2.0], [-1.0, -1.0]]])
+    full = orc.iterate(m["n_states"], 4, m["row_ptr"], m["target"], m["lo"], m["hi"], cls,
+                       "reach_avoid", 1e-9, 20000, optimistic=optimistic)
+    rows = np.arange(m["n_states"]) * 4 + np.maximum(full["policy"], 0)
+    starts, ends = m["row_ptr"][rows], m["row_ptr"][rows + 1]
+    idx = np.concatenate([np.arange(a, b) for a, b in zip(starts, ends)])
+    rp = np.concatenate([[0], np.cumsum(ends - starts)]).astype(np.int64)
+    imc = orc.iterate(m["n_states"], 1, rp, m["target"][idx], m["lo"][idx], m["hi"][idx], cls,
+                      "reach_avoid", 1e-9, 20000, optimistic=optimistic)
+    k = "lo" if optimistic else "hi"
+    assert imc["sweeps"][1] == full["sweeps"][1]
+    assert np.array_equal(imc[k], full[k])
+
+
+# --------------------------------------------------------------------------
+# Finite horizon (Remark 5.1): each pass is T sweeps of value iteration
+# --------------------------------------------------------------------------
+
+def _self_loop_choice(kind):
+    # state 0 SAFE, state 1 TARGET (reach) or AVOID (safety).  Each input keeps
+    # the chain in state 0 or moves it to state 1; the move's probability is
+    # in [.3, .4] under input 0 and in [.2, .6] under input 1.
+    row_ptr = [0, 2, 4, 4, 4]
+    target = [0, 1, 0, 1]
+    lo = [.6, .3, .4, .2]
+    hi = [.7, .4, .8, .6]
+    return row_ptr, target, lo, hi, np.array([0, 1 if kind != "safety" else 2], np.int8)
+
+
+@pytest.mark.parametrize("T", [1, 3, 10])
+def test_finite_horizon_geometric_closed_forms(orc, T):
+    # reach within T steps with a per-step move probability q: 1 - (1 - q)^T;
+    # staying safe for T steps: (1 - q)^T.  The adversary's q is an end of the
+    # interval at every step.  Pessimistic: reach takes u maximising the worst
+    # q (input 0, .3), safety u minimising the worst q (input 0, .4); the
+    # optimistic policy takes the best q (input 1: .6 to reach, .2 to fail).
+    cases = {
+        ("reach", False): (0, 1 - .7 ** T, 1 - .6 ** T),
+        ("reach", True): (1, 1 - .8 ** T, 1 - .4 ** T),
+        ("safety", False): (0, .6 ** T, .7 ** T),
+        ("safety", True): (1, .4 ** T, .8 ** T),
+    }
+    for (kind, opt), (pi, lo, hi) in cases.items():
+        row_ptr, target, l, h, cls = _self_loop_choice(kind)
+        r = orc.iterate(2, 2, row_ptr, target, l, h, cls, kind, 1e-8, 1, optimistic=opt,
+                        horizon=T)
+        assert r["status"] == 0 and r["sweeps"] == (T, T), (kind, opt)
+        assert r["policy"][0] == pi, (kind, opt)
+        assert r["lo"][0] == pytest.approx(lo, abs=1e-15), (kind, opt)
+        assert r["hi"][0] == pytest.approx(hi, abs=1e-15), (kind, opt)
+
+
+def _random_interval_imdp(rng, n_safe, n_u):
+    # dense rows over n_safe SAFE states + TARGET + AVOID; each interval holds
+    # a probability vector, so every row is feasible
+    n = n_safe + 2
+    row_ptr, target, lo, hi = [0], [], [], []
+    for s in range(n):
+        for u in range(n_u):
+            if s < n_safe:
+                p = rng.dirichlet(np.ones(n))
+                lo += list(np.maximum(0.0, p - rng.uniform(0, .15, n)))
+                hi += list(np.minimum(1.0, p + rng.uniform(0, .15, n)))
+                target += list(range(n))
+            row_ptr.append(len(target))
+    cls = np.array([0] * n_safe + [1, 2], np.int8)
+    return n, row_ptr, np.array(target), np.array(lo), np.array(hi), cls
+
+
+def _highs_lp(lo, hi, val, maximise):
+    res = linprog(-val if maximise else val, A_eq=np.ones((1, len(val))), b_eq=[1.0],
+                  bounds=list(zip(lo, hi)), method="highs")
+    return -res.fun if maximise else res.fun
+
+
+@pytest.mark.parametrize("kind,opt,seed", [("reach_avoid", False, 1), ("reach_avoid", True, 2),
+                                           ("safety", False, 3), ("safety", True, 4)])
+def test_finite_horizon_equals_backward_induction(orc, kind, opt, seed):
+    # T-step game by backward induction with HiGHS LPs: the first pass's
+    # bound is the T-step optimum over inputs (a decision per step), the
+    # policy is an optimal first decision, the second pass holds it for T steps
+    rng = np.random.default_rng(seed)
+    n_safe, n_u, T = 4, 3, 6
+    n, row_ptr, tgt, lo, hi, cls = _random_interval_imdp(rng, n_safe, n_u)
+    if kind == "safety":
+        cls = cls.copy()
+        cls[n_safe] = 2  # no TARGET under safety: both extra states are unsafe
+    safety = kind == "safety"
+    r = orc.iterate(n, n_u, row_ptr, tgt, lo, hi, cls, kind, 1e-8, 1, optimistic=opt,
+                    horizon=T, want_q0=True)
+    safe = np.where(cls == 0)[0]
+
+    def value(V, t):
+        if cls[t] == 0:
+            return V[t]
+        if cls[t] == 1:
+            return 1.0
+        return 1.0 if safety else 0.0
+
+    adverse_max = safety            # the adversary's LP direction
+    first_max = adverse_max if not opt else not adverse_max
+    better = min if safety else max  # over inputs
+    W = np.zeros(n)
+    last_q = None
+    for _ in range(T):
+        Wn = W.copy()
+        last_q = {}
+        for s in safe:
+            qs = []
+            for u in range(n_u):
+                a, b = row_ptr[s * n_u + u], row_ptr[s * n_u + u + 1]
+                val = np.array([value(W, t) for t in tgt[a:b]])
+                qs.append(_highs_lp(lo[a:b], hi[a:b], val, first_max))
+            Wn[s] = better(qs)
+            last_q[s] = qs
+        W = Wn
+    pol = r["policy"]
+    H = np.zeros(n)
+    for _ in range(T):
+        Hn = H.copy()
+        for s in safe:
+            a, b = row_ptr[s * n_u + pol[s]], row_ptr[s * n_u + pol[s] + 1]
+            val = np.array([value(H, t) for t in tgt[a:b]])
+            Hn[s] = _highs_lp(lo[a:b], hi[a:b], val, not first_max)
+        H = Hn
+    for s in safe:
+        assert last_q[s][pol[s]] == pytest.approx(better(last_q[s]), abs=1e-9)
+    first = 1 - W[safe] if safety else W[safe]
+    second = 1 - H[safe] if safety else H[safe]
+    lo_ref, hi_ref = (second, first) if opt else (first, second)
+    assert np.abs(r["lo"][safe] - lo_ref).max() < 1e-9
+    assert np.abs(r["hi"][safe] - hi_ref).max() < 1e-9
+    assert r["sweeps"] == (T, T) and r["status"] == 0
+
+
+def test_finite_horizon_rises_to_the_infinite_horizon_bound(orc):
+    # reach within T steps grows with T and stays below the infinite-horizon
+    # lower bound's limit (V0 of interval iteration approaches it from below)
+    system = W.tiny_affine(d=2, n=7, seed=12, n_inputs=4)
+    m = orc.build(system, system["k_sigma"])
+    cls = orc.label(system, [[[0.5, 0.5], [2.0, 2.0]]], [[[-2.0, -2.0], [-1.0, -1.0]]])
+    args = (m["n_states"], 4, m["row_ptr"], m["target"], m["lo"], m["hi"], cls, "reach_avoid")
+    inf = orc.iterate(*args, 1e-12, 100000)
+    prev = np.zeros(m["n_states"])
+    for T in (1, 2, 4, 8, 16, 64, 256):
+        r = orc.iterate(*args, 1e-8, 1, horizon=T)
+        assert (r["lo"] >= prev - 1e-15).all()
+        assert (r["lo"] <= inf["lo"] + 1e-12).all()
+        prev = r["lo"]
+    assert np.abs(prev - inf["lo"]).max() < 1e-6
+
+
+def test_finite_horizon_without_safe_states_runs_no_sweep(orc):
+    row_ptr, target, lo, hi, cls = _self_loop_choice("reach")
+    cls = np.array([1, 1], np.int8)
+    r = orc.iterate(2, 2, row_ptr, target, lo, hi, cls, "reach", 1e-8, 1, horizon=5)
+    assert r["sweeps"] == (0, 0) and r["status"] == 0
+    assert (r["lo"] == 1).all() and (r["hi"] == 1).all()
