@@ -168,12 +168,20 @@ enum { IMPACT_SAFETY = 0, IMPACT_REACH = 1, IMPACT_REACH_AVOID = 2 };
  * favourable one), 0 for the optimistic policy (optimised on the favourable
  * LP, fixed for the adversarial one); any other value is E_INVAL.  Either
  * way lo is the lower and hi the upper satisfaction bound under the policy.
- * max_sweeps >= 1 caps each of the two passes. */
+ * max_sweeps >= 1 caps each of the two passes.
+ * horizon: 0 for the infinite-horizon properties; T > 0 for the finite
+ * horizon of Remark 5.1: each pass runs exactly T sweeps with no stop test
+ * (eps and max_sweeps unused beyond validation; no sweep without SAFE
+ * cells), value iteration from zero, so lo and hi are the T-step bounds
+ * taken from the V0 iterate of the adversarial and the favourable pass; the
+ * policy is the optimising input of the last policy-pass sweep, held for the
+ * fixed-input pass; negative is E_INVAL. */
 typedef struct {
   int32_t kind, n_target, n_avoid;
   const double *target_boxes, *avoid_boxes;
   int32_t pessimistic;
   int64_t max_sweeps;
+  int64_t horizon;
 } impact_spec;
 
 /*
@@ -199,7 +207,8 @@ int impact_interval_iterate(impact_imdp *imdp, const impact_spec *spec, double e
 typedef struct {
   int64_t sweeps[2];    /* sweeps run in pass 1 / pass 2                 */
   double gap[2];        /* max(V1 - V0) over SAFE cells at the end       */
-  int32_t converged[2]; /* 1 if the pass met eps                         */
+  int32_t converged[2]; /* 1 if the pass met eps (finite horizon: ran
+                           its T sweeps)                                 */
   int64_t n_safe;       /* number of SAFE cells                          */
   int64_t updates[2];   /* (s,u)-row LP pairs solved per pass            */
   int64_t launches[2];  /* sweep-kernel launches per pass (a launch after

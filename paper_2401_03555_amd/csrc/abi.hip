@@ -541,6 +541,7 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
   if (spec->pessimistic != 0 && spec->pessimistic != 1)
     return fail(IMPACT_E_INVAL, "pessimistic must be 0 or 1");
   if (spec->max_sweeps < 1) return fail(IMPACT_E_INVAL, "max_sweeps must be >= 1");
+  if (spec->horizon < 0) return fail(IMPACT_E_INVAL, "horizon must be >= 0");
   if (!is_finite(eps) || !(eps > 0.0)) return fail(IMPACT_E_INVAL, "eps must be finite and > 0");
   const int d = h->d;
   for (int64_t k = 0; k < (int64_t)spec->n_target * 2 * d; ++k)
@@ -643,10 +644,15 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       a.states_per_block = G;
 
       HIP_TRY(launch_init_values(cls, N, safety, vb[0], vb[1], pass == 0 ? pi : nullptr, h->st));
-      HIP_TRY(launch_ctrl_init(ctrl, eps, spec->max_sweeps, h->st));
+      // finite horizon: the device stop test never fires (gap >= 0 > -1) and
+      // the cap is the horizon
+      const bool finite = spec->horizon > 0;
+      const double eps_dev = finite ? -1.0 : eps;
+      const int64_t cap = finite ? spec->horizon : spec->max_sweeps;
+      HIP_TRY(launch_ctrl_init(ctrl, eps_dev, cap, h->st));
       int64_t sweeps = 0, launched = 0;
       double gap = n_safe > 0 ? 1.0 : 0.0;
-      int converged = gap <= eps;
+      int converged = finite ? n_safe == 0 : gap <= eps;
       float sweep_ms = 0.f, launch_ms = 0.f;
       if (!converged) {
         // Sweeps go out in batches between host polls of the control block.
@@ -658,7 +664,7 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
         double prev_gap = 1.0;
         std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
         for (;;) {
-          const int64_t n = std::min<int64_t>(chunk, spec->max_sweeps - launched);
+          const int64_t n = std::min<int64_t>(chunk, cap - launched);
           if (n <= 0) break;
           const auto c0 = std::chrono::steady_clock::now();
           for (int64_t k = 0; k < n; ++k) {
@@ -689,7 +695,7 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
               std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0)
                   .count() / (double)n;
           int64_t next = (int64_t)std::max(1.0, std::min(256.0, 2.0 / std::max(per_sweep_ms, 1e-3)));
-          if (hc.sweeps > prev_sweeps && hc.gap > 0.0 && hc.gap < prev_gap) {
+          if (!finite && hc.sweeps > prev_sweeps && hc.gap > 0.0 && hc.gap < prev_gap) {
             const double rate = std::pow(hc.gap / prev_gap, 1.0 / (double)(hc.sweeps - prev_sweeps));
             if (rate > 0.0 && rate < 1.0) {
               const double need = std::ceil(std::log(eps / hc.gap) / std::log(rate));
@@ -702,7 +708,7 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
         }
         sweeps = hc.sweeps;
         gap = hc.gap;
-        converged = hc.converged;
+        converged = finite ? hc.sweeps == cap : hc.converged;
         for (int64_t k = 0; k < (int64_t)marks.size(); ++k) {
           const float ms = event_ms(marks[k].first, marks[k].second);
           launch_ms += ms;
@@ -716,7 +722,7 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       info.sweep_ms[pass] = sweep_ms;
       info.launch_ms[pass] = launch_ms;
       info.launches[pass] = launched;
-      HIP_TRY(launch_finalize(cls, N, vb[sweeps & 1], pi, adverse ? 0 : 1, safety,
+      HIP_TRY(launch_finalize(cls, N, vb[sweeps & 1], pi, adverse ? 0 : 1, safety, finite,
                               adverse ? lo : hi, pass == 0 ? policy : nullptr, h->st));
     }
     HIP_TRY(hipStreamSynchronize(h->st));

@@ -51,6 +51,7 @@ struct QueryDesc {
   int32_t box_class;        // 1: state-box kernel class, 0: workgroup kernel class
   int32_t max_lp[2];        // LP direction of each pass (1: maximising)
   int32_t upper_first;      // 1: the policy pass yields the upper output (optimistic policy)
+  int32_t finite;           // 1: finite horizon (cap sweeps per pass, no stop test)
   double eps;
   int64_t cap;
   int64_t work_begin, work_end;  // its items in its class's work list
@@ -129,9 +130,10 @@ hipError_t launch_mq_sweep_block(const QueryDesc* desc, const QueryCtrl* ctrl, c
                                  const int32_t* ws, int64_t n_items, double* gap_item,
                                  int32_t max_row, hipStream_t st);
 // out = the lower (upper = 0) or upper (upper = 1) satisfaction bound of
-// every cell; policy (may be null) = pi on SAFE cells, -1 elsewhere.
+// every cell (finite = 1: from the V0 iterate of a finite-horizon pass);
+// policy (may be null) = pi on SAFE cells, -1 elsewhere.
 hipError_t launch_finalize(const int8_t* cls, int64_t n, const double2* v, const int32_t* pi,
-                           int32_t upper, int32_t safety, double* out, int32_t* policy,
-                           hipStream_t st);
+                           int32_t upper, int32_t safety, int32_t finite, double* out,
+                           int32_t* policy, hipStream_t st);
 
 }  // namespace impact

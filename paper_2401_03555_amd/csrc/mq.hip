@@ -55,6 +55,7 @@ __global__ __launch_bounds__(256) void k_mq_finish(const QueryDesc* __restrict__
       c.converged[pass] = 1;
       c.phase = phase + 1;
     } else if (c.sweeps[pass] >= D.cap) {
+      c.converged[pass] = D.finite;
       c.phase = phase + 1;
     }
   } else if (phase == 1) {
@@ -401,6 +402,7 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
   if (spec->pessimistic != 0 && spec->pessimistic != 1)
     return mq_fail(IMPACT_E_INVAL, "pessimistic must be 0 or 1");
   if (spec->max_sweeps < 1) return mq_fail(IMPACT_E_INVAL, "max_sweeps must be >= 1");
+  if (spec->horizon < 0) return mq_fail(IMPACT_E_INVAL, "horizon must be >= 0");
   if (!std::isfinite(eps) || !(eps > 0.0)) return mq_fail(IMPACT_E_INVAL, "eps must be > 0");
   ImdpView v;
   if (imdp_view(h, &v) != IMPACT_OK) return mq_fail(IMPACT_E_INVAL, "bad abstraction handle");
@@ -471,8 +473,8 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
     MQ_TRY(launch_compact(cls, pos, N, safe, m->st));
     MQ_TRY(launch_init_values(cls, N, safety, vb0, vb1, pi, m->st));
     // outputs of non-SAFE cells now (SAFE cells are written when the passes close)
-    MQ_TRY(launch_finalize(cls, N, vb0, pi, 0, safety, lo, policy, m->st));
-    MQ_TRY(launch_finalize(cls, N, vb0, pi, 1, safety, hi, nullptr, m->st));
+    MQ_TRY(launch_finalize(cls, N, vb0, pi, 0, safety, 0, lo, policy, m->st));
+    MQ_TRY(launch_finalize(cls, N, vb0, pi, 1, safety, 0, hi, nullptr, m->st));
     QueryDesc D;
     std::memset(&D, 0, sizeof(D));
     D.a = v.a;
@@ -491,8 +493,10 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
     D.max_lp[0] = spec->pessimistic ? safety : !safety;
     D.max_lp[1] = spec->pessimistic ? !safety : safety;
     D.box_class = v.max_row <= 512;
-    D.eps = eps;
-    D.cap = spec->max_sweeps;
+    // finite horizon: no stop test (gap >= 0 > -1), exactly `horizon` sweeps per pass
+    D.finite = spec->horizon > 0;
+    D.eps = D.finite ? -1.0 : eps;
+    D.cap = D.finite ? spec->horizon : spec->max_sweeps;
     QueryCtrl c;
     std::memset(&c, 0, sizeof(c));
     c.gap[0] = c.gap[1] = n_safe > 0 ? 1.0 : 0.0;
@@ -500,8 +504,8 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
       c.phase = 4;  // nothing to iterate: outputs are final
       c.converged[0] = c.converged[1] = 1;
     } else {
-      c.phase = 1.0 <= eps ? 1 : 0;
-      c.converged[0] = 1.0 <= eps;
+      c.phase = 1.0 <= D.eps ? 1 : 0;
+      c.converged[0] = 1.0 <= D.eps;
     }
     MQ_TRY(hipMemcpyAsync(m->d_ctrl + k, &c, sizeof(c), hipMemcpyHostToDevice, m->st));
     MQ_TRY(hipStreamSynchronize(m->st));

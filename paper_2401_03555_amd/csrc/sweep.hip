@@ -453,10 +453,11 @@ __global__ void k_init_values(const int8_t* __restrict__ cls, int64_t n, int32_t
 // Outputs: pass 0 writes lo and the policy, pass 1 writes hi.
 __global__ void k_finalize(const int8_t* __restrict__ cls, int64_t n, const double2* __restrict__ v,
                            const int32_t* __restrict__ pi, int32_t upper, int32_t safety,
-                           double* __restrict__ out, int32_t* __restrict__ policy) {
+                           int32_t finite, double* __restrict__ out,
+                           int32_t* __restrict__ policy) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
-  out[s] = cls[s] == kSafe ? bound_of(v[s], upper != 0, safety != 0)
+  out[s] = cls[s] == kSafe ? bound_of(v[s], upper != 0, safety != 0, finite != 0)
                            : (cls[s] == kTarget ? 1.0 : 0.0);
   if (policy) policy[s] = cls[s] == kSafe ? pi[s] : -1;
 }
@@ -549,11 +550,11 @@ int64_t sweep_blocks(const SweepArgs& a, bool box_path) {
 }
 
 hipError_t launch_finalize(const int8_t* cls, int64_t n, const double2* v, const int32_t* pi,
-                           int32_t upper, int32_t safety, double* out, int32_t* policy,
-                           hipStream_t st) {
+                           int32_t upper, int32_t safety, int32_t finite, double* out,
+                           int32_t* policy, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, st, cls, n, v, pi, upper,
-                     safety, out, policy);
+                     safety, finite, out, policy);
   return hipGetLastError();
 }
 

@@ -516,7 +516,9 @@ __device__ void solve_row_g(const SweepArgs& a, const SysParams& p, int64_t row,
 // Satisfaction bound of a SAFE state from its converged (V0, V1): the
 // adversarial pass gives the lower bound (reach: V0; safety, whose values are
 // probabilities of the bad set: 1 - V1), the favourable pass the upper bound.
-__device__ __forceinline__ double bound_of(double2 V, bool upper, bool safety) {
+// Finite horizon: value iteration, both bounds from the V0 iterate.
+__device__ __forceinline__ double bound_of(double2 V, bool upper, bool safety, bool finite) {
+  if (finite) return safety ? 1.0 - V.x : V.x;
   return upper ? (safety ? 1.0 - V.x : V.y) : (safety ? 1.0 - V.y : V.x);
 }
 
@@ -529,7 +531,7 @@ __device__ __forceinline__ void mq_close_state(const QueryDesc& D, int64_t step,
   double2* vout = (step & 1) ? D.vb0 : D.vb1;
   const double2 V = vin[s];
   const bool upper = (phase == 1) == (D.upper_first != 0);
-  (upper ? D.hi : D.lo)[s] = bound_of(V, upper, D.safety != 0);
+  (upper ? D.hi : D.lo)[s] = bound_of(V, upper, D.safety != 0, D.finite != 0);
   if (phase == 1) {
     D.pol[s] = D.a.pi[s];
     vout[s] = make_double2(0.0, 1.0);

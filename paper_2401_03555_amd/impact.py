@@ -68,7 +68,7 @@ class Device(C.Structure):
 class Spec(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_target", C.c_int32), ("n_avoid", C.c_int32),
                 ("target_boxes", _pd), ("avoid_boxes", _pd), ("pessimistic", C.c_int32),
-                ("max_sweeps", C.c_int64)]
+                ("max_sweeps", C.c_int64), ("horizon", C.c_int64)]
 
 
 class IterInfo(C.Structure):
@@ -280,7 +280,8 @@ class Imdp:
         s = Spec(SPEC_KINDS[spec["kind"]], tb.shape[0], ab.shape[0],
                  _dptr(tb) if tb.size else None, _dptr(ab) if ab.size else None,
                  int(bool(spec.get("pessimistic", True))),
-                 int(max_sweeps if max_sweeps is not None else spec.get("max_sweeps", 100000)))
+                 int(max_sweeps if max_sweeps is not None else spec.get("max_sweeps", 100000)),
+                 int(spec.get("horizon", 0)))
         dev = f"cuda:{self._dev.device}"
         if out is None:
             lo = torch.empty(n, dtype=torch.float64, device=dev)
@@ -343,7 +344,8 @@ def _spec_struct(spec, d, max_sweeps=None):
     s = Spec(SPEC_KINDS[spec["kind"]], tb.shape[0], ab.shape[0],
              _dptr(tb) if tb.size else None, _dptr(ab) if ab.size else None,
              int(bool(spec.get("pessimistic", True))),
-             int(max_sweeps if max_sweeps is not None else spec.get("max_sweeps", 100000)))
+             int(max_sweeps if max_sweeps is not None else spec.get("max_sweeps", 100000)),
+             int(spec.get("horizon", 0)))
     return s, (tb, ab)
 
 

@@ -11,7 +11,8 @@ System dict keys: ``kind`` ("affine" | "unicycle"), ``A``, ``B``, ``c`` (affine)
 standard deviations; 0 means dense rows).
 Spec dict keys: ``kind`` ("safety" | "reach" | "reach_avoid"), ``target``,
 ``avoid`` (lists of [lo, hi] boxes), ``eps``, ``max_sweeps``, optionally
-``pessimistic`` (default true; false: optimistic policy).
+``pessimistic`` (default true; false: optimistic policy) and ``horizon``
+(default 0: infinite horizon; T > 0: T sweeps of value iteration per pass).
 """
 import itertools
 import math

@@ -167,3 +167,19 @@ def test_engine_reuses_slots_and_handles_degenerate_queries(I):
     r = eng.run_all()[q]
     plain = imdp.iterate(dict(spec, eps=2.0))
     _same(r, plain, "eps >= 1")
+
+
+@pytest.mark.parametrize("pessimistic", [True, False], ids=["pess", "opt"])
+def test_engine_finite_horizon_equals_plain_iterate(I, pessimistic):
+    imdps, specs = [], []
+    for name, make, spec in CASES:
+        imdps.append(_engine_modes(I.build_imdp(make())))
+        specs.append(dict(spec, horizon=5 + len(specs), pessimistic=pessimistic))
+    plain = [im.iterate(sp) for im, sp in zip(imdps, specs)]
+    eng = I.Engine(max_queries=len(CASES))
+    ids = [eng.submit(im, sp) for im, sp in zip(imdps, specs)]
+    res = eng.run_all()
+    for qid, p, (name, _, _), sp in zip(ids, plain, CASES, specs):
+        _same(res[qid], p, f"{name} T={sp['horizon']}")
+        assert res[qid]["status"] == p["status"] == 0
+        assert tuple(res[qid]["info"]["sweeps"]) == (sp["horizon"], sp["horizon"])

@@ -97,7 +97,8 @@ def fixed_pass_under(m, cls, spec, policy, optimistic):
     idx = np.concatenate([np.arange(a, b) for a, b in zip(starts, ends)])
     new_rp = np.concatenate([[0], np.cumsum(ends - starts)]).astype(np.int64)
     return oracle.iterate(N, 1, new_rp, m["target"][idx], m["lo"][idx], m["hi"][idx], cls,
-                          spec["kind"], spec["eps"], spec["max_sweeps"], optimistic=optimistic)
+                          spec["kind"], spec["eps"], spec["max_sweeps"], optimistic=optimistic,
+                          horizon=spec.get("horizon", 0))
 
 
 def compare_iter(g, o, cls, reach, label, q0=None, model=None, spec=None, optimistic=False):
@@ -476,3 +477,66 @@ def test_optimistic_and_pessimistic_policies_differ_where_choice_matters(I):
     assert (ohi >= phi - tol).all()
     assert (ohi - phi).max() > 1e3 * tol
     assert (rp["policy"] != ro["policy"]).any()
+
+
+# ---------------------------------------------------------------------------
+# finite horizon (Remark 5.1): T sweeps of value iteration per pass
+# ---------------------------------------------------------------------------
+
+FH_CASES = ["affine2_window", "affine3_window", "affine2_dense", "unicycle_small"]
+
+
+@pytest.mark.parametrize("mode", ["per_row", "state_box"])
+@pytest.mark.parametrize("pessimistic", [True, False], ids=["pess", "opt"])
+@pytest.mark.parametrize("name", FH_CASES)
+def test_finite_horizon_matches_oracle(I, name, pessimistic, mode):
+    system = SMALL_SYSTEMS[name]()
+    T = 7
+    spec = dict(SPECS[name], eps=1e-8, max_sweeps=1, horizon=T, pessimistic=pessimistic)
+    say(f"finite horizon T={T}: {name} {spec['kind']} pessimistic={pessimistic} [{mode}]")
+    g = I.build_imdp(system, sweep_mode=mode)
+    rg = g.iterate(spec)
+    m = oracle.build(system, system["k_sigma"])
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    ro = oracle.iterate(m["n_states"], m["n_inputs"], m["row_ptr"], m["target"], m["lo"], m["hi"],
+                        cls, spec["kind"], spec["eps"], 1, want_q0=True,
+                        optimistic=not pessimistic, horizon=T)
+    assert rg["status"] == ro["status"] == 0
+    assert tuple(rg["info"]["sweeps"]) == (T, T)
+    compare_iter(rg, ro, cls, spec["kind"] != "safety", f"{name} T={T}", q0=ro["q0"],
+                 model=m, spec=spec, optimistic=not pessimistic)
+
+
+def test_finite_horizon_full_size_unicycle(I):
+    system, spec = W.unicycle3d()
+    T = 3
+    spec = dict(spec, horizon=T)
+    say(f"unicycle3d full size, finite horizon T={T}")
+    g = gpu_build(I, system, "factors")
+    rg = g.iterate(spec)
+    m = oracle.build(system, system["k_sigma"])
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    ro = oracle.iterate(m["n_states"], m["n_inputs"], m["row_ptr"], m["target"], m["lo"], m["hi"],
+                        cls, spec["kind"], spec["eps"], 1, want_q0=True, horizon=T)
+    assert rg["status"] == ro["status"] == 0
+    compare_iter(rg, ro, cls, True, f"unicycle3d T={T}", q0=ro["q0"], model=m, spec=spec)
+
+
+def test_finite_horizon_degenerate_cases(I):
+    system = SMALL_SYSTEMS["affine2_window"]()
+    g = gpu_build(I, system)
+    # no SAFE cell: nothing to sweep, whatever the horizon
+    everything = [[[-100.0, -100.0], [100.0, 100.0]]]
+    r = g.iterate(dict(kind="reach", target=everything, avoid=[], eps=1e-8, max_sweeps=1,
+                       horizon=9))
+    assert r["status"] == 0 and tuple(r["info"]["sweeps"]) == (0, 0)
+    assert bool((r["lo"] == 1).all()) and bool((r["hi"] == 1).all())
+    # T = 1: one sweep from zero is the one-step probability; both passes agree
+    # with the infinite-horizon call capped at one sweep on the V0 side
+    spec = dict(SPECS["affine2_window"], eps=1e-8, max_sweeps=1)
+    one = g.iterate(dict(spec, horizon=1))
+    capped = g.iterate(spec)
+    assert tuple(one["info"]["sweeps"]) == (1, 1) and one["status"] == 0
+    assert bool((one["lo"] == capped["lo"]).all())
+    with pytest.raises(I.ImpactError, match="horizon"):
+        g.iterate(dict(spec, horizon=-1))
