@@ -88,7 +88,7 @@ def lib():
         L.orc_iterate.restype = C.c_int
         L.orc_iterate.argtypes = [i64, i32, C.POINTER(C.c_int64), C.POINTER(C.c_int32), pd, pd,
                                   C.POINTER(C.c_int8), i32, d, i64, pd, pd,
-                                  C.POINTER(C.c_int32), C.POINTER(_IterInfo), pd, i64, pd, pd, i32, i64]
+                                  C.POINTER(C.c_int32), C.POINTER(_IterInfo), pd, i64, pd, pd, i32, i64, i32]
         _lib = L
     return _lib
 
@@ -235,10 +235,12 @@ def lp_sorted(lo, hi, val, maximise):
 
 
 def iterate(n_states_, n_inputs, row_ptr, target, lo, hi, cls, spec_kind, eps, max_sweeps,
-            want_q0=False, hist_cap=0, optimistic=False, horizon=0):
+            want_q0=False, hist_cap=0, optimistic=False, horizon=0, self_stop=False):
     """Interval iteration (Alg. 3 / Alg. 4 with the sorting method); the
     policy is pessimistic (IMDP_lower = true, Sec. 5) unless ``optimistic``.
     ``horizon`` T > 0: finite horizon, T sweeps per pass (Remark 5.1).
+    ``self_stop``: each pass stops when both its iterates converge to
+    themselves (the first step of Remark 5.2).
 
     Returns dict(lo, hi, policy, status, sweeps, gap, converged, n_safe[, q0][, hist_v0, hist_v1]).
     """
@@ -260,7 +262,8 @@ def iterate(n_states_, n_inputs, row_ptr, target, lo, hi, cls, spec_kind, eps, m
         cls.ctypes.data_as(C.POINTER(C.c_int8)), spec_kind, float(eps), int(max_sweeps),
         _dptr(out_lo), _dptr(out_hi), pol.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(info),
         _dptr(q0) if want_q0 else None, hist_cap, _dptr(h0) if hist_cap else None,
-        _dptr(h1) if hist_cap else None, int(bool(optimistic)), int(horizon))
+        _dptr(h1) if hist_cap else None, int(bool(optimistic)), int(horizon),
+        int(bool(self_stop)))
     if rc < 0:
         raise ValueError(f"oracle iterate rejected its input ({rc})")
     res = dict(lo=out_lo, hi=out_hi, policy=pol, status=rc, sweeps=tuple(info.sweeps),
@@ -270,6 +273,22 @@ def iterate(n_states_, n_inputs, row_ptr, target, lo, hi, cls, spec_kind, eps, m
     if hist_cap:
         res["hist_v0"], res["hist_v1"] = h0, h1
     return res
+
+
+def iterate_auto_horizon(n_states_, n_inputs, row_ptr, target, lo, hi, cls, spec_kind, eps,
+                         max_sweeps, **kw):
+    """Remark 5.2 for runs whose two bounds need not meet: the sweeps each pass
+    needs for both of its iterates to converge to themselves; the larger count
+    K is the horizon of a finite-horizon (value iteration) run, returned with
+    ``horizon`` = K, ``self_sweeps`` and the self runs' ``converged``/``status``.
+    """
+    args = (n_states_, n_inputs, row_ptr, target, lo, hi, cls, spec_kind, eps, max_sweeps)
+    first = iterate(*args, self_stop=True, **kw)
+    K = max(1, max(first["sweeps"]))
+    r = iterate(*args, horizon=K, **kw)
+    r.update(horizon=K, self_sweeps=first["sweeps"], converged=first["converged"],
+             status=first["status"])
+    return r
 
 
 def solve(system, k_sigma, spec_kind, target_boxes, avoid_boxes, eps, max_sweeps, **kw):

@@ -599,6 +599,10 @@ static double max_gap(int64_t n, const int8_t *cls, const double *V0, const doub
  * favourable one; safety: 1 - V0 of each).  The policy is the optimising
  * input of the last pass-1 sweep (the first decision of the T-step game),
  * held fixed for pass 2, as above.
+ * self_stop (Remark 5.2, with horizon = 0): each pass instead stops once both
+ * of its iterates converge to themselves, max_S max(|V0' - V0|, |V1' - V1|)
+ * <= eps after a sweep (at least one sweep when S is not empty; at most
+ * max_sweeps); info->gap then holds that last move.
  * Returns 0 if both passes met eps (or ran their T sweeps), 1 if a cap
  * fired, < 0 on bad input.
  */
@@ -608,8 +612,9 @@ int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
                 int64_t max_sweeps, double *out_lo, double *out_hi,
                 int32_t *policy, orc_iter_info *info, double *q0_last,
                 int64_t hist_cap, double *hist_v0, double *hist_v1,
-                int32_t optimistic, int64_t horizon) {
+                int32_t optimistic, int64_t horizon, int32_t self_stop) {
   if (n_inputs < 1 || max_sweeps < 1 || !(eps > 0.0) || horizon < 0) return -1;
+  if (self_stop && horizon > 0) return -1;
   int64_t n_safe = 0, max_len = 1;
   for (int64_t s = 0; s < n_states; ++s) {
     if (spec_kind == ORC_SAFETY && cls[s] == ORC_TARGET) return -1;
@@ -641,13 +646,24 @@ int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
       V1[s] = 1.0;
     }
     int64_t sweeps = 0;
-    double gap;
+    double gap, last_delta = 0.0;
     int converged;
     for (;;) {
       gap = n_safe > 0 ? max_gap(n_states, cls, V0, V1) : 0.0;
+      if (self_stop)
+        gap = last_delta;
       if (horizon > 0) {
         if (n_safe == 0 || sweeps >= horizon) {
           converged = 1;
+          break;
+        }
+      } else if (self_stop) {
+        if (n_safe == 0 || (sweeps > 0 && last_delta <= eps)) {
+          converged = 1;
+          break;
+        }
+        if (sweeps >= max_sweeps) {
+          converged = 0;
           break;
         }
       } else if (gap <= eps) {
@@ -688,11 +704,14 @@ int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
           N1[s] = row_lp(row_ptr, target, lo, hi, cls, V1, spec_kind, maximise, r, vb);
         }
       }
+      double delta = 0.0; /* largest move of either iterate in this sweep */
       for (int64_t s = 0; s < n_states; ++s) {
         if (cls[s] != ORC_SAFE) continue;
+        delta = fmax(delta, fmax(fabs(N0[s] - V0[s]), fabs(N1[s] - V1[s])));
         V0[s] = N0[s];
         V1[s] = N1[s];
       }
+      last_delta = delta;
       if (pass == 0 && sweeps < hist_cap) {
         if (hist_v0) memcpy(hist_v0 + sweeps * n_states, V0, sizeof(double) * (size_t)n_states);
         if (hist_v1) memcpy(hist_v1 + sweeps * n_states, V1, sizeof(double) * (size_t)n_states);

@@ -807,3 +807,57 @@ def test_finite_horizon_without_safe_states_runs_no_sweep(orc):
     r = orc.iterate(2, 2, row_ptr, target, lo, hi, cls, "reach", 1e-8, 1, horizon=5)
     assert r["sweeps"] == (0, 0) and r["status"] == 0
     assert (r["lo"] == 1).all() and (r["hi"] == 1).all()
+
+
+# --------------------------------------------------------------------------
+# Remark 5.2: horizon from the self-convergence of each iterate
+# --------------------------------------------------------------------------
+
+def _first_k(move, eps=1e-8):
+    # first sweep k >= 1 whose move (a closed form in k) is at most eps
+    return next(k for k in range(1, 100000) if move(k) <= eps)
+
+
+def test_self_stop_worked_reach_avoid(orc):
+    # the single-state chain of the worked reach-avoid example: pass 1
+    # V' = .1 + .4 V moves V0 by .1 * .4^(k-1) and V1 (from 1) by .5 * .4^(k-1);
+    # pass 2 V' = .3 + .5 V moves V0 by .3 * .5^(k-1), V1 by .2 * .5^(k-1)
+    row_ptr, cls = [0, 3, 3, 3], np.array([0, 1, 2], np.int8)
+    args = (3, 1, row_ptr, [0, 1, 2], [.3, .1, .2], [.6, .3, .5], cls, "reach_avoid", 1e-8, 1000)
+    k1 = _first_k(lambda k: .5 * .4 ** (k - 1))
+    k2 = _first_k(lambda k: .3 * .5 ** (k - 1))
+    r = orc.iterate(*args, self_stop=True)
+    assert r["sweeps"] == (k1, k2) and r["converged"] == (1, 1)
+    assert r["gap"][0] == pytest.approx(.5 * .4 ** (k1 - 1), rel=1e-9)
+    a = orc.iterate_auto_horizon(*args)
+    K = max(k1, k2)
+    assert a["horizon"] == K and a["sweeps"] == (K, K) and a["self_sweeps"] == (k1, k2)
+    assert a["status"] == 0
+    assert a["lo"][0] == pytest.approx((1 - .4 ** K) / 6, abs=1e-15)
+    assert a["hi"][0] == pytest.approx(.6 * (1 - .5 ** K), abs=1e-15)
+
+
+def test_auto_horizon_where_the_bounds_never_meet(orc):
+    # the non-converging safety chain: self in [.9, 1], OUT in [0, .1].  Pass 1
+    # (bad mass maximised): V' = .1 + .9 V moves V0 by .1 * .9^(k-1) while V1
+    # stays at 1; pass 2 (minimised): nothing moves, so one sweep.  The horizon
+    # is pass 1's count K, and the K-step bounds are .9^K (the adversary leaves
+    # with .1 each step) and 1 (it never leaves).
+    args = (1, 1, [0, 2], [0, -1], [.9, 0.0], [1.0, .1], np.array([0], np.int8), "safety",
+            1e-8, 500)
+    K = _first_k(lambda k: .1 * .9 ** (k - 1))
+    a = orc.iterate_auto_horizon(*args)
+    assert a["self_sweeps"] == (K, 1) and a["horizon"] == K and a["status"] == 0
+    assert a["lo"][0] == pytest.approx(.9 ** K, rel=1e-12)
+    assert a["hi"][0] == 1.0
+    # the plain interval iteration hits its cap on the same chain
+    assert orc.iterate(*args)["status"] == 1
+
+
+def test_self_stop_cap_and_empty_safe_set(orc):
+    args = (1, 1, [0, 2], [0, -1], [.9, 0.0], [1.0, .1], np.array([0], np.int8), "safety", 1e-8)
+    r = orc.iterate(*args, 50, self_stop=True)
+    assert r["sweeps"] == (50, 1) and r["converged"] == (0, 1) and r["status"] == 1
+    r = orc.iterate(1, 1, [0, 2], [0, -1], [.9, 0.0], [1.0, .1], np.array([2], np.int8), "safety",
+                    1e-8, 50, self_stop=True)
+    assert r["sweeps"] == (0, 0) and r["status"] == 0
