@@ -175,7 +175,15 @@ enum { IMPACT_SAFETY = 0, IMPACT_REACH = 1, IMPACT_REACH_AVOID = 2 };
  * cells), value iteration from zero, so lo and hi are the T-step bounds
  * taken from the V0 iterate of the adversarial and the favourable pass; the
  * policy is the optimising input of the last policy-pass sweep, held for the
- * fixed-input pass; negative is E_INVAL. */
+ * fixed-input pass.  IMPACT_HORIZON_AUTO (-1): the procedure of Remark 5.2
+ * for runs whose two bounds need not meet: both passes first run until each
+ * of their two iterates converges to itself, max(|V0' - V0|, |V1' - V1|) <=
+ * eps over the SAFE cells after a sweep (at most max_sweeps sweeps); the
+ * larger of the two sweep counts K is then the horizon of a finite-horizon
+ * run as above, whose bounds and policy are returned (statistics: sweeps =
+ * K per pass, self_sweeps = the two counts, converged = whether each pass's
+ * iterates converged before the cap).  Any other negative value is E_INVAL. */
+enum { IMPACT_HORIZON_AUTO = -1 };
 typedef struct {
   int32_t kind, n_target, n_avoid;
   const double *target_boxes, *avoid_boxes;
@@ -217,6 +225,12 @@ typedef struct {
                            (timing on; else 0)                           */
   double launch_ms[2];  /* HIP-event time of every sweep launch (timing on) */
   double iterate_ms;    /* host wall time of the call                    */
+  int64_t horizon;      /* horizon of the returned run: 0 infinite, else
+                           the T (or K of IMPACT_HORIZON_AUTO) swept      */
+  int64_t self_sweeps[2]; /* IMPACT_HORIZON_AUTO: sweeps until each pass's
+                           iterates converged to themselves; else 0      */
+  double self_sweep_ms; /* IMPACT_HORIZON_AUTO: HIP-event time of those
+                           sweeps (timing on); else 0                    */
 } impact_iter_info;
 
 int impact_last_iter_info(const impact_imdp *imdp, impact_iter_info *info);

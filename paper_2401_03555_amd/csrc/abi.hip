@@ -541,7 +541,8 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
   if (spec->pessimistic != 0 && spec->pessimistic != 1)
     return fail(IMPACT_E_INVAL, "pessimistic must be 0 or 1");
   if (spec->max_sweeps < 1) return fail(IMPACT_E_INVAL, "max_sweeps must be >= 1");
-  if (spec->horizon < 0) return fail(IMPACT_E_INVAL, "horizon must be >= 0");
+  if (spec->horizon < IMPACT_HORIZON_AUTO)
+    return fail(IMPACT_E_INVAL, "horizon must be >= 0 or IMPACT_HORIZON_AUTO");
   if (!is_finite(eps) || !(eps > 0.0)) return fail(IMPACT_E_INVAL, "eps must be finite and > 0");
   const int d = h->d;
   for (int64_t k = 0; k < (int64_t)spec->n_target * 2 * d; ++k)
@@ -599,6 +600,10 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       return e;
     };
     Ctrl hc{};
+    // Both passes under one stop rule: self_rule stops a pass once both its
+    // iterates stop moving (Remark 5.2); otherwise the gap rule, or exactly
+    // `horizon` sweeps when horizon > 0 (Remark 5.1).
+    auto run_passes = [&](bool self_rule, int64_t horizon) -> int {
     for (int pass = 0; pass < 2; ++pass) {
       // policy pass: one sort per state over its rows' window box when every
       // row fits a wavefront; the fixed-input pass has one row per state and
@@ -646,13 +651,15 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       HIP_TRY(launch_init_values(cls, N, safety, vb[0], vb[1], pass == 0 ? pi : nullptr, h->st));
       // finite horizon: the device stop test never fires (gap >= 0 > -1) and
       // the cap is the horizon
-      const bool finite = spec->horizon > 0;
+      const bool finite = horizon > 0;
       const double eps_dev = finite ? -1.0 : eps;
-      const int64_t cap = finite ? spec->horizon : spec->max_sweeps;
+      const int64_t cap = finite ? horizon : spec->max_sweeps;
+      // workgroups of the self-convergence measure (within gap_part's N slots)
+      const int64_t n_delta = std::min<int64_t>(1024, (n_safe + 255) / 256);
       HIP_TRY(launch_ctrl_init(ctrl, eps_dev, cap, h->st));
       int64_t sweeps = 0, launched = 0;
       double gap = n_safe > 0 ? 1.0 : 0.0;
-      int converged = finite ? n_safe == 0 : gap <= eps;
+      int converged = (finite || self_rule) ? n_safe == 0 : gap <= eps;
       float sweep_ms = 0.f, launch_ms = 0.f;
       if (!converged) {
         // Sweeps go out in batches between host polls of the control block.
@@ -685,7 +692,13 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
               HIP_TRY(hipEventRecord(e1, h->st));
               marks.emplace_back(e0, e1);
             }
-            HIP_TRY(launch_finish(ctrl, gap_part, sweep_blocks(a, use_box), h->st));
+            if (self_rule) {
+              HIP_TRY(launch_self_delta(ctrl, safe, n_safe, a.vin, a.vout, gap_part, n_delta,
+                                        h->st));
+              HIP_TRY(launch_finish(ctrl, gap_part, n_delta, h->st));
+            } else {
+              HIP_TRY(launch_finish(ctrl, gap_part, sweep_blocks(a, use_box), h->st));
+            }
           }
           launched += n;
           HIP_TRY(hipMemcpyAsync(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->st));
@@ -724,6 +737,29 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       info.launches[pass] = launched;
       HIP_TRY(launch_finalize(cls, N, vb[sweeps & 1], pi, adverse ? 0 : 1, safety, finite,
                               adverse ? lo : hi, pass == 0 ? policy : nullptr, h->st));
+    }
+    info.horizon = horizon;
+    return IMPACT_OK;
+    };
+    int rc;
+    if (spec->horizon == IMPACT_HORIZON_AUTO) {
+      // Remark 5.2: the sweeps each pass needs for both of its iterates to
+      // converge to themselves; the larger count is the horizon of a
+      // value-iteration run, whose outputs are returned
+      if ((rc = run_passes(true, 0)) < 0) return rc;
+      const int64_t s0 = info.sweeps[0], s1 = info.sweeps[1];
+      const int32_t c0 = info.converged[0], c1 = info.converged[1];
+      const double self_ms = info.sweep_ms[0] + info.sweep_ms[1];
+      info = impact_iter_info{};
+      info.n_safe = n_safe;
+      if ((rc = run_passes(false, std::max<int64_t>(1, std::max(s0, s1)))) < 0) return rc;
+      info.self_sweeps[0] = s0;
+      info.self_sweeps[1] = s1;
+      info.converged[0] = c0;
+      info.converged[1] = c1;
+      info.self_sweep_ms = self_ms;
+    } else if ((rc = run_passes(false, spec->horizon)) < 0) {
+      return rc;
     }
     HIP_TRY(hipStreamSynchronize(h->st));
     for (hipEvent_t e : evs) (void)hipEventDestroy(e);

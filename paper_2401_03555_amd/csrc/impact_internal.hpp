@@ -115,6 +115,12 @@ hipError_t launch_sweep_sb(const SweepArgs& a, int64_t max_box, int32_t max_row,
 hipError_t launch_state_box_max(const BuildTable& T, int64_t n_states, const int32_t* win,
                                 unsigned long long* out, hipStream_t st);
 hipError_t launch_finish(Ctrl* c, const double* part, int64_t n_part, hipStream_t st);
+// part[0, n_part) = per-workgroup max(|V0' - V0|, |V1' - V1|) over the SAFE
+// states of one sweep from vin to vout (n_part workgroups of 256 threads;
+// nothing if the control block is done).
+hipError_t launch_self_delta(const Ctrl* c, const int32_t* safe, int64_t n_safe,
+                             const double2* vin, const double2* vout, double* part, int64_t n_part,
+                             hipStream_t st);
 constexpr int kSbWavesPerBlock = 2;  // state-box sweep: wavefronts (= states) per workgroup
 int64_t sweep_blocks(const SweepArgs& a, bool box_path);
 

@@ -402,6 +402,8 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
   if (spec->pessimistic != 0 && spec->pessimistic != 1)
     return mq_fail(IMPACT_E_INVAL, "pessimistic must be 0 or 1");
   if (spec->max_sweeps < 1) return mq_fail(IMPACT_E_INVAL, "max_sweeps must be >= 1");
+  if (spec->horizon == IMPACT_HORIZON_AUTO)
+    return mq_fail(IMPACT_E_UNSUPPORTED, "IMPACT_HORIZON_AUTO runs through impact_interval_iterate");
   if (spec->horizon < 0) return mq_fail(IMPACT_E_INVAL, "horizon must be >= 0");
   if (!std::isfinite(eps) || !(eps > 0.0)) return mq_fail(IMPACT_E_INVAL, "eps must be > 0");
   ImdpView v;
@@ -530,6 +532,7 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
       m->finished_info[q.id] = impact_iter_info{};
       m->finished_info[q.id].n_safe = 0;
       m->finished_info[q.id].converged[0] = m->finished_info[q.id].converged[1] = 1;
+      m->finished_info[q.id].horizon = D.finite ? D.cap : 0;
       m->slots[k].finished = true;
       m->unreported.push_back(q.id);
     } else {
@@ -587,6 +590,7 @@ int impact_mq_poll(impact_mq* m, int32_t* ids, int32_t cap, int32_t* n_out) {
         info.updates[p] = c[k].sweeps[p] * q.n_safe * (p == 0 ? q.nu : 1);
       }
       info.n_safe = q.n_safe;
+      info.horizon = m->h_desc[k].finite ? m->h_desc[k].cap : 0;
       m->finished_info[q.id] = info;
       q.finished = true;
       m->unreported.push_back(q.id);

@@ -381,6 +381,39 @@ __global__ __launch_bounds__(1024) void k_finish(Ctrl* c, const double* __restri
   }
 }
 
+// Self-convergence measure of one sweep (Remark 5.2): per workgroup, the
+// largest change of either iterate, max(|V0' - V0|, |V1' - V1|), over its
+// share of the SAFE states (grid-stride).
+__global__ __launch_bounds__(256) void k_self_delta(const Ctrl* __restrict__ c,
+                                                    const int32_t* __restrict__ safe,
+                                                    int64_t n_safe,
+                                                    const double2* __restrict__ vin,
+                                                    const double2* __restrict__ vout,
+                                                    double* __restrict__ part) {
+  __shared__ double wmax[4];
+  if (c->done) return;
+  double g = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_safe;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t s = safe[i];
+    const double2 o = vin[s], n = vout[s];
+    g = fmax(g, fmax(fabs(n.x - o.x), fabs(n.y - o.y)));
+  }
+  g = wave_max(g);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = g;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+}
+
+hipError_t launch_self_delta(const Ctrl* c, const int32_t* safe, int64_t n_safe,
+                             const double2* vin, const double2* vout, double* part, int64_t n_part,
+                             hipStream_t st) {
+  if (n_safe == 0 || n_part < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_self_delta, dim3((unsigned)n_part), dim3(256), 0, st, c, safe, n_safe, vin,
+                     vout, part);
+  return hipGetLastError();
+}
+
 __global__ void k_ctrl_init(Ctrl* c, double eps, int64_t cap) {
   if (threadIdx.x != 0) return;
   c->gap_bits = 0ull;

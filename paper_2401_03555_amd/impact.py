@@ -76,7 +76,8 @@ class IterInfo(C.Structure):
                 ("converged", C.c_int32 * 2), ("n_safe", C.c_int64),
                 ("updates", C.c_int64 * 2), ("launches", C.c_int64 * 2),
                 ("sweep_ms", C.c_double * 2), ("launch_ms", C.c_double * 2),
-                ("iterate_ms", C.c_double)]
+                ("iterate_ms", C.c_double), ("horizon", C.c_int64),
+                ("self_sweeps", C.c_int64 * 2), ("self_sweep_ms", C.c_double)]
 
 
 class ImdpInfo(C.Structure):
@@ -152,6 +153,14 @@ def lib():
         L.impact_mq_free.argtypes = [C.c_void_p]
         _lib = L
     return _lib
+
+
+HORIZON_AUTO = -1  # the two-step procedure for bounds that need not meet (Remark 5.2)
+
+
+def _horizon(spec):
+    h = spec.get("horizon", 0)
+    return HORIZON_AUTO if h == "auto" else int(h)
 
 
 def _check(rc):
@@ -281,7 +290,7 @@ class Imdp:
                  _dptr(tb) if tb.size else None, _dptr(ab) if ab.size else None,
                  int(bool(spec.get("pessimistic", True))),
                  int(max_sweeps if max_sweeps is not None else spec.get("max_sweeps", 100000)),
-                 int(spec.get("horizon", 0)))
+                 _horizon(spec))
         dev = f"cuda:{self._dev.device}"
         if out is None:
             lo = torch.empty(n, dtype=torch.float64, device=dev)
@@ -300,7 +309,8 @@ class Imdp:
         return dict(sweeps=tuple(i.sweeps), gap=tuple(i.gap), converged=tuple(i.converged),
                     n_safe=i.n_safe, updates=tuple(i.updates), launches=tuple(i.launches),
                     sweep_ms=tuple(i.sweep_ms), launch_ms=tuple(i.launch_ms),
-                    iterate_ms=i.iterate_ms)
+                    iterate_ms=i.iterate_ms, horizon=i.horizon,
+                    self_sweeps=tuple(i.self_sweeps), self_sweep_ms=i.self_sweep_ms)
 
     def free(self):
         if self._h:
@@ -345,7 +355,7 @@ def _spec_struct(spec, d, max_sweeps=None):
              _dptr(tb) if tb.size else None, _dptr(ab) if ab.size else None,
              int(bool(spec.get("pessimistic", True))),
              int(max_sweeps if max_sweeps is not None else spec.get("max_sweeps", 100000)),
-             int(spec.get("horizon", 0)))
+             _horizon(spec))
     return s, (tb, ab)
 
 
@@ -400,7 +410,7 @@ class Engine:
                              status=0 if (i.converged[0] and i.converged[1]) else 1,
                              info=dict(sweeps=tuple(i.sweeps), gap=tuple(i.gap),
                                        converged=tuple(i.converged), n_safe=i.n_safe,
-                                       updates=tuple(i.updates))))
+                                       updates=tuple(i.updates), horizon=i.horizon)))
         return done
 
     def run_all(self, chunk=64):

@@ -12,7 +12,8 @@ standard deviations; 0 means dense rows).
 Spec dict keys: ``kind`` ("safety" | "reach" | "reach_avoid"), ``target``,
 ``avoid`` (lists of [lo, hi] boxes), ``eps``, ``max_sweeps``, optionally
 ``pessimistic`` (default true; false: optimistic policy) and ``horizon``
-(default 0: infinite horizon; T > 0: T sweeps of value iteration per pass).
+(default 0: infinite horizon; T > 0: T sweeps of value iteration per pass;
+"auto": the horizon at which each pass's iterates converge to themselves).
 """
 import itertools
 import math

@@ -539,4 +539,37 @@ def test_finite_horizon_degenerate_cases(I):
     assert tuple(one["info"]["sweeps"]) == (1, 1) and one["status"] == 0
     assert bool((one["lo"] == capped["lo"]).all())
     with pytest.raises(I.ImpactError, match="horizon"):
-        g.iterate(dict(spec, horizon=-1))
+        g.iterate(dict(spec, horizon=-2))  # -1 is the automatic horizon
+
+
+# ---------------------------------------------------------------------------
+# Remark 5.2: horizon from the self-convergence of each pass's iterates
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("pessimistic", [True, False], ids=["pess", "opt"])
+@pytest.mark.parametrize("name", ["affine2_window", "affine2_dense", "unicycle_small"])
+def test_auto_horizon_matches_oracle(I, name, pessimistic):
+    system = SMALL_SYSTEMS[name]()
+    spec = dict(SPECS[name], eps=1e-8, max_sweeps=3000, horizon="auto", pessimistic=pessimistic)
+    say(f"auto horizon: {name} {spec['kind']} pessimistic={pessimistic}")
+    g = I.build_imdp(system)
+    rg = g.iterate(spec)
+    m = oracle.build(system, system["k_sigma"])
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    ro = oracle.iterate_auto_horizon(m["n_states"], m["n_inputs"], m["row_ptr"], m["target"],
+                                     m["lo"], m["hi"], cls, spec["kind"], spec["eps"],
+                                     spec["max_sweeps"], want_q0=True, optimistic=not pessimistic)
+    info = rg["info"]
+    say(f"  self sweeps gpu {info['self_sweeps']} oracle {ro['self_sweeps']}, K {ro['horizon']}")
+    assert tuple(info["self_sweeps"]) == tuple(ro["self_sweeps"])
+    assert info["horizon"] == ro["horizon"]
+    assert rg["status"] == ro["status"]
+    compare_iter(rg, ro, cls, spec["kind"] != "safety", f"{name} auto", q0=ro["q0"], model=m,
+                 spec=dict(spec, horizon=ro["horizon"]), optimistic=not pessimistic)
+
+
+def test_auto_horizon_is_rejected_by_the_engine(I):
+    imdp = I.build_imdp(SMALL_SYSTEMS["affine2_window"]())
+    eng = I.Engine(max_queries=2)
+    with pytest.raises(I.ImpactError, match="IMPACT_HORIZON_AUTO"):
+        eng.submit(imdp, dict(SPECS["affine2_window"], eps=1e-8, max_sweeps=10, horizon="auto"))
