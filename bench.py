@@ -315,6 +315,29 @@ def run_served(args):
     }
 
 
+def measured_peaks(impact, mib=1024, reps=5):
+    """This device's copy bandwidth (a 1 GiB device-to-device copy, read +
+    write bytes) and FP64 FMA rate (the library's probe kernel), measured
+    outside the timed region; the roofline quotes the published peaks."""
+    import torch
+    src = torch.ones((mib << 20) // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    copy_gbs = 2.0 * src.numel() * 8 / (best * 1e-3) / 1e9
+    del src, dst
+    fp64 = impact.probe_fp64_fma()
+    return {"copy_gbs": copy_gbs, "copy_frac_of_peak": copy_gbs / HBM_PEAK_GBS,
+            "fp64_fma_tflops": fp64, "fp64_frac_of_peak": fp64 / 78.6}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -432,6 +455,7 @@ def main():
         },
     }
     imdp.free()
+    line["measured_peaks"] = measured_peaks(impact)
     forms = [f for f in args.forms.split(",") if f]
     if forms:
         line["forms"] = {}

@@ -341,6 +341,14 @@ const char *impact_last_error(void);
 /* Library version string. */
 const char *impact_version(void);
 
+/* Measurement support (not a step of the method): n_blocks workgroups of
+ * 256 threads each run 16 independent FP64 FMA chains of `iters` steps, i.e.
+ * 2 * 16 * iters * 256 * n_blocks FLOP, on `stream` (a hipStream_t, null for
+ * the default stream).  `out` is a device double the kernel never writes in
+ * practice.  Asynchronous; the caller times it with events on that stream.
+ * E_INVAL for n_blocks outside [1, 2^24], iters < 1 or a null out. */
+int impact_probe_fp64_fma(int64_t n_blocks, int32_t iters, double *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

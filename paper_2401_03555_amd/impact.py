@@ -27,7 +27,8 @@ EXPORTS = ["impact_build_imdp", "impact_interval_iterate", "impact_last_iter_inf
            "impact_imdp_free", "impact_last_error", "impact_version", "impact_set_sweep_mode",
            "impact_set_sweep_modes",
            "impact_build_imdp_batch", "impact_mq_create", "impact_mq_submit", "impact_mq_run",
-           "impact_mq_poll", "impact_mq_query_info", "impact_mq_last_error", "impact_mq_free"]
+           "impact_mq_poll", "impact_mq_query_info", "impact_mq_last_error", "impact_mq_free",
+           "impact_probe_fp64_fma"]
 SWEEP_MODES = {"auto": 0, "per_row": 1, "state_box": 2}
 
 _pd = C.POINTER(C.c_double)
@@ -151,6 +152,8 @@ def lib():
         L.impact_mq_last_error.argtypes = []
         L.impact_mq_free.restype = None
         L.impact_mq_free.argtypes = [C.c_void_p]
+        L.impact_probe_fp64_fma.restype = C.c_int
+        L.impact_probe_fp64_fma.argtypes = [C.c_int64, C.c_int32, _pd, C.c_void_p]
         _lib = L
     return _lib
 
@@ -457,3 +460,22 @@ def build_imdp_batch(systems, storage="bounds", stream=None, sweep_mode="auto"):
 
 def version():
     return lib().impact_version().decode()
+
+
+def probe_fp64_fma(n_blocks=2048, iters=1024, reps=3):
+    """FP64 FMA rate (TFLOP/s) of the library's probe kernel on torch's
+    current stream, best of ``reps`` launches (measurement support)."""
+    import torch
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+    best = None
+    for _ in range(reps + 1):                   # the first launch is a warmup
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        _check(lib().impact_probe_fp64_fma(n_blocks, iters, C.cast(out.data_ptr(), _pd),
+                                           C.c_void_p(st.cuda_stream)))
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    return 2.0 * 16 * iters * 256 * n_blocks / (best * 1e-3) / 1e12
