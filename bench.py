@@ -101,14 +101,18 @@ FP64_PEAK_TFLOPS = 78.6
 
 
 def kernel_source_hash():
-    """Digest of the HIP sources and the C header: identifies the kernels'
-    build for hardware counters recorded under profiles/."""
-    import glob
+    """Digest of what the state-box sweep kernels are compiled from (their
+    sources, the headers they include and the build flags): identifies the
+    build whose hardware counters are recorded under profiles/."""
     import hashlib
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2401_03555_amd", "csrc")
-    files = sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp")))
-    for f in files + [os.path.join(ROOT, "include", "impact.h")]:
+    pkg = os.path.join(ROOT, "paper_2401_03555_amd")
+    csrc = os.path.join(pkg, "csrc")
+    names = [f"sweep_sb_d{d}.hip" for d in (0, 2, 3, 5)] + [
+        "sweep_sb.hpp", "sweep_common.hpp", "impact_internal.hpp", "impact_device.hpp"]
+    files = [os.path.join(csrc, n) for n in names] + [
+        os.path.join(ROOT, "include", "impact.h"), os.path.join(pkg, "build_lib.py")]
+    for f in files:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
