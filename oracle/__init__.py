@@ -88,7 +88,7 @@ def lib():
         L.orc_iterate.restype = C.c_int
         L.orc_iterate.argtypes = [i64, i32, C.POINTER(C.c_int64), C.POINTER(C.c_int32), pd, pd,
                                   C.POINTER(C.c_int8), i32, d, i64, pd, pd,
-                                  C.POINTER(C.c_int32), C.POINTER(_IterInfo), pd, i64, pd, pd, i32, i64, i32]
+                                  C.POINTER(C.c_int32), C.POINTER(_IterInfo), pd, i64, pd, pd, i32, i64, i32, i32]
         _lib = L
     return _lib
 
@@ -101,10 +101,33 @@ def _f64(x):
     return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
 
 
+def with_disturbances(system):
+    """The system whose input list is every (u, w) pair, u-major, and whose
+    input matrix is [B | D], so that its mean A x + [B | D] (u, w) + c is the
+    disturbed mean A x + B u + D w + c of eq. (5.1)'s rows (x, u, w).  Returns
+    (system, number of control inputs, number of disturbances)."""
+    U = np.asarray(system["inputs"], dtype=np.float64)
+    if U.ndim == 1:
+        U = U.reshape(-1, 1) if U.size else np.zeros((1, 0))
+    if "disturbances" not in system:
+        return system, U.shape[0], 1
+    if system["kind"] != "affine":
+        raise ValueError("disturbances are supported for affine systems")
+    Wd = np.asarray(system["disturbances"], dtype=np.float64)
+    d = len(system["lb"])
+    Dm = np.asarray(system["D"], dtype=np.float64).reshape(d, Wd.shape[1])
+    B = np.asarray(system.get("B", np.zeros((d, U.shape[1]))), dtype=np.float64).reshape(d, U.shape[1])
+    pairs = np.array([np.concatenate([u, w]) for u in U for w in Wd])
+    out = {k: v for k, v in system.items() if k not in ("disturbances", "D")}
+    out.update(inputs=pairs, B=np.hstack([B, Dm]))
+    return out, U.shape[0], Wd.shape[0]
+
+
 class _Marshal:
     """Holds the numpy buffers behind the ctypes structs for one call."""
 
     def __init__(self, system):
+        system = with_disturbances(system)[0]
         kind = system["kind"]
         self.lb, self.ub = _f64(system["lb"]), _f64(system["ub"])
         self.n = np.ascontiguousarray(np.asarray(system["n"], dtype=np.int32))
@@ -235,12 +258,15 @@ def lp_sorted(lo, hi, val, maximise):
 
 
 def iterate(n_states_, n_inputs, row_ptr, target, lo, hi, cls, spec_kind, eps, max_sweeps,
-            want_q0=False, hist_cap=0, optimistic=False, horizon=0, self_stop=False):
+            want_q0=False, hist_cap=0, optimistic=False, horizon=0, self_stop=False,
+            n_dist=1):
     """Interval iteration (Alg. 3 / Alg. 4 with the sorting method); the
     policy is pessimistic (IMDP_lower = true, Sec. 5) unless ``optimistic``.
     ``horizon`` T > 0: finite horizon, T sweeps per pass (Remark 5.1).
     ``self_stop``: each pass stops when both its iterates converge to
     themselves (the first step of Remark 5.2).
+    ``n_dist``: disturbances per (state, input); ``n_inputs`` then counts the
+    control inputs only and the rows are (s * n_inputs + u) * n_dist + w.
 
     Returns dict(lo, hi, policy, status, sweeps, gap, converged, n_safe[, q0][, hist_v0, hist_v1]).
     """
@@ -263,7 +289,7 @@ def iterate(n_states_, n_inputs, row_ptr, target, lo, hi, cls, spec_kind, eps, m
         _dptr(out_lo), _dptr(out_hi), pol.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(info),
         _dptr(q0) if want_q0 else None, hist_cap, _dptr(h0) if hist_cap else None,
         _dptr(h1) if hist_cap else None, int(bool(optimistic)), int(horizon),
-        int(bool(self_stop)))
+        int(bool(self_stop)), int(n_dist))
     if rc < 0:
         raise ValueError(f"oracle iterate rejected its input ({rc})")
     res = dict(lo=out_lo, hi=out_hi, policy=pol, status=rc, sweeps=tuple(info.sweeps),
@@ -295,8 +321,9 @@ def solve(system, k_sigma, spec_kind, target_boxes, avoid_boxes, eps, max_sweeps
     """Build + label + iterate, the whole path on the CPU."""
     m = build(system, k_sigma)
     cls = label(system, target_boxes, avoid_boxes)
-    r = iterate(m["n_states"], m["n_inputs"], m["row_ptr"], m["target"], m["lo"], m["hi"], cls,
-                spec_kind, eps, max_sweeps, **kw)
+    _, nu, nw = with_disturbances(system)
+    r = iterate(m["n_states"], nu, m["row_ptr"], m["target"], m["lo"], m["hi"], cls,
+                spec_kind, eps, max_sweeps, n_dist=nw, **kw)
     r["cls"] = cls
     r["imdp"] = m
     return r

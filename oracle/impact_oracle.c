@@ -571,6 +571,24 @@ static double row_lp(const int64_t *row_ptr, const int32_t *target, const double
   return orc_lp_sorted(e - b, lo + b, hi + b, val_buf, maximise, 0);
 }
 
+/* Value of input u at state s against the disturbance player (eq. (5.1): the
+   inner optimisation over w-hat): the worst of the n_dist rows (s, u, w) --
+   the lowest satisfaction probability for reach, the highest probability of
+   the bad set for safety.  Rows of (s, u) are (s * n_inputs + u) * n_dist + w. */
+static double input_value(const int64_t *row_ptr, const int32_t *target, const double *lo,
+                          const double *hi, const int8_t *cls, const double *V, int spec,
+                          int maximise, int64_t s, int32_t u, int32_t n_inputs,
+                          int32_t n_dist, double *val_buf) {
+  int reach = spec != ORC_SAFETY;
+  double worst = 0.0;
+  for (int32_t w = 0; w < n_dist; ++w) {
+    int64_t r = (s * n_inputs + u) * (int64_t)n_dist + w;
+    double q = row_lp(row_ptr, target, lo, hi, cls, V, spec, maximise, r, val_buf);
+    if (w == 0 || (reach ? q < worst : q > worst)) worst = q;
+  }
+  return worst;
+}
+
 static double max_gap(int64_t n, const int8_t *cls, const double *V0, const double *V1) {
   double gmax = 0.0;
   for (int64_t s = 0; s < n; ++s)
@@ -603,6 +621,9 @@ static double max_gap(int64_t n, const int8_t *cls, const double *V0, const doub
  * of its iterates converge to themselves, max_S max(|V0' - V0|, |V1' - V1|)
  * <= eps after a sweep (at least one sweep when S is not empty; at most
  * max_sweeps); info->gap then holds that last move.
+ * n_dist >= 1 disturbances (eq. (5.1)): each (s, u) has n_dist rows and is
+ * valued by its worst one (the disturbance is always an adversary), in both
+ * passes; the policy chooses u only.
  * Returns 0 if both passes met eps (or ran their T sweeps), 1 if a cap
  * fired, < 0 on bad input.
  */
@@ -612,16 +633,16 @@ int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
                 int64_t max_sweeps, double *out_lo, double *out_hi,
                 int32_t *policy, orc_iter_info *info, double *q0_last,
                 int64_t hist_cap, double *hist_v0, double *hist_v1,
-                int32_t optimistic, int64_t horizon, int32_t self_stop) {
-  if (n_inputs < 1 || max_sweeps < 1 || !(eps > 0.0) || horizon < 0) return -1;
+                int32_t optimistic, int64_t horizon, int32_t self_stop, int32_t n_dist) {
+  if (n_inputs < 1 || n_dist < 1 || max_sweeps < 1 || !(eps > 0.0) || horizon < 0) return -1;
   if (self_stop && horizon > 0) return -1;
   int64_t n_safe = 0, max_len = 1;
   for (int64_t s = 0; s < n_states; ++s) {
     if (spec_kind == ORC_SAFETY && cls[s] == ORC_TARGET) return -1;
     if (cls[s] != ORC_SAFE) continue;
     ++n_safe;
-    for (int32_t u = 0; u < n_inputs; ++u) {
-      int64_t r = s * n_inputs + u;
+    for (int64_t k = 0; k < (int64_t)n_inputs * n_dist; ++k) {
+      int64_t r = s * n_inputs * (int64_t)n_dist + k;
       if (row_ptr[r + 1] - row_ptr[r] > max_len) max_len = row_ptr[r + 1] - row_ptr[r];
     }
   }
@@ -679,10 +700,11 @@ int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
           double best0 = 0.0, best1 = 0.0;
           int32_t arg = 0;
           for (int32_t u = 0; u < n_inputs; ++u) {
-            int64_t r = s * n_inputs + u;
-            double q0 = row_lp(row_ptr, target, lo, hi, cls, V0, spec_kind, maximise, r, vb);
-            double q1 = row_lp(row_ptr, target, lo, hi, cls, V1, spec_kind, maximise, r, vb);
-            if (q0_last) q0_last[r] = q0;
+            double q0 = input_value(row_ptr, target, lo, hi, cls, V0, spec_kind, maximise, s, u,
+                                    n_inputs, n_dist, vb);
+            double q1 = input_value(row_ptr, target, lo, hi, cls, V1, spec_kind, maximise, s, u,
+                                    n_inputs, n_dist, vb);
+            if (q0_last) q0_last[s * n_inputs + u] = q0;
             if (u == 0) {
               best0 = q0;
               best1 = q1;
@@ -699,9 +721,10 @@ int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
           N1[s] = best1;
           pi[s] = arg;
         } else {
-          int64_t r = s * n_inputs + pi[s];
-          N0[s] = row_lp(row_ptr, target, lo, hi, cls, V0, spec_kind, maximise, r, vb);
-          N1[s] = row_lp(row_ptr, target, lo, hi, cls, V1, spec_kind, maximise, r, vb);
+          N0[s] = input_value(row_ptr, target, lo, hi, cls, V0, spec_kind, maximise, s, pi[s],
+                              n_inputs, n_dist, vb);
+          N1[s] = input_value(row_ptr, target, lo, hi, cls, V1, spec_kind, maximise, s, pi[s],
+                              n_inputs, n_dist, vb);
         }
       }
       double delta = 0.0; /* largest move of either iterate in this sweep */

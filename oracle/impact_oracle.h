@@ -111,14 +111,16 @@ double orc_lp_sorted(int64_t n, const double *lo, const double *hi,
    horizon = 0: infinite horizon (stop test on eps, cap max_sweeps);
    horizon = T > 0: finite horizon, exactly T sweeps per pass (Remark 5.1).
    self_stop = 1 (horizon 0): a pass stops once both iterates stop moving
-   by more than eps in a sweep (Remark 5.2). */
+   by more than eps in a sweep (Remark 5.2).
+   n_dist >= 1: disturbances per (s, u); rows (s * n_inputs + u) * n_dist + w,
+   the worst row valuing the input (eq. (5.1)). */
 int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
                 const int32_t *target, const double *lo, const double *hi,
                 const int8_t *cls, int32_t spec_kind, double eps,
                 int64_t max_sweeps, double *out_lo, double *out_hi,
                 int32_t *policy, orc_iter_info *info, double *q0_last,
                 int64_t hist_cap, double *hist_v0, double *hist_v1,
-                int32_t optimistic, int64_t horizon, int32_t self_stop);
+                int32_t optimistic, int64_t horizon, int32_t self_stop, int32_t n_dist);
 
 #ifdef __cplusplus
 }

@@ -861,3 +861,99 @@ def test_self_stop_cap_and_empty_safe_set(orc):
     r = orc.iterate(1, 1, [0, 2], [0, -1], [.9, 0.0], [1.0, .1], np.array([2], np.int8), "safety",
                     1e-8, 50, self_stop=True)
     assert r["sweeps"] == (0, 0) and r["status"] == 0
+
+
+# --------------------------------------------------------------------------
+# Disturbance player (eq. (5.1): max over u of min over w-hat)
+# --------------------------------------------------------------------------
+
+def _two_by_two():
+    # state 0 SAFE, 1 TARGET, 2 AVOID; rows (u, w) of state 0 are exact
+    # (lo = hi): (0,0) target .5; (0,1) .1; (1,0) .3; (1,1) .3, the rest to AVOID
+    row_ptr = [0, 2, 4, 6, 8] + [8] * 8
+    target = [1, 2] * 4
+    p = [.5, .5, .1, .9, .3, .7, .3, .7]
+    return row_ptr, target, p, p, np.array([0, 1, 2], np.int8)
+
+
+def test_disturbance_worked_example(orc):
+    # the disturbance answers each input with its worst row: input 0 is worth
+    # .1, input 1 .3, so pi = 1 and both bounds are .3; with the disturbances
+    # read as four more inputs the controller would claim .5
+    row_ptr, target, lo, hi, cls = _two_by_two()
+    for opt in (False, True):
+        r = orc.iterate(3, 2, row_ptr, target, lo, hi, cls, "reach_avoid", 1e-9, 100,
+                        optimistic=opt, n_dist=2, want_q0=True)
+        assert r["policy"][0] == 1 and r["status"] == 0
+        assert r["lo"][0] == pytest.approx(.3, abs=1e-15) and r["hi"][0] == pytest.approx(.3, abs=1e-15)
+        assert r["q0"][0] == pytest.approx([.1, .3], abs=1e-15)
+    r = orc.iterate(3, 4, row_ptr, target, lo, hi, cls, "reach_avoid", 1e-9, 100)
+    assert r["policy"][0] == 0 and r["lo"][0] == pytest.approx(.5, abs=1e-15)
+
+
+def test_disturbance_safety_finite_horizon(orc):
+    # state 0 SAFE with a self loop, state 1 AVOID.  Bad mass per step:
+    # (u0,w0) .1, (u0,w1) .4, (u1,w0) .2, (u1,w1) .25.  The disturbance takes
+    # the larger bad mass (.4 and .25), the controller the smaller: pi = 1 and
+    # staying safe for T steps has probability .75^T
+    row_ptr = [0, 2, 4, 6, 8] + [8] * 4
+    target = [0, 1] * 4
+    p = [.9, .1, .6, .4, .8, .2, .75, .25]
+    for T in (1, 4, 9):
+        r = orc.iterate(2, 2, row_ptr, target, p, p, np.array([0, 2], np.int8), "safety", 1e-9, 1,
+                        horizon=T, n_dist=2)
+        assert r["policy"][0] == 1
+        assert r["lo"][0] == pytest.approx(.75 ** T, rel=1e-14)
+        assert r["hi"][0] == pytest.approx(.75 ** T, rel=1e-14)
+
+
+def _disturbed_system(seed, n_dist=3):
+    sys_ = W.tiny_affine(d=2, n=7, seed=seed, n_inputs=3)
+    rng = np.random.default_rng(seed + 100)
+    sys_ = dict(sys_, D=rng.normal(0, 0.3, (2, 2)),
+                disturbances=rng.uniform(-0.5, 0.5, (n_dist, 2)))
+    return sys_
+
+
+def test_disturbed_mean_box_contains_and_is_tight(orc):
+    # the build row (u, w) has the mean box of A x + B u + D w + c over the cell
+    system = _disturbed_system(3)
+    A, B, c = (np.asarray(system[k]) for k in ("A", "B", "c"))
+    Dm, Wd, U = np.asarray(system["D"]), np.asarray(system["disturbances"]), np.asarray(system["inputs"])
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        s = int(rng.integers(0, 49))
+        u, w = int(rng.integers(0, len(U))), int(rng.integers(0, len(Wd)))
+        mlo, mhi = orc.mean_box(system, s, u * len(Wd) + w)
+        k = np.unravel_index(s, system["n"])
+        lo = np.array([orc.cell_edge(system, i, k[i]) for i in range(2)])
+        hi = np.array([orc.cell_edge(system, i, k[i] + 1) for i in range(2)])
+        corners = np.array(list(itertools.product(*zip(lo, hi))))
+        f = corners @ A.T + B @ U[u] + Dm @ Wd[w] + c
+        assert (f >= mlo - 1e-15).all() and (f <= mhi + 1e-15).all()
+        assert np.abs(f.min(0) - mlo).max() < 1e-12 and np.abs(f.max(0) - mhi).max() < 1e-12
+
+
+def test_single_disturbance_is_a_shift_of_c(orc):
+    # one disturbance w0: rows are those of the system with c + D w0
+    system = _disturbed_system(5, n_dist=1)
+    shifted = {k: v for k, v in system.items() if k not in ("D", "disturbances")}
+    shifted["c"] = np.asarray(system["c"]) + np.asarray(system["D"]) @ np.asarray(system["disturbances"][0])
+    a, b = orc.build(system, system["k_sigma"]), orc.build(shifted, shifted["k_sigma"])
+    assert np.array_equal(a["row_ptr"], b["row_ptr"]) and np.array_equal(a["target"], b["target"])
+    assert np.abs(a["lo"] - b["lo"]).max() < 1e-12 and np.abs(a["hi"] - b["hi"]).max() < 1e-12
+
+
+@pytest.mark.parametrize("seed", [12, 21])
+def test_disturbance_player_lowers_the_guarantee(orc, seed):
+    # a stronger adversary cannot raise the pessimistic lower bound: with all
+    # disturbances the bound is at most that of every single-disturbance system
+    system = _disturbed_system(seed)
+    tgt, avd = [[[0.5, 0.5], [2.0, 2.0]]], [[[-2.0, -2.0], [-1.0, -1.0]]]
+    full = orc.solve(system, system["k_sigma"], "reach_avoid", tgt, avd, 1e-10, 100000)
+    assert full["status"] == 0
+    for k in range(len(system["disturbances"])):
+        one = dict(system, disturbances=np.asarray(system["disturbances"])[k:k + 1])
+        r = orc.solve(one, one["k_sigma"], "reach_avoid", tgt, avd, 1e-10, 100000)
+        assert (full["lo"] <= r["lo"] + 1e-9).all()
+    assert (full["lo"] <= full["hi"] + 1e-9).all()
