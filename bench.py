@@ -21,6 +21,8 @@ plain counterpart on the same GPU at the same eps:
            loop of plain build + iterate calls, one instance at a time;
   served : a Poisson request trace over a 64-system pool served by the
            continuous-batching loop, against serial plain solves.
+``--forms disturbed`` adds the disturbance player (the 2D robot with 11
+disturbances) with its own roofline and oracle sample.
 """
 import argparse
 import json
@@ -46,7 +48,9 @@ def parse():
     ap.add_argument("--sweep-mode", default="tuned",
                     choices=["tuned", "auto", "per_row", "state_box"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="", help="comma list of: batched, served")
+    ap.add_argument("--forms", default="", help="comma list of: batched, served, disturbed")
+    ap.add_argument("--dist-max-sweeps", type=int, default=5000,
+                    help="sweep cap per pass of the disturbed form")
     ap.add_argument("--instances", type=int, default=384)
     ap.add_argument("--batch-max-sweeps", type=int, default=1000)
     ap.add_argument("--batch-dims", default="2,3",
@@ -85,7 +89,7 @@ def algorithmic_bytes(imdp, policy, n_states, d):
     and are not counted.
     """
     info = imdp.info()
-    nu = info["n_inputs"]
+    nu = info["n_inputs"] * info.get("n_dist", 1)   # rows per state in the policy pass
     ex = imdp.export_rows(0, info["n_rows"], entries=False)
     safe = policy >= 0
     counts = ex["counts"].reshape(-1, nu)
@@ -284,6 +288,67 @@ def run_batched(args, tuner):
     }
 
 
+def run_disturbed(args):
+    """The disturbance player (eq. (5.1)) on the 2D robot with 11 disturbances:
+    build + iterate timed like the plain step; the per-row policy-pass sweep's
+    roofline; the oracle on one sweep of each pass."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2401_03555_amd import impact, workloads as W
+    system, spec = W.robot2d_disturbed()
+    spec = dict(spec, max_sweeps=args.dist_max_sweeps)
+
+    def step(timing=False):
+        imdp = impact.build_imdp(system, storage="bounds", timing=timing)
+        return imdp, imdp.iterate(spec)
+
+    imdp, r = step()
+    imdp.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        imdp, r = step()
+        imdp.free()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    imdp, r = step(timing=True)
+    info, it = imdp.info(), r["info"]
+    policy = r["policy"].cpu().numpy()
+    bytes_sweep, cells, rows = algorithmic_bytes(imdp, policy, info["n_states"], info["dim"])
+    launch_ms = it["launch_ms"][0] / max(1, it["launches"][0])
+    achieved = bytes_sweep * it["sweeps"][0] / max(1, it["launches"][0]) / (launch_ms * 1e-3) / 1e9
+    imdp.free()
+    updates = sum(it["updates"])
+    # the oracle, one sweep of each pass (bounded sample)
+    m = oracle.build(system, system["k_sigma"])
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    t1 = time.perf_counter()
+    ro = oracle.iterate(m["n_states"], len(system["inputs"]), m["row_ptr"], m["target"], m["lo"],
+                        m["hi"], cls, spec["kind"], spec["eps"], 1, n_dist=info["n_dist"])
+    t_o = time.perf_counter() - t1
+    o_updates = int(ro["n_safe"]) * info["n_dist"] * (len(system["inputs"]) + 1)
+    return {
+        "workload": ("2D robot reach-avoid with a disturbance player: 20x20 cells, 9 inputs, "
+                     "11 disturbances (drift along x in [-0.5, 0.5]), dense rows, eps 1e-8, "
+                     f"at most {args.dist_max_sweeps} sweeps per pass"),
+        "ms_per_step": ms,
+        "value": updates / (ms * 1e-3),
+        "unit": "(s,u,w)-row updates/s",
+        "sweeps": list(it["sweeps"]),
+        "converged": list(it["converged"]),
+        "rows_per_sweep_pass1": rows,
+        "roofline": {"kernel": "k_sweep policy pass (per-row LP, all (u, w) rows)",
+                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_sweep": bytes_sweep, "avg_launch_ms": launch_ms},
+        "cpu_baseline": {"value": o_updates / t_o, "unit": "(s,u,w)-row updates/s", "cores": 1,
+                         "kind": "oracle",
+                         "sample": f"one sweep of each pass ({o_updates} row updates, {t_o:.1f} s)"},
+        "vs_oracle": (updates / (ms * 1e-3)) / (o_updates / t_o),
+    }
+
+
 def run_served(args):
     """Served form vs serial plain solves over the same request trace."""
     import torch
@@ -465,6 +530,8 @@ def main():
         line["forms"] = {}
     if "batched" in forms:
         line["forms"]["batched"] = run_batched(args, tuner)
+    if "disturbed" in forms:
+        line["forms"]["disturbed"] = run_disturbed(args)
     if "served" in forms:
         line["forms"]["served"] = run_served(args)
         line["components"]["served_p99_ms"] = line["forms"]["served"]["served"]["p99_ms"]

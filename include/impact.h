@@ -141,6 +141,34 @@ int impact_build_imdp(const impact_system *sys, const impact_grid *grid,
                       const impact_window *window, const impact_device *dev,
                       impact_imdp **out);
 
+/* Finite disturbance set W-hat of an affine system, x+ = A x + B u + D w + c
+ * + noise (eq. (5.1); Alg. 2 iterates over it like over the inputs).  Host
+ * pointers, row-major: values count x dim_w, D dim_x x dim_w. */
+typedef struct {
+  int32_t count, dim_w;
+  const double *values, *D;
+} impact_disturbances;
+
+/*
+ * impact_build_imdp for an affine system with a disturbance player: one row
+ * per (state, input, disturbance), row index (s * inputs.count + u) *
+ * dist.count + w, each with the bounds of Def. 3.1 for the mean
+ * A x + B u + D w + c (summed as (sum_j a_ij x_j + sum_j b_ij u_j +
+ * sum_k d_ik w_k) + c_i).  impact_interval_iterate then values each (state,
+ * input) by its worst row -- the lowest satisfaction probability for reach,
+ * the highest bad-set probability for safety -- in both passes (eq. (5.1):
+ * the disturbance is an adversary whatever the policy), and the policy
+ * chooses the input only.  Such handles iterate with the per-row sweep
+ * kernels (the sweep mode is ignored) and are rejected by the multi-query
+ * engine.  Errors as impact_build_imdp, plus E_INVAL for count or dim_w < 1,
+ * null values or D, or non-finite entries; E_UNSUPPORTED for a non-affine
+ * system, dim_u + dim_w > 8 or more than 256 (input, disturbance) pairs.
+ */
+int impact_build_imdp_dist(const impact_system *sys, const impact_grid *grid,
+                           const impact_inputs *inputs, const impact_disturbances *dist,
+                           const impact_noise *noise, const impact_window *window,
+                           const impact_device *dev, impact_imdp **out);
+
 /*
  * Build n abstractions with one launch of each construction kernel over the
  * rows of all of them (the parallel loop of Alg. 2 spanning every system).
@@ -244,6 +272,7 @@ typedef struct {
                             (cells; the unit sorted once per state)      */
   int64_t device_bytes;  /* bytes held by the handle                     */
   double build_ms;       /* build-kernel time, from HIP events           */
+  int32_t n_dist;        /* disturbances per (state, input); 1 if none    */
 } impact_imdp_info;
 
 int impact_imdp_get_info(const impact_imdp *imdp, impact_imdp_info *info);
@@ -308,8 +337,9 @@ int impact_mq_create(const impact_device *dev, int32_t max_queries, impact_mq **
  * once the query finishes (cells outside the SAFE set immediately).  The
  * abstraction handle may be released after submitting (the engine keeps its
  * device storage alive until the query is polled).  *id receives the query id.
- * Errors: E_INVAL (bad spec/eps/buffers), E_UNSUPPORTED (no free slot),
- * E_NOMEM, E_HIP. */
+ * Errors: E_INVAL (bad spec/eps/buffers), E_UNSUPPORTED (no free slot, an
+ * abstraction with a disturbance player, or IMPACT_HORIZON_AUTO), E_NOMEM,
+ * E_HIP. */
 int impact_mq_submit(impact_mq *mq, const impact_imdp *imdp, const impact_spec *spec, double eps,
                      double *lo, double *hi, int32_t *policy, int32_t *id);
 

@@ -105,6 +105,7 @@ struct impact_imdp {
   const double2* fac = nullptr;
   int64_t n_states = 0, n_rows = 0, n_cells = 0;
   int32_t d = 0, nu = 0, windowed = 0, storage = IMPACT_STORE_BOUNDS, max_row = 0, fs = 0;
+  int32_t nw = 1;       // disturbances per (state, input); rows per state nu * nw
   int64_t max_box = 0;  // largest bounding box of one state's row windows (cells)
   int32_t sweep_mode[2] = {IMPACT_SWEEP_AUTO, IMPACT_SWEEP_AUTO};  // per pass
   impact_iter_info last{};
@@ -264,6 +265,7 @@ int imdp_view(const impact_imdp* h, ImdpView* v) {
   v->max_row = h->max_row;
   v->d = h->d;
   v->nu = h->nu;
+  v->nw = h->nw;
   v->keep = h->store;
   return IMPACT_OK;
 }
@@ -453,6 +455,58 @@ int impact_build_imdp(const impact_system* sys, const impact_grid* grid,
   return build_many(1, sys, grid, inputs, noise, window, dev, out);
 }
 
+int impact_build_imdp_dist(const impact_system* sys, const impact_grid* grid,
+                           const impact_inputs* inputs, const impact_disturbances* dist,
+                           const impact_noise* noise, const impact_window* window,
+                           const impact_device* dev, impact_imdp** out) {
+  g_err.clear();
+  if (!out) return fail(IMPACT_E_INVAL, "out is null");
+  *out = nullptr;
+  if (!sys || !grid || !inputs || !dist || !noise || !window)
+    return fail(IMPACT_E_INVAL, "null argument");
+  if (sys->kind != IMPACT_SYS_AFFINE)
+    return fail(IMPACT_E_UNSUPPORTED, "disturbances need an affine system");
+  const int d = grid->dim;
+  if (d < 1 || d > IMPACT_MAX_DIM || sys->dim_x != d)
+    return fail(IMPACT_E_INVAL, "grid.dim must equal system.dim_x and be in [1, 8]");
+  if (dist->count < 1 || dist->dim_w < 1)
+    return fail(IMPACT_E_INVAL, "disturbances.count and dim_w must be >= 1");
+  if (!dist->values || !dist->D) return fail(IMPACT_E_INVAL, "disturbances.values or D is null");
+  const int du = sys->dim_u, dw = dist->dim_w;
+  if (du < 0 || inputs->dim_u != du || inputs->count < 1 || (du > 0 && (!inputs->values || !sys->B)))
+    return fail(IMPACT_E_INVAL, "inputs must match system.dim_u and hold at least one input");
+  if (du + dw > IMPACT_MAX_DIM) return fail(IMPACT_E_UNSUPPORTED, "dim_u + dim_w must be at most 8");
+  if ((int64_t)inputs->count * dist->count > 256)
+    return fail(IMPACT_E_UNSUPPORTED, "more than 256 (input, disturbance) pairs");
+  for (int64_t k = 0; k < (int64_t)dist->count * dw; ++k)
+    if (!is_finite(dist->values[k])) return fail(IMPACT_E_INVAL, "non-finite disturbance value");
+  for (int64_t k = 0; k < (int64_t)d * dw; ++k)
+    if (!is_finite(dist->D[k])) return fail(IMPACT_E_INVAL, "non-finite D");
+  // one input per (u, w) pair, u-major, with input matrix [B | D]: the build
+  // computes the mean A x + B u + D w + c of every row
+  const int dc = du + dw;
+  std::vector<double> B2((size_t)d * dc), U2((size_t)inputs->count * dist->count * dc);
+  for (int i = 0; i < d; ++i) {
+    for (int j = 0; j < du; ++j) B2[(size_t)i * dc + j] = sys->B[(size_t)i * du + j];
+    for (int k = 0; k < dw; ++k) B2[(size_t)i * dc + du + k] = dist->D[(size_t)i * dw + k];
+  }
+  for (int32_t u = 0; u < inputs->count; ++u)
+    for (int32_t w = 0; w < dist->count; ++w) {
+      double* r = U2.data() + ((size_t)u * dist->count + w) * dc;
+      for (int j = 0; j < du; ++j) r[j] = inputs->values[(size_t)u * du + j];
+      for (int k = 0; k < dw; ++k) r[du + k] = dist->values[(size_t)w * dw + k];
+    }
+  impact_system s2 = *sys;
+  s2.dim_u = dc;
+  s2.B = B2.data();
+  impact_inputs i2{inputs->count * dist->count, dc, U2.data()};
+  const int rc = build_many(1, &s2, grid, &i2, noise, window, dev, out);
+  if (rc < 0) return rc;
+  (*out)->nu = inputs->count;
+  (*out)->nw = dist->count;
+  return rc;
+}
+
 int impact_build_imdp_batch(int32_t n, const impact_system* sys, const impact_grid* grid,
                             const impact_inputs* inputs, const impact_noise* noise,
                             const impact_window* window, const impact_device* dev,
@@ -498,6 +552,7 @@ int impact_imdp_get_info(const impact_imdp* h, impact_imdp_info* info) {
   info->max_box = h->max_box;
   info->device_bytes = h->store->bytes;
   info->build_ms = h->build_ms;
+  info->n_dist = h->nw;
   return IMPACT_OK;
 }
 
@@ -609,7 +664,8 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       // row fits a wavefront; the fixed-input pass has one row per state and
       // sorts per row unless the state-box mode is forced
       const int32_t mode = h->sweep_mode[pass];
-      const bool use_box = h->max_row <= 512 &&
+      // (with a disturbance player every pass runs the per-row kernels)
+      const bool use_box = h->nw == 1 && h->max_row <= 512 &&
                            (mode == IMPACT_SWEEP_STATE_BOX ||
                             (mode == IMPACT_SWEEP_AUTO && pass == 0));
       SweepArgs a{};
@@ -633,18 +689,19 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       const bool adverse = (pass == 0) == (spec->pessimistic != 0);
       a.maximise = adverse ? safety : !safety;
       a.nu = h->nu;
+      a.nw = h->nw;
       a.d = d;
       a.windowed = h->windowed;
       a.storage = h->storage;
       a.out_val = safety ? 1.0 : 0.0;
-      a.inputs_per_state = pass == 0 ? h->nu : 1;
+      a.inputs_per_state = (pass == 0 ? h->nu : 1) * h->nw;  // rows swept per state
       int G = 1;
       if (h->max_row <= 512) G = std::max(1, 4 / a.inputs_per_state);
       while (G > 1 && G * a.inputs_per_state > 256) --G;
       if (a.inputs_per_state > 256)
-        return fail(IMPACT_E_UNSUPPORTED, "more than 256 inputs per state");
+        return fail(IMPACT_E_UNSUPPORTED, "more than 256 rows per state");
       // the fixed-input pass sorting per row runs several rows per wavefront
-      if (pass == 1 && !use_box && rows_g_states_per_block(h->max_row) > 0)
+      if (pass == 1 && !use_box && h->nw == 1 && rows_g_states_per_block(h->max_row) > 0)
         G = rows_g_states_per_block(h->max_row);
       a.states_per_block = G;
 

@@ -34,6 +34,8 @@ struct SweepArgs {
   int32_t states_per_block;
   int32_t inputs_per_state;
   int32_t nu, d, windowed, storage;
+  int32_t nw;              // disturbances per (state, input), 0 or 1: none;
+                           // rows of (s, u) are (s * nu + u) * nw + w
   double out_val;          // objective value of OUT
 };
 
@@ -80,6 +82,7 @@ struct ImdpView {
   const SysParams* dp;
   int64_t n_states, max_box;
   int32_t max_row, d, nu;
+  int32_t nw;  // disturbances per (state, input); the engine takes 1 only
   std::shared_ptr<void> keep;  // the abstraction's device storage
 };
 int imdp_view(const impact_imdp* h, ImdpView* v);

@@ -408,6 +408,9 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
   if (!std::isfinite(eps) || !(eps > 0.0)) return mq_fail(IMPACT_E_INVAL, "eps must be > 0");
   ImdpView v;
   if (imdp_view(h, &v) != IMPACT_OK) return mq_fail(IMPACT_E_INVAL, "bad abstraction handle");
+  if (v.nw > 1)
+    return mq_fail(IMPACT_E_UNSUPPORTED,
+                   "abstractions with a disturbance player run through impact_interval_iterate");
   const int d = v.d;
   for (int b = 0; b < spec->n_target; ++b)
     for (int i = 0; i < d; ++i)

@@ -43,15 +43,18 @@ __device__ double block_sweep_states(const SweepArgs& a, const int32_t* __restri
                                      int nst, BlockLds<BLOCK_E>& L) {
   const SysParams& p = *a.sys;
   const int tid = threadIdx.x, lane = tid & 63, wv = uniform_i32(tid >> 6);
-  const int U = PASS == 0 ? a.nu : 1;
+  // rows per state: (inputs swept) x (disturbances), disturbance fastest
+  const int NW = a.nw > 1 ? a.nw : 1;
+  const int U = (PASS == 0 ? a.nu : 1) * NW;
   const int items = nst * U;
   const int extra = 1 + a.windowed;
   constexpr bool UN = WAVE_E < 8 && BLOCK_E == 0;
   auto row_of = [&](int m) -> int64_t {
     const int gi = m / U, ui = m - gi * U;
     const int64_t s = states[gi];
-    const int u = PASS == 0 ? ui : a.pi[s];
-    return s * a.nu + u;
+    const int ku = ui / NW, w = ui - ku * NW;
+    const int u = PASS == 0 ? ku : a.pi[s];
+    return (s * a.nu + u) * NW + w;
   };
 
   if constexpr (BLOCK_E > 0) {
@@ -97,13 +100,23 @@ __device__ double block_sweep_states(const SweepArgs& a, const int32_t* __restri
   double gap = 0.0;
   if (tid < nst) {
     const int64_t s = states[tid];
-    double b0 = L.qb0[tid * U], b1 = L.qb1[tid * U];
+    // an input is worth its worst row over the disturbances (eq. (5.1)):
+    // the minimum for reach, the maximum of the bad mass for safety
+    auto worst = [&](const double* q, int ku) {
+      double v = q[tid * U + ku * NW];
+      for (int w = 1; w < NW; ++w) {
+        const double x = q[tid * U + ku * NW + w];
+        v = a.reach ? fmin(v, x) : fmax(v, x);
+      }
+      return v;
+    };
+    double b0 = worst(L.qb0, 0), b1 = worst(L.qb1, 0);
     int arg = 0;
-    for (int ui = 1; ui < U; ++ui) {
-      const double q0 = L.qb0[tid * U + ui], q1 = L.qb1[tid * U + ui];
+    for (int ku = 1; ku < U / NW; ++ku) {
+      const double q0 = worst(L.qb0, ku), q1 = worst(L.qb1, ku);
       if (a.reach ? (q0 > b0) : (q0 < b0)) {
         b0 = q0;
-        arg = ui;
+        arg = ku;
       }
       if (a.reach ? (q1 > b1) : (q1 < b1)) b1 = q1;
     }

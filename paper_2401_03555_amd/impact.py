@@ -28,7 +28,7 @@ EXPORTS = ["impact_build_imdp", "impact_interval_iterate", "impact_last_iter_inf
            "impact_set_sweep_modes",
            "impact_build_imdp_batch", "impact_mq_create", "impact_mq_submit", "impact_mq_run",
            "impact_mq_poll", "impact_mq_query_info", "impact_mq_last_error", "impact_mq_free",
-           "impact_probe_fp64_fma"]
+           "impact_probe_fp64_fma", "impact_build_imdp_dist"]
 SWEEP_MODES = {"auto": 0, "per_row": 1, "state_box": 2}
 
 _pd = C.POINTER(C.c_double)
@@ -51,6 +51,10 @@ class Inputs(C.Structure):
 
 class Noise(C.Structure):
     _fields_ = [("sigma", _pd)]
+
+
+class Disturbances(C.Structure):
+    _fields_ = [("count", C.c_int32), ("dim_w", C.c_int32), ("values", _pd), ("D", _pd)]
 
 
 class Window(C.Structure):
@@ -85,7 +89,7 @@ class ImdpInfo(C.Structure):
     _fields_ = [("n_states", C.c_int64), ("n_rows", C.c_int64), ("n_entries", C.c_int64),
                 ("dim", C.c_int32), ("n_inputs", C.c_int32), ("windowed", C.c_int32),
                 ("storage", C.c_int32), ("max_row", C.c_int32), ("max_box", C.c_int64),
-                ("device_bytes", C.c_int64), ("build_ms", C.c_double)]
+                ("device_bytes", C.c_int64), ("build_ms", C.c_double), ("n_dist", C.c_int32)]
 
 
 class ImpactError(RuntimeError):
@@ -152,6 +156,11 @@ def lib():
         L.impact_mq_last_error.argtypes = []
         L.impact_mq_free.restype = None
         L.impact_mq_free.argtypes = [C.c_void_p]
+        L.impact_build_imdp_dist.restype = C.c_int
+        L.impact_build_imdp_dist.argtypes = [C.POINTER(System), C.POINTER(Grid), C.POINTER(Inputs),
+                                             C.POINTER(Disturbances), C.POINTER(Noise),
+                                             C.POINTER(Window), C.POINTER(Device),
+                                             C.POINTER(C.c_void_p)]
         L.impact_probe_fp64_fma.restype = C.c_int
         L.impact_probe_fp64_fma.argtypes = [C.c_int64, C.c_int32, _pd, C.c_void_p]
         _lib = L
@@ -221,6 +230,13 @@ class _Marshal:
         self.grid = Grid(d, _dptr(self.lb), _dptr(self.ub), self.n.ctypes.data_as(_pi32))
         self.inp = Inputs(self.inputs.shape[0], du, _dptr(self.inputs) if du else None)
         self.noise = Noise(_dptr(self.sigma))
+        self.dist = None
+        if "disturbances" in system:
+            wv = np.asarray(system["disturbances"], dtype=np.float64)
+            self.wv = _f64(wv.reshape(wv.shape[0], -1))
+            self.D = _f64(np.asarray(system["D"], dtype=np.float64).reshape(d, self.wv.shape[1]))
+            self.dist = Disturbances(self.wv.shape[0], self.wv.shape[1], _dptr(self.wv),
+                                     _dptr(self.D))
         kind = system["kind"]
         if kind == "affine":
             self.A = _f64(system["A"]).reshape(d, d)
@@ -335,8 +351,14 @@ def build_imdp(system, k_sigma=None, storage="bounds", stream=None, timing=False
     w = Window(float(system.get("k_sigma", 0.0) if k_sigma is None else k_sigma),
                STORAGE[storage])
     h = C.c_void_p()
-    _check(lib().impact_build_imdp(C.byref(m.sys), C.byref(m.grid), C.byref(m.inp),
-                                   C.byref(m.noise), C.byref(w), C.byref(dev.struct), C.byref(h)))
+    if m.dist is not None:
+        _check(lib().impact_build_imdp_dist(C.byref(m.sys), C.byref(m.grid), C.byref(m.inp),
+                                            C.byref(m.dist), C.byref(m.noise), C.byref(w),
+                                            C.byref(dev.struct), C.byref(h)))
+    else:
+        _check(lib().impact_build_imdp(C.byref(m.sys), C.byref(m.grid), C.byref(m.inp),
+                                       C.byref(m.noise), C.byref(w), C.byref(dev.struct),
+                                       C.byref(h)))
     imdp = Imdp(h.value, dev)
     if timing:
         imdp.set_timing(True)
@@ -440,6 +462,8 @@ class Engine:
 
 def build_imdp_batch(systems, storage="bounds", stream=None, sweep_mode="auto"):
     """Build several abstractions with one launch of each construction kernel."""
+    if any("disturbances" in s for s in systems):
+        raise ValueError("the batch build takes no disturbance player; use build_imdp")
     n = len(systems)
     ms = [_Marshal(s) for s in systems]
     dev = _TorchDevice(stream)

@@ -42,6 +42,17 @@ def robot2d(sigma=0.25):
     return system, spec
 
 
+def robot2d_disturbed(n_dist=11):
+    """The 2D robot with a disturbance player (stand-in for the paper's 2D robot
+    rows with |W| = 11): x+ = x + 0.5 u + D w + noise, D = (1, 0)^T, w in 11
+    evenly spaced values of [-0.5, 0.5] (an uncertain drift along x); grid,
+    inputs, noise and specification as robot2d."""
+    system, spec = robot2d()
+    system = dict(system, D=np.array([[1.0], [0.0]]),
+                  disturbances=np.linspace(-0.5, 0.5, n_dist).reshape(-1, 1))
+    return system, spec
+
+
 def unicycle3d(n=(50, 50, 24)):
     """3D unicycle vehicle, reach-avoid, +-6 sigma windows (stand-in for the 3D vehicle study).
 

@@ -84,24 +84,28 @@ def check_policy(pol_g, pol_o, q0, cls, reach, label):
     assert not bad, f"{label}: policy mismatch beyond ties at {bad[:10]}"
 
 
-def fixed_pass_under(m, cls, spec, policy, optimistic):
-    """Oracle run of the interval Markov chain that ``policy`` induces.
+def fixed_pass_under(m, cls, spec, policy, optimistic, n_dist=1):
+    """Oracle run of the interval Markov chain that ``policy`` induces (with
+    its disturbance rows, if any).
 
     The fixed-input pass starts afresh from the policy alone, so its bound and
     sweep count are those of the second pass of this run.
     """
-    U, N = m["n_inputs"], m["n_states"]
-    rows = np.arange(N) * U + np.maximum(np.asarray(policy), 0)
+    N = m["n_states"]
+    U = m["n_inputs"] // n_dist
+    pol = np.maximum(np.asarray(policy), 0)
+    rows = ((np.arange(N) * U + pol)[:, None] * n_dist + np.arange(n_dist)[None, :]).ravel()
     rp = m["row_ptr"]
     starts, ends = rp[rows], rp[rows + 1]
     idx = np.concatenate([np.arange(a, b) for a, b in zip(starts, ends)])
     new_rp = np.concatenate([[0], np.cumsum(ends - starts)]).astype(np.int64)
     return oracle.iterate(N, 1, new_rp, m["target"][idx], m["lo"][idx], m["hi"][idx], cls,
                           spec["kind"], spec["eps"], spec["max_sweeps"], optimistic=optimistic,
-                          horizon=spec.get("horizon", 0))
+                          horizon=spec.get("horizon", 0), n_dist=n_dist)
 
 
-def compare_iter(g, o, cls, reach, label, q0=None, model=None, spec=None, optimistic=False):
+def compare_iter(g, o, cls, reach, label, q0=None, model=None, spec=None, optimistic=False,
+                 n_dist=1):
     """Policy-pass bound and sweeps against the oracle; the policy equal up to
     ties.  Where the policies differ at ties (``model`` given), the
     fixed-input pass is checked against the oracle run under the GPU's policy."""
@@ -121,7 +125,7 @@ def compare_iter(g, o, cls, reach, label, q0=None, model=None, spec=None, optimi
         assert np.array_equal(pol, o["policy"])
     ref = o
     if model is not None and not np.array_equal(pol, np.asarray(o["policy"])):
-        ref = fixed_pass_under(model, cls, spec, pol, optimistic)
+        ref = fixed_pass_under(model, cls, spec, pol, optimistic, n_dist)
         d = np.abs(got[kf] - ref[kf]).max()
         say(f"{label}: policies differ at ties; fixed pass under the GPU policy: "
             f"sweeps {ref['sweeps'][1]} max|d{kf}| {d:.2e}")
@@ -573,3 +577,86 @@ def test_auto_horizon_is_rejected_by_the_engine(I):
     eng = I.Engine(max_queries=2)
     with pytest.raises(I.ImpactError, match="IMPACT_HORIZON_AUTO"):
         eng.submit(imdp, dict(SPECS["affine2_window"], eps=1e-8, max_sweeps=10, horizon="auto"))
+
+
+# ---------------------------------------------------------------------------
+# disturbance player (eq. (5.1)): rows (s, u, w), worst over w, best over u
+# ---------------------------------------------------------------------------
+
+def _disturbed(seed, n_dist=3, d=2, n=7):
+    system = W.tiny_affine(d=d, n=n, seed=seed, n_inputs=3)
+    rng = np.random.default_rng(seed + 100)
+    return dict(system, D=rng.normal(0, 0.3, (d, 2)),
+                disturbances=rng.uniform(-0.5, 0.5, (n_dist, 2)))
+
+
+@pytest.mark.parametrize("storage", ["bounds", "factors"])
+def test_disturbance_build_parity(I, storage):
+    system = _disturbed(3)
+    g = I.build_imdp(system, storage=storage)
+    info = g.info()
+    assert info["n_dist"] == 3 and info["n_inputs"] == 3
+    o = oracle.build(system, system["k_sigma"])
+    R = info["n_rows"]
+    assert R == o["row_ptr"].size - 1 == 49 * 9
+    compare_rows(g.export_rows(0, R), o, R, 2, f"disturbed build [{storage}]")
+
+
+DIST_SPECS = {
+    "reach_avoid": dict(kind="reach_avoid", target=[[[0.5, 0.5], [2.0, 2.0]]],
+                        avoid=[[[-2.0, -2.0], [-1.0, -1.0]]]),
+    "safety": dict(kind="safety", target=[], avoid=[[[-0.5, -0.5], [0.5, 0.5]]]),
+}
+
+
+@pytest.mark.parametrize("horizon", [0, 6])
+@pytest.mark.parametrize("pessimistic", [True, False], ids=["pess", "opt"])
+@pytest.mark.parametrize("kind", list(DIST_SPECS))
+def test_disturbance_iterate_parity(I, kind, pessimistic, horizon):
+    system = _disturbed(21 if kind == "safety" else 12)
+    spec = dict(DIST_SPECS[kind], eps=1e-8, max_sweeps=1 if horizon else 3000,
+                pessimistic=pessimistic, horizon=horizon)
+    say(f"disturbed iterate: {kind} pessimistic={pessimistic} horizon={horizon}")
+    g = I.build_imdp(system)
+    g.set_sweep_modes("state_box", "state_box")   # ignored: disturbed handles sweep per row
+    rg = g.iterate(spec)
+    m = oracle.build(system, system["k_sigma"])
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    ro = oracle.iterate(m["n_states"], 3, m["row_ptr"], m["target"], m["lo"], m["hi"], cls,
+                        spec["kind"], spec["eps"], spec["max_sweeps"], want_q0=True,
+                        optimistic=not pessimistic, horizon=horizon, n_dist=3)
+    assert rg["status"] == ro["status"]
+    compare_iter(rg, ro, cls, kind != "safety", f"disturbed {kind}", q0=ro["q0"], model=m,
+                 spec=spec, optimistic=not pessimistic, n_dist=3)
+
+
+def test_disturbance_with_long_rows_uses_the_workgroup_path(I):
+    # dense rows of 26 x 26 + 1 = 677 entries go to the workgroup LP
+    system = dict(kind="affine", A=np.eye(2) * 0.8, B=np.eye(2) * 0.5, c=np.zeros(2),
+                  lb=[-2.0, -2.0], ub=[2.0, 2.0], n=[26, 26], inputs=[[0.5, 0.0], [0.0, 0.5]],
+                  sigma=[0.3, 0.3], k_sigma=0.0, D=np.eye(2) * 0.2,
+                  disturbances=[[1.0, 0.0], [0.0, -1.0]])
+    spec = dict(kind="reach_avoid", target=[[[1.0, 1.0], [2.0, 2.0]]],
+                avoid=[[[-0.5, -0.5], [0.5, 0.5]]], eps=1e-8, max_sweeps=40)
+    g = I.build_imdp(system)
+    assert g.info()["max_row"] > 512
+    rg = g.iterate(spec)
+    m = oracle.build(system, 0.0)
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    ro = oracle.iterate(m["n_states"], 2, m["row_ptr"], m["target"], m["lo"], m["hi"], cls,
+                        spec["kind"], spec["eps"], spec["max_sweeps"], want_q0=True, n_dist=2)
+    compare_iter(rg, ro, cls, True, "disturbed long rows", q0=ro["q0"], model=m, spec=spec,
+                 n_dist=2)
+
+
+def test_disturbance_rejections(I):
+    system = _disturbed(5)
+    g = I.build_imdp(system)
+    eng = I.Engine(max_queries=2)
+    with pytest.raises(I.ImpactError, match="disturbance"):
+        eng.submit(g, dict(DIST_SPECS["reach_avoid"], eps=1e-8, max_sweeps=10))
+    with pytest.raises(ValueError):
+        I.build_imdp_batch([system])
+    uni = dict(W.unicycle3d(n=(6, 6, 4))[0], D=np.eye(3), disturbances=[[0.0, 0.0, 0.0]])
+    with pytest.raises(I.ImpactError, match="affine"):
+        I.build_imdp(uni)
