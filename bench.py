@@ -338,7 +338,8 @@ def run_disturbed(args):
         "sweeps": list(it["sweeps"]),
         "converged": list(it["converged"]),
         "rows_per_sweep_pass1": rows,
-        "roofline": {"kernel": "k_sweep policy pass (per-row LP, all (u, w) rows)",
+        "roofline": {"kernel": ("k_sweep_sb" if info["max_box"] <= 512 and info["max_row"] <= 512
+                                else "k_sweep") + " policy pass (all (u, w) rows per SAFE state)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_sweep": bytes_sweep, "avg_launch_ms": launch_ms},

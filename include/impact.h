@@ -158,9 +158,10 @@ typedef struct {
  * input) by its worst row -- the lowest satisfaction probability for reach,
  * the highest bad-set probability for safety -- in both passes (eq. (5.1):
  * the disturbance is an adversary whatever the policy), and the policy
- * chooses the input only.  Such handles iterate with the per-row sweep
- * kernels (the sweep mode is ignored) and are rejected by the multi-query
- * engine.  Errors as impact_build_imdp, plus E_INVAL for count or dim_w < 1,
+ * chooses the input only.  Such handles sweep both passes by state box
+ * (one sort per state serving all its input and disturbance rows) when a
+ * state's rows fit a box of 512 cells and the per-row mode is not set, and
+ * per row otherwise; the multi-query engine rejects them.  Errors as impact_build_imdp, plus E_INVAL for count or dim_w < 1,
  * null values or D, or non-finite entries; E_UNSUPPORTED for a non-affine
  * system, dim_u + dim_w > 8 or more than 256 (input, disturbance) pairs.
  */

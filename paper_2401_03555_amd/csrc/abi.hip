@@ -664,10 +664,13 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       // row fits a wavefront; the fixed-input pass has one row per state and
       // sorts per row unless the state-box mode is forced
       const int32_t mode = h->sweep_mode[pass];
-      // (with a disturbance player every pass runs the per-row kernels)
-      const bool use_box = h->nw == 1 && h->max_row <= 512 &&
-                           (mode == IMPACT_SWEEP_STATE_BOX ||
-                            (mode == IMPACT_SWEEP_AUTO && pass == 0));
+      // (with a disturbance player the state box must hold a whole state's
+      // rows; the fixed-input pass then also sweeps by state box, so that an
+      // item's disturbance rows share one sort)
+      const bool use_box = h->max_row <= 512 &&
+                           (h->nw > 1 ? h->max_box <= 512 && mode != IMPACT_SWEEP_PER_ROW
+                                      : (mode == IMPACT_SWEEP_STATE_BOX ||
+                                         (mode == IMPACT_SWEEP_AUTO && pass == 0)));
       SweepArgs a{};
       a.row_off = h->row_off;
       a.win = h->win;

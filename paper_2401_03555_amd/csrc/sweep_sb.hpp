@@ -65,6 +65,15 @@ __device__ __forceinline__ int row_input(const SweepArgs& a, int64_t s, int ui) 
   return PASS == 0 ? ui : a.pi[s];
 }
 
+// Row of item ui of state s (an input of the policy pass, the policy's input
+// in the fixed-input pass) and disturbance w; without a disturbance player
+// (DIST false) w is 0 and rows are s * nu + u.
+template <int PASS, bool DIST>
+__device__ __forceinline__ int64_t item_row(const SweepArgs& a, int64_t s, int ui, int w) {
+  const int64_t su = s * a.nu + row_input<PASS>(a, s, ui);
+  return DIST ? su * a.nw + w : su;
+}
+
 // Inclusive prefix min / max across the wavefront (lane l: over lanes 0..l).
 __device__ __forceinline__ int wave_prefix_min_i32(int x, int lane) {
 #pragma unroll
@@ -89,7 +98,7 @@ __device__ __forceinline__ int wave_prefix_max_i32(int x, int lane) {
 // larger.  Rows whose window is empty in some dimension hold no cells and do
 // not widen the box.  D > 0: the grid dimension is the compile-time D (every
 // dimension loop unrolls to straight-line code); D == 0: read at run time.
-template <int PASS, int D>
+template <int PASS, int D, bool DIST = false>
 __device__ __forceinline__ int group_box(const SweepArgs& a, int64_t s, int g0, int U, int64_t cap, int lane,
                          StateBox& b) {
   const int d = D > 0 ? D : a.d;
@@ -100,15 +109,29 @@ __device__ __forceinline__ int group_box(const SweepArgs& a, int64_t s, int g0, 
   }
   const int ui = g0 + lane;
   if (ui < U) {
-    const int64_t row = s * a.nu + row_input<PASS>(a, s, ui);
-    const int32_t* wr = a.win + row * 2 * d;
-    bool empty = false;
-    IMPACT_FOR_DIMS(i, d) empty = empty || wr[d + i] == 0;
-    if (!empty)
-      IMPACT_FOR_DIMS(i, d) {
-        lo[i] = wr[i];
-        hi[i] = wr[i] + wr[d + i];
+    if constexpr (DIST) {
+      // an item's box covers the windows of all its disturbance rows
+      for (int w = 0; w < a.nw; ++w) {
+        const int32_t* wr = a.win + item_row<PASS, true>(a, s, ui, w) * 2 * d;
+        bool empty = false;
+        IMPACT_FOR_DIMS(i, d) empty = empty || wr[d + i] == 0;
+        if (!empty)
+          IMPACT_FOR_DIMS(i, d) {
+            lo[i] = wr[i] < lo[i] ? wr[i] : lo[i];
+            hi[i] = wr[i] + wr[d + i] > hi[i] ? wr[i] + wr[d + i] : hi[i];
+          }
       }
+    } else {
+      const int64_t row = s * a.nu + row_input<PASS>(a, s, ui);
+      const int32_t* wr = a.win + row * 2 * d;
+      bool empty = false;
+      IMPACT_FOR_DIMS(i, d) empty = empty || wr[d + i] == 0;
+      if (!empty)
+        IMPACT_FOR_DIMS(i, d) {
+          lo[i] = wr[i];
+          hi[i] = wr[i] + wr[d + i];
+        }
+    }
   }
   int64_t P = 1;
   IMPACT_FOR_DIMS(i, d) {
@@ -401,7 +424,7 @@ __device__ double sb_row_scan(const double (&dd)[EL], const uint32_t (&pk)[EL], 
 // holding up to 8 of the row's window cells with their widths, values and
 // order positions.  The group's best is merged into (best0, best1, arg),
 // which hold the earlier groups' (lower inputs') best.
-template <int E, int GW, int PASS, int D, bool SCAN>
+template <int E, int GW, int PASS, int D, bool SCAN, bool DIST = false>
 __device__ __forceinline__ void sb_state(const SweepArgs& a, const SysParams& p, int64_t s, int g0, int g1,
                          const StateBox& b, int lane, SbLds<64 * E>& L, double& best0,
                          double& best1, int& arg) {
@@ -468,6 +491,11 @@ __device__ __forceinline__ void sb_state(const SweepArgs& a, const SysParams& p,
   for (int ui0 = g0; ui0 < g1; ui0 += NG) {
     const int ui = ui0 + g;
     const bool act = ui < g1;
+    int u = 0;
+    // with a disturbance player the item's value is its worst row over them
+    double wq0 = 0.0, wq1 = 0.0;
+    // one row of the item: its LP values, folded into the item's value
+    auto row_pass = [&](const int w) __attribute__((always_inline)) {
     double dd[EL];
     uint32_t pk[EL];
     double lane_lo = 0.0, lq0 = 0.0, lq1 = 0.0;
@@ -476,11 +504,10 @@ __device__ __forceinline__ void sb_state(const SweepArgs& a, const SysParams& p,
       dd[k] = 0.0;
       pk[k] = kNoEntry;
     }
-    int u = 0;
     int64_t row = 0;
     if (act) {
       u = row_input<PASS>(a, s, ui);
-      row = s * a.nu + u;
+      row = item_row<PASS, DIST>(a, s, ui, w);
       const int64_t base = a.row_off[row];
       const int nw = (int)(a.row_off[row + 1] - base);
       if (nw > 0) {
@@ -558,12 +585,32 @@ __device__ __forceinline__ void sb_state(const SweepArgs& a, const SysParams& p,
         q0 = sb_row_lp<EL, GW, 64 * E>(dd, pk, 0, L, (int)PB, r, s0, mx, sp);
         q1 = sb_row_lp<EL, GW, 64 * E>(dd, pk, 1, L, (int)PB, r, s1, mx, sp);
       }
-      // rows of a group come in increasing u: a strict improvement keeps the lowest u
-      if (a.reach ? (q0 > gb0) : (q0 < gb0)) {
-        gb0 = q0;
-        garg = u;
+      if constexpr (DIST) {
+        wq0 = w == 0 ? q0 : (a.reach ? fmin(wq0, q0) : fmax(wq0, q0));
+        wq1 = w == 0 ? q1 : (a.reach ? fmin(wq1, q1) : fmax(wq1, q1));
+      } else {
+        // rows of a group come in increasing u: a strict improvement keeps the lowest u
+        if (a.reach ? (q0 > gb0) : (q0 < gb0)) {
+          gb0 = q0;
+          garg = u;
+        }
+        if (a.reach ? (q1 > gb1) : (q1 < gb1)) gb1 = q1;
       }
-      if (a.reach ? (q1 > gb1) : (q1 < gb1)) gb1 = q1;
+    }
+    };
+    if constexpr (DIST) {
+      for (int w = 0; w < a.nw; ++w) row_pass(w);
+    } else {
+      row_pass(0);
+    }
+    if constexpr (DIST) {
+      if (act) {
+        if (a.reach ? (wq0 > gb0) : (wq0 < gb0)) {
+          gb0 = wq0;
+          garg = u;
+        }
+        if (a.reach ? (wq1 > gb1) : (wq1 < gb1)) gb1 = wq1;
+      }
     }
   }
   // combine the lane groups: best value, lowest input on exact ties
@@ -593,7 +640,7 @@ __device__ __forceinline__ void sb_state(const SweepArgs& a, const SysParams& p,
 // cells (one sort per group); a single row always fits, because the state-box
 // kernels run only on abstractions whose rows have at most 512 entries and
 // ESB is 8 unless every state's whole box fits.
-template <int ESB, int GW, int PASS, int D>
+template <int ESB, int GW, int PASS, int D, bool DIST = false>
 __device__ __forceinline__ double sb_sweep_state(const SweepArgs& a, int64_t s, int lane,
                                                 SbLds<64 * ESB>& L) {
   const SysParams& p = *a.sys;
@@ -603,19 +650,19 @@ __device__ __forceinline__ double sb_sweep_state(const SweepArgs& a, int64_t s, 
   int arg = 0x7fffffff;
   for (int g0 = 0; g0 < U;) {
     StateBox b;
-    const int g1 = uniform_i32(group_box<PASS, D>(a, s, g0, U, 64 * ESB, lane, b));
+    const int g1 = uniform_i32(group_box<PASS, D, DIST>(a, s, g0, U, 64 * ESB, lane, b));
     if (ESB == 1 || b.P <= 64)
-      sb_state<1, GW, PASS, D, (ESB <= 2)>(a, p, s, g0, g1, b, lane, *(SbLds<64>*)&L, best0, best1, arg);
+      sb_state<1, GW, PASS, D, (ESB <= 2), DIST>(a, p, s, g0, g1, b, lane, *(SbLds<64>*)&L, best0,
+                                                 best1, arg);
     else if (ESB == 2 || b.P <= 128)
-      sb_state<(ESB < 2 ? ESB : 2), GW, PASS, D, (ESB <= 2)>(a, p, s, g0, g1, b, lane,
-                                              *(SbLds<64 * (ESB < 2 ? ESB : 2)>*)&L, best0,
-                                              best1, arg);
+      sb_state<(ESB < 2 ? ESB : 2), GW, PASS, D, (ESB <= 2), DIST>(
+          a, p, s, g0, g1, b, lane, *(SbLds<64 * (ESB < 2 ? ESB : 2)>*)&L, best0, best1, arg);
     else if (ESB == 4 || b.P <= 256)
-      sb_state<(ESB < 4 ? ESB : 4), GW, PASS, D, (ESB <= 2)>(a, p, s, g0, g1, b, lane,
-                                              *(SbLds<64 * (ESB < 4 ? ESB : 4)>*)&L, best0,
-                                              best1, arg);
+      sb_state<(ESB < 4 ? ESB : 4), GW, PASS, D, (ESB <= 2), DIST>(
+          a, p, s, g0, g1, b, lane, *(SbLds<64 * (ESB < 4 ? ESB : 4)>*)&L, best0, best1, arg);
     else
-      sb_state<ESB, GW, PASS, D, (ESB <= 2)>(a, p, s, g0, g1, b, lane, L, best0, best1, arg);
+      sb_state<ESB, GW, PASS, D, (ESB <= 2), DIST>(a, p, s, g0, g1, b, lane, L, best0, best1,
+                                                   arg);
     g0 = g1;
     wave_lds_sync();
   }
@@ -627,7 +674,7 @@ __device__ __forceinline__ double sb_sweep_state(const SweepArgs& a, int64_t s, 
   return gap > 0.0 ? gap : 0.0;
 }
 
-template <int ESB, int GW, int PASS, int D>
+template <int ESB, int GW, int PASS, int D, bool DIST = false>
 __global__ __launch_bounds__(64 * kSbWaves) void k_sweep_sb(SweepArgs a) {
   if (a.ctrl->done) return;
   __shared__ SbLds<64 * ESB> lds[kSbWaves];
@@ -637,7 +684,7 @@ __global__ __launch_bounds__(64 * kSbWaves) void k_sweep_sb(SweepArgs a) {
   double gap = 0.0;
   if (si < a.n_safe) {
     const int64_t s = uniform_i64(a.safe[si]);
-    gap = sb_sweep_state<ESB, GW, PASS, D>(a, s, lane, lds[wv]);
+    gap = sb_sweep_state<ESB, GW, PASS, D, DIST>(a, s, lane, lds[wv]);
   }
   if (lane == 0) gapw[wv] = gap;
   __syncthreads();
@@ -731,6 +778,27 @@ hipError_t launch_sb_d(const SweepArgs& a, int pass, int64_t max_box, int32_t ma
   return hipGetLastError();
 }
 
+// With a disturbance player (a.nw > 1): the generic-dimension kernels that
+// value each item by its worst disturbance row.  Every item's box (the union
+// of its rows' windows) must fit the capacity: the caller passes the largest
+// state box, at most 512 cells.
+template <int D>
+hipError_t launch_sb_dist(const SweepArgs& a, int pass, int64_t max_box, int32_t max_row,
+                          hipStream_t st) {
+  int eb = 0, gw = 0;
+  if (max_box > 512 || !sb_variant(max_box, max_row, eb, gw)) return hipErrorInvalidValue;
+  const int64_t blocks = (a.n_safe + kSbWaves - 1) / kSbWaves;
+  const dim3 g((unsigned)blocks), bl(64 * kSbWaves);
+#define SBW(E1, G1)                                                              \
+  if (pass == 0)                                                                 \
+    hipLaunchKernelGGL((k_sweep_sb<E1, G1, 0, D, true>), g, bl, 0, st, a);       \
+  else                                                                           \
+    hipLaunchKernelGGL((k_sweep_sb<E1, G1, 1, D, true>), g, bl, 0, st, a);
+  IMPACT_SB_SWITCH(SBW)
+#undef SBW
+  return hipGetLastError();
+}
+
 template <int D>
 hipError_t launch_mq_sb_d(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
                           const int32_t* ws, int64_t n_items, double* gap_item, int64_t max_box,
@@ -759,5 +827,7 @@ IMPACT_SB_DECLARE(3)
 IMPACT_SB_DECLARE(5)
 IMPACT_SB_DECLARE(0)
 #undef IMPACT_SB_DECLARE
+extern template hipError_t launch_sb_dist<0>(const SweepArgs&, int, int64_t, int32_t,
+                                             hipStream_t);
 
 }  // namespace impact

@@ -609,16 +609,17 @@ DIST_SPECS = {
 }
 
 
+@pytest.mark.parametrize("mode", ["state_box", "per_row"])
 @pytest.mark.parametrize("horizon", [0, 6])
 @pytest.mark.parametrize("pessimistic", [True, False], ids=["pess", "opt"])
 @pytest.mark.parametrize("kind", list(DIST_SPECS))
-def test_disturbance_iterate_parity(I, kind, pessimistic, horizon):
+def test_disturbance_iterate_parity(I, kind, pessimistic, horizon, mode):
     system = _disturbed(21 if kind == "safety" else 12)
     spec = dict(DIST_SPECS[kind], eps=1e-8, max_sweeps=1 if horizon else 3000,
                 pessimistic=pessimistic, horizon=horizon)
-    say(f"disturbed iterate: {kind} pessimistic={pessimistic} horizon={horizon}")
+    say(f"disturbed iterate: {kind} pessimistic={pessimistic} horizon={horizon} [{mode}]")
     g = I.build_imdp(system)
-    g.set_sweep_modes("state_box", "state_box")   # ignored: disturbed handles sweep per row
+    g.set_sweep_modes(mode, mode)
     rg = g.iterate(spec)
     m = oracle.build(system, system["k_sigma"])
     cls = oracle.label(system, spec["target"], spec["avoid"])
@@ -660,3 +661,21 @@ def test_disturbance_rejections(I):
     uni = dict(W.unicycle3d(n=(6, 6, 4))[0], D=np.eye(3), disturbances=[[0.0, 0.0, 0.0]])
     with pytest.raises(I.ImpactError, match="affine"):
         I.build_imdp(uni)
+
+
+def test_disturbance_robot2d_state_box_equals_per_row(I):
+    # the measured disturbed workload (dense 401-entry rows, 99 rows per state)
+    # with a sweep cap: both sweep kernels against the oracle at 25 sweeps
+    system, spec = W.robot2d_disturbed()
+    spec = dict(spec, max_sweeps=25)
+    m = oracle.build(system, 0.0)
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    ro = oracle.iterate(m["n_states"], 9, m["row_ptr"], m["target"], m["lo"], m["hi"], cls,
+                        spec["kind"], spec["eps"], 25, want_q0=True, n_dist=11)
+    for mode in ("state_box", "per_row"):
+        g = I.build_imdp(system)
+        g.set_sweep_modes(mode, mode)
+        rg = g.iterate(spec)
+        assert rg["status"] == ro["status"] == 1
+        compare_iter(rg, ro, cls, True, f"robot2d disturbed [{mode}]", q0=ro["q0"], model=m,
+                     spec=spec, n_dist=11)
