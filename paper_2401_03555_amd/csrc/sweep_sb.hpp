@@ -65,15 +65,6 @@ __device__ __forceinline__ int row_input(const SweepArgs& a, int64_t s, int ui) 
   return PASS == 0 ? ui : a.pi[s];
 }
 
-// Row of item ui of state s (an input of the policy pass, the policy's input
-// in the fixed-input pass) and disturbance w; without a disturbance player
-// (DIST false) w is 0 and rows are s * nu + u.
-template <int PASS, bool DIST>
-__device__ __forceinline__ int64_t item_row(const SweepArgs& a, int64_t s, int ui, int w) {
-  const int64_t su = s * a.nu + row_input<PASS>(a, s, ui);
-  return DIST ? su * a.nw + w : su;
-}
-
 // Inclusive prefix min / max across the wavefront (lane l: over lanes 0..l).
 __device__ __forceinline__ int wave_prefix_min_i32(int x, int lane) {
 #pragma unroll
@@ -98,7 +89,7 @@ __device__ __forceinline__ int wave_prefix_max_i32(int x, int lane) {
 // larger.  Rows whose window is empty in some dimension hold no cells and do
 // not widen the box.  D > 0: the grid dimension is the compile-time D (every
 // dimension loop unrolls to straight-line code); D == 0: read at run time.
-template <int PASS, int D, bool DIST = false>
+template <int PASS, int D>
 __device__ __forceinline__ int group_box(const SweepArgs& a, int64_t s, int g0, int U, int64_t cap, int lane,
                          StateBox& b) {
   const int d = D > 0 ? D : a.d;
@@ -109,29 +100,15 @@ __device__ __forceinline__ int group_box(const SweepArgs& a, int64_t s, int g0, 
   }
   const int ui = g0 + lane;
   if (ui < U) {
-    if constexpr (DIST) {
-      // an item's box covers the windows of all its disturbance rows
-      for (int w = 0; w < a.nw; ++w) {
-        const int32_t* wr = a.win + item_row<PASS, true>(a, s, ui, w) * 2 * d;
-        bool empty = false;
-        IMPACT_FOR_DIMS(i, d) empty = empty || wr[d + i] == 0;
-        if (!empty)
-          IMPACT_FOR_DIMS(i, d) {
-            lo[i] = wr[i] < lo[i] ? wr[i] : lo[i];
-            hi[i] = wr[i] + wr[d + i] > hi[i] ? wr[i] + wr[d + i] : hi[i];
-          }
+    const int64_t row = s * a.nu + row_input<PASS>(a, s, ui);
+    const int32_t* wr = a.win + row * 2 * d;
+    bool empty = false;
+    IMPACT_FOR_DIMS(i, d) empty = empty || wr[d + i] == 0;
+    if (!empty)
+      IMPACT_FOR_DIMS(i, d) {
+        lo[i] = wr[i];
+        hi[i] = wr[i] + wr[d + i];
       }
-    } else {
-      const int64_t row = s * a.nu + row_input<PASS>(a, s, ui);
-      const int32_t* wr = a.win + row * 2 * d;
-      bool empty = false;
-      IMPACT_FOR_DIMS(i, d) empty = empty || wr[d + i] == 0;
-      if (!empty)
-        IMPACT_FOR_DIMS(i, d) {
-          lo[i] = wr[i];
-          hi[i] = wr[i] + wr[d + i];
-        }
-    }
   }
   int64_t P = 1;
   IMPACT_FOR_DIMS(i, d) {
@@ -424,8 +401,322 @@ __device__ double sb_row_scan(const double (&dd)[EL], const uint32_t (&pk)[EL], 
 // holding up to 8 of the row's window cells with their widths, values and
 // order positions.  The group's best is merged into (best0, best1, arg),
 // which hold the earlier groups' (lower inputs') best.
-template <int E, int GW, int PASS, int D, bool SCAN, bool DIST = false>
+template <int E, int GW, int PASS, int D, bool SCAN>
 __device__ __forceinline__ void sb_state(const SweepArgs& a, const SysParams& p, int64_t s, int g0, int g1,
+                         const StateBox& b, int lane, SbLds<64 * E>& L, double& best0,
+                         double& best1, int& arg) {
+  constexpr int NG = 64 / GW, EL = kSbEntriesPerLane;
+  const int d = D > 0 ? D : a.d;
+  const bool mx = a.maximise != 0;
+  const int64_t PB = b.P;
+  {
+    uint64_t k0[E], k1[E];
+    int32_t p0[E], p1[E];
+    // values over the box, blocked layout: lane holds positions lane*E + e
+    int32_t c[kMaxDim];
+    int64_t rem = (int64_t)lane * E < PB ? (int64_t)lane * E : 0;
+    int64_t t = 0;
+    IMPACT_FOR_DIMS_REV(i, d) {
+      c[i] = PB > 0 ? (int32_t)(rem % b.ext[i]) : 0;
+      rem = PB > 0 ? rem / b.ext[i] : 0;
+    }
+    IMPACT_FOR_DIMS(i, d) t += ((int64_t)b.blo[i] + c[i]) * p.stride[i];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int bi = lane * E + e;
+      p0[e] = bi;
+      p1[e] = bi;
+      if (bi < PB) {
+        const double2 V = a.vin[t];
+        L.vb[bi] = V;
+        const uint64_t b0 = dbits(V.x + 0.0), b1 = dbits(V.y + 0.0);
+        k0[e] = mx ? ~b0 : b0;
+        k1[e] = mx ? ~b1 : b1;
+        IMPACT_FOR_DIMS_REV(i, d) {
+          ++c[i];
+          t += p.stride[i];
+          if (c[i] < b.ext[i]) break;
+          c[i] = 0;
+          t -= (int64_t)b.ext[i] * p.stride[i];
+        }
+      } else {
+        k0[e] = ~0ull;
+        k1[e] = ~0ull;
+      }
+    }
+    if constexpr (E >= 8) {
+      // one order at a time: half the registers of the paired network
+      bitonic_sort1<E>(k0, p0, lane);
+      bitonic_sort1<E>(k1, p1, lane);
+    } else {
+      bitonic_sort2<E>(k0, p0, k1, p1, lane);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = lane * E + e;
+      if (p0[e] < PB) L.rk[0][p0[e]] = (uint16_t)j;
+      if (p1[e] < PB) L.rk[1][p1[e]] = (uint16_t)j;
+    }
+  }
+  wave_lds_sync();
+
+  const int g = lane / GW, gl = lane % GW;
+  const double tail_v = mx ? 1.0 : 0.0;
+  const double worst = a.reach ? -1.0 : 2.0;
+  double gb0 = worst, gb1 = worst;
+  int garg = 0x7fffffff;
+  for (int ui0 = g0; ui0 < g1; ui0 += NG) {
+    const int ui = ui0 + g;
+    const bool act = ui < g1;
+    double dd[EL];
+    uint32_t pk[EL];
+    double lane_lo = 0.0, lq0 = 0.0, lq1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < EL; ++k) {
+      dd[k] = 0.0;
+      pk[k] = kNoEntry;
+    }
+    int u = 0;
+    int64_t row = 0;
+    if (act) {
+      u = row_input<PASS>(a, s, ui);
+      row = s * a.nu + u;
+      const int64_t base = a.row_off[row];
+      const int nw = (int)(a.row_off[row + 1] - base);
+      if (nw > 0) {
+        const int32_t* wr = a.win + row * 2 * d;
+        int32_t W[kMaxDim], off[kMaxDim], j[kMaxDim], inc[kMaxDim], fo[kMaxDim];
+        int tot = 0;
+        IMPACT_FOR_DIMS(i, d) {
+          W[i] = wr[d + i];
+          off[i] = wr[i] - b.blo[i];
+          fo[i] = tot;
+          tot += W[i];
+        }
+        int64_t q0i = gl, q1i = GW;
+        IMPACT_FOR_DIMS_REV(i, d) {
+          j[i] = (int32_t)(q0i % W[i]);
+          q0i /= W[i];
+          inc[i] = (int32_t)(q1i % W[i]);
+          q1i /= W[i];
+        }
+        const double2* fr = a.fac ? a.fac + row * (int64_t)a.fs : nullptr;
+#pragma unroll
+        for (int k = 0; k < EL; ++k) {
+          const int slot = gl + k * GW;
+          if (slot < nw) {
+            int bi = 0;
+            IMPACT_FOR_DIMS(i, d) bi += (off[i] + j[i]) * b.bstride[i];
+            double2 e;
+            if (a.storage == IMPACT_STORE_FACTORS) {
+              double lo = 1.0, hi = 1.0;
+              IMPACT_FOR_DIMS(i, d) {
+                const double2 fv = fr[fo[i] + j[i]];
+                lo *= fv.x;
+                hi *= fv.y;
+              }
+              e = make_double2(lo, hi);
+            } else {
+              e = a.ent[base + slot];
+            }
+            const double2 V = L.vb[bi];
+            dd[k] = e.y - e.x;
+            pk[k] = (uint32_t)L.rk[0][bi] | ((uint32_t)L.rk[1][bi] << 10) | ((uint32_t)bi << 20);
+            lane_lo += e.x;
+            lq0 += e.x * V.x;
+            lq1 += e.x * V.y;
+            int carry = 0;
+            IMPACT_FOR_DIMS_REV(i, d) {
+              j[i] += inc[i] + carry;
+              carry = j[i] >= W[i];
+              if (carry) j[i] -= W[i];
+            }
+          }
+        }
+      }
+    }
+    if (act) {
+      const double4 o = a.ot[row];
+      Specials sp;
+      sp.n = 1 + a.windowed;
+      sp.lo[0] = o.x;
+      sp.dd[0] = o.y - o.x;
+      sp.v[0] = a.out_val;
+      sp.lo[1] = o.z;
+      sp.dd[1] = o.w - o.z;
+      sp.v[1] = tail_v;
+      double slo = group_sum<GW>(lane_lo) + o.x;
+      if (a.windowed) slo += o.z;
+      double r = 1.0 - slo;
+      if (r < 0.0) r = 0.0;
+      const double s0 = group_sum<GW>(lq0), s1 = group_sum<GW>(lq1);
+      double q0, q1;
+      if constexpr (SCAN && E <= 2) {
+        q0 = sb_row_scan<EL, GW, E>(dd, pk, 0, L, L.stg[g], gl, r, s0, mx, sp);
+        q1 = sb_row_scan<EL, GW, E>(dd, pk, 1, L, L.stg[g], gl, r, s1, mx, sp);
+      } else {
+        q0 = sb_row_lp<EL, GW, 64 * E>(dd, pk, 0, L, (int)PB, r, s0, mx, sp);
+        q1 = sb_row_lp<EL, GW, 64 * E>(dd, pk, 1, L, (int)PB, r, s1, mx, sp);
+      }
+      // rows of a group come in increasing u: a strict improvement keeps the lowest u
+      if (a.reach ? (q0 > gb0) : (q0 < gb0)) {
+        gb0 = q0;
+        garg = u;
+      }
+      if (a.reach ? (q1 > gb1) : (q1 < gb1)) gb1 = q1;
+    }
+  }
+  // combine the lane groups: best value, lowest input on exact ties
+#pragma unroll
+  for (int off = GW; off < 64; off <<= 1) {
+    const double o0 = __shfl_xor(gb0, off), o1 = __shfl_xor(gb1, off);
+    const int oa = __shfl_xor(garg, off);
+    const bool better = a.reach ? (o0 > gb0 || (o0 == gb0 && oa < garg))
+                                : (o0 < gb0 || (o0 == gb0 && oa < garg));
+    if (better) {
+      gb0 = o0;
+      garg = oa;
+    }
+    gb1 = a.reach ? fmax(gb1, o1) : fmin(gb1, o1);
+  }
+  // earlier groups hold lower inputs: a strict improvement is needed to replace them
+  if (a.reach ? (gb0 > best0) : (gb0 < best0)) {
+    best0 = gb0;
+    arg = garg;
+  }
+  best1 = a.reach ? fmax(best1, gb1) : fmin(best1, gb1);
+}
+
+// Sweep update of one SAFE state s on one wavefront: writes vout[s] (and
+// pi[s] in the policy pass); returns the state's V1 - V0 (>= 0).  The inputs
+// are taken in consecutive groups whose windows' box holds at most 64 * ESB
+// cells (one sort per group); a single row always fits, because the state-box
+// kernels run only on abstractions whose rows have at most 512 entries and
+// ESB is 8 unless every state's whole box fits.
+template <int ESB, int GW, int PASS, int D>
+__device__ __forceinline__ double sb_sweep_state(const SweepArgs& a, int64_t s, int lane,
+                                                SbLds<64 * ESB>& L) {
+  const SysParams& p = *a.sys;
+  const int U = PASS == 0 ? a.nu : 1;
+  const double worst = a.reach ? -1.0 : 2.0;
+  double best0 = worst, best1 = worst;
+  int arg = 0x7fffffff;
+  for (int g0 = 0; g0 < U;) {
+    StateBox b;
+    const int g1 = uniform_i32(group_box<PASS, D>(a, s, g0, U, 64 * ESB, lane, b));
+    if (ESB == 1 || b.P <= 64)
+      sb_state<1, GW, PASS, D, (ESB <= 2)>(a, p, s, g0, g1, b, lane, *(SbLds<64>*)&L, best0, best1, arg);
+    else if (ESB == 2 || b.P <= 128)
+      sb_state<(ESB < 2 ? ESB : 2), GW, PASS, D, (ESB <= 2)>(a, p, s, g0, g1, b, lane,
+                                              *(SbLds<64 * (ESB < 2 ? ESB : 2)>*)&L, best0,
+                                              best1, arg);
+    else if (ESB == 4 || b.P <= 256)
+      sb_state<(ESB < 4 ? ESB : 4), GW, PASS, D, (ESB <= 2)>(a, p, s, g0, g1, b, lane,
+                                              *(SbLds<64 * (ESB < 4 ? ESB : 4)>*)&L, best0,
+                                              best1, arg);
+    else
+      sb_state<ESB, GW, PASS, D, (ESB <= 2)>(a, p, s, g0, g1, b, lane, L, best0, best1, arg);
+    g0 = g1;
+    wave_lds_sync();
+  }
+  if (lane == 0) {
+    a.vout[s] = make_double2(best0, best1);
+    if (PASS == 0) a.pi[s] = arg;
+  }
+  const double gap = best1 - best0;
+  return gap > 0.0 ? gap : 0.0;
+}
+
+template <int ESB, int GW, int PASS, int D>
+__global__ __launch_bounds__(64 * kSbWaves) void k_sweep_sb(SweepArgs a) {
+  if (a.ctrl->done) return;
+  __shared__ SbLds<64 * ESB> lds[kSbWaves];
+  __shared__ double gapw[kSbWaves];
+  const int tid = threadIdx.x, lane = tid & 63, wv = uniform_i32(tid >> 6);
+  const int64_t si = (int64_t)blockIdx.x * kSbWaves + wv;
+  double gap = 0.0;
+  if (si < a.n_safe) {
+    const int64_t s = uniform_i64(a.safe[si]);
+    gap = sb_sweep_state<ESB, GW, PASS, D>(a, s, lane, lds[wv]);
+  }
+  if (lane == 0) gapw[wv] = gap;
+  __syncthreads();
+  if (tid == 0) {
+    double gm = gapw[0];
+    for (int w = 1; w < kSbWaves; ++w) gm = fmax(gm, gapw[w]);
+    a.gap_part[blockIdx.x] = gm;
+  }
+}
+
+
+// ---- the same sweep with a disturbance player (rows (s, u, w)) -------------
+// Separate copies of the functions above, so that the kernels without a
+// disturbance player keep their register allocation.  A lane group takes an
+// item (an input, or the policy's input) and walks its disturbance rows,
+// keeping the worst; an item's box covers all of its rows' windows.
+
+// Row of item ui of state s (an input of the policy pass, the policy's input
+// in the fixed-input pass) and disturbance w.
+template <int PASS>
+__device__ __forceinline__ int64_t dist_row(const SweepArgs& a, int64_t s, int ui, int w) {
+  return (s * a.nu + row_input<PASS>(a, s, ui)) * a.nw + w;
+}
+
+template <int PASS, int D>
+__device__ __forceinline__ int group_box_dist(const SweepArgs& a, int64_t s, int g0, int U, int64_t cap, int lane,
+                         StateBox& b) {
+  const int d = D > 0 ? D : a.d;
+  int lo[kMaxDim], hi[kMaxDim];
+  IMPACT_FOR_DIMS(i, d) {
+    lo[i] = 0x7fffffff;
+    hi[i] = -0x7fffffff;
+  }
+  const int ui = g0 + lane;
+  if (ui < U) {
+    // an item's box covers the windows of all its disturbance rows
+    for (int w = 0; w < a.nw; ++w) {
+      const int32_t* wr = a.win + dist_row<PASS>(a, s, ui, w) * 2 * d;
+      bool empty = false;
+      IMPACT_FOR_DIMS(i, d) empty = empty || wr[d + i] == 0;
+      if (!empty)
+        IMPACT_FOR_DIMS(i, d) {
+          lo[i] = wr[i] < lo[i] ? wr[i] : lo[i];
+          hi[i] = wr[i] + wr[d + i] > hi[i] ? wr[i] + wr[d + i] : hi[i];
+        }
+    }
+  }
+  int64_t P = 1;
+  IMPACT_FOR_DIMS(i, d) {
+    lo[i] = wave_prefix_min_i32(lo[i], lane);
+    hi[i] = wave_prefix_max_i32(hi[i], lane);
+    P *= hi[i] > lo[i] ? (int64_t)(hi[i] - lo[i]) : 0;
+  }
+  // first lane whose prefix box is too large ends the group (at least one row)
+  const bool over = ui < U && P > cap;
+  const uint64_t m = (uint64_t)__ballot(over);
+  const int n_in = U - g0 < 64 ? U - g0 : 64;
+  int len = m ? __builtin_ctzll(m) : n_in;
+  if (len == 0) len = 1;
+  const int last = len - 1;
+  int64_t PB = 1;
+  IMPACT_FOR_DIMS(i, d) {
+    const int l = uniform_i32(__shfl(lo[i], last)), h = uniform_i32(__shfl(hi[i], last));
+    b.blo[i] = l;
+    b.ext[i] = h > l ? h - l : 0;
+    PB *= b.ext[i];
+  }
+  int32_t st = 1;
+  IMPACT_FOR_DIMS_REV(i, d) {
+    b.bstride[i] = st;
+    st = (int32_t)((int64_t)st * b.ext[i] > 0x3fffffff ? 0x3fffffff : st * b.ext[i]);
+  }
+  b.P = PB;
+  return g0 + len;
+}
+
+
+template <int E, int GW, int PASS, int D, bool SCAN>
+__device__ __forceinline__ void sb_state_dist(const SweepArgs& a, const SysParams& p, int64_t s, int g0, int g1,
                          const StateBox& b, int lane, SbLds<64 * E>& L, double& best0,
                          double& best1, int& arg) {
   constexpr int NG = 64 / GW, EL = kSbEntriesPerLane;
@@ -507,7 +798,7 @@ __device__ __forceinline__ void sb_state(const SweepArgs& a, const SysParams& p,
     int64_t row = 0;
     if (act) {
       u = row_input<PASS>(a, s, ui);
-      row = item_row<PASS, DIST>(a, s, ui, w);
+      row = dist_row<PASS>(a, s, ui, w);
       const int64_t base = a.row_off[row];
       const int nw = (int)(a.row_off[row + 1] - base);
       if (nw > 0) {
@@ -585,32 +876,18 @@ __device__ __forceinline__ void sb_state(const SweepArgs& a, const SysParams& p,
         q0 = sb_row_lp<EL, GW, 64 * E>(dd, pk, 0, L, (int)PB, r, s0, mx, sp);
         q1 = sb_row_lp<EL, GW, 64 * E>(dd, pk, 1, L, (int)PB, r, s1, mx, sp);
       }
-      if constexpr (DIST) {
-        wq0 = w == 0 ? q0 : (a.reach ? fmin(wq0, q0) : fmax(wq0, q0));
-        wq1 = w == 0 ? q1 : (a.reach ? fmin(wq1, q1) : fmax(wq1, q1));
-      } else {
-        // rows of a group come in increasing u: a strict improvement keeps the lowest u
-        if (a.reach ? (q0 > gb0) : (q0 < gb0)) {
-          gb0 = q0;
-          garg = u;
-        }
-        if (a.reach ? (q1 > gb1) : (q1 < gb1)) gb1 = q1;
-      }
+      wq0 = w == 0 ? q0 : (a.reach ? fmin(wq0, q0) : fmax(wq0, q0));
+      wq1 = w == 0 ? q1 : (a.reach ? fmin(wq1, q1) : fmax(wq1, q1));
     }
     };
-    if constexpr (DIST) {
-      for (int w = 0; w < a.nw; ++w) row_pass(w);
-    } else {
-      row_pass(0);
-    }
-    if constexpr (DIST) {
-      if (act) {
-        if (a.reach ? (wq0 > gb0) : (wq0 < gb0)) {
-          gb0 = wq0;
-          garg = u;
-        }
-        if (a.reach ? (wq1 > gb1) : (wq1 < gb1)) gb1 = wq1;
+    for (int w = 0; w < a.nw; ++w) row_pass(w);
+    // items of a group come in increasing u: a strict improvement keeps the lowest u
+    if (act) {
+      if (a.reach ? (wq0 > gb0) : (wq0 < gb0)) {
+        gb0 = wq0;
+        garg = u;
       }
+      if (a.reach ? (wq1 > gb1) : (wq1 < gb1)) gb1 = wq1;
     }
   }
   // combine the lane groups: best value, lowest input on exact ties
@@ -634,14 +911,8 @@ __device__ __forceinline__ void sb_state(const SweepArgs& a, const SysParams& p,
   best1 = a.reach ? fmax(best1, gb1) : fmin(best1, gb1);
 }
 
-// Sweep update of one SAFE state s on one wavefront: writes vout[s] (and
-// pi[s] in the policy pass); returns the state's V1 - V0 (>= 0).  The inputs
-// are taken in consecutive groups whose windows' box holds at most 64 * ESB
-// cells (one sort per group); a single row always fits, because the state-box
-// kernels run only on abstractions whose rows have at most 512 entries and
-// ESB is 8 unless every state's whole box fits.
-template <int ESB, int GW, int PASS, int D, bool DIST = false>
-__device__ __forceinline__ double sb_sweep_state(const SweepArgs& a, int64_t s, int lane,
+template <int ESB, int GW, int PASS, int D>
+__device__ __forceinline__ double sb_sweep_state_dist(const SweepArgs& a, int64_t s, int lane,
                                                 SbLds<64 * ESB>& L) {
   const SysParams& p = *a.sys;
   const int U = PASS == 0 ? a.nu : 1;
@@ -650,18 +921,18 @@ __device__ __forceinline__ double sb_sweep_state(const SweepArgs& a, int64_t s, 
   int arg = 0x7fffffff;
   for (int g0 = 0; g0 < U;) {
     StateBox b;
-    const int g1 = uniform_i32(group_box<PASS, D, DIST>(a, s, g0, U, 64 * ESB, lane, b));
+    const int g1 = uniform_i32(group_box_dist<PASS, D>(a, s, g0, U, 64 * ESB, lane, b));
     if (ESB == 1 || b.P <= 64)
-      sb_state<1, GW, PASS, D, (ESB <= 2), DIST>(a, p, s, g0, g1, b, lane, *(SbLds<64>*)&L, best0,
+      sb_state_dist<1, GW, PASS, D, (ESB <= 2)>(a, p, s, g0, g1, b, lane, *(SbLds<64>*)&L, best0,
                                                  best1, arg);
     else if (ESB == 2 || b.P <= 128)
-      sb_state<(ESB < 2 ? ESB : 2), GW, PASS, D, (ESB <= 2), DIST>(
+      sb_state_dist<(ESB < 2 ? ESB : 2), GW, PASS, D, (ESB <= 2)>(
           a, p, s, g0, g1, b, lane, *(SbLds<64 * (ESB < 2 ? ESB : 2)>*)&L, best0, best1, arg);
     else if (ESB == 4 || b.P <= 256)
-      sb_state<(ESB < 4 ? ESB : 4), GW, PASS, D, (ESB <= 2), DIST>(
+      sb_state_dist<(ESB < 4 ? ESB : 4), GW, PASS, D, (ESB <= 2)>(
           a, p, s, g0, g1, b, lane, *(SbLds<64 * (ESB < 4 ? ESB : 4)>*)&L, best0, best1, arg);
     else
-      sb_state<ESB, GW, PASS, D, (ESB <= 2), DIST>(a, p, s, g0, g1, b, lane, L, best0, best1,
+      sb_state_dist<ESB, GW, PASS, D, (ESB <= 2)>(a, p, s, g0, g1, b, lane, L, best0, best1,
                                                    arg);
     g0 = g1;
     wave_lds_sync();
@@ -674,8 +945,8 @@ __device__ __forceinline__ double sb_sweep_state(const SweepArgs& a, int64_t s, 
   return gap > 0.0 ? gap : 0.0;
 }
 
-template <int ESB, int GW, int PASS, int D, bool DIST = false>
-__global__ __launch_bounds__(64 * kSbWaves) void k_sweep_sb(SweepArgs a) {
+template <int ESB, int GW, int PASS, int D>
+__global__ __launch_bounds__(64 * kSbWaves) void k_sweep_sb_dist(SweepArgs a) {
   if (a.ctrl->done) return;
   __shared__ SbLds<64 * ESB> lds[kSbWaves];
   __shared__ double gapw[kSbWaves];
@@ -684,7 +955,7 @@ __global__ __launch_bounds__(64 * kSbWaves) void k_sweep_sb(SweepArgs a) {
   double gap = 0.0;
   if (si < a.n_safe) {
     const int64_t s = uniform_i64(a.safe[si]);
-    gap = sb_sweep_state<ESB, GW, PASS, D, DIST>(a, s, lane, lds[wv]);
+    gap = sb_sweep_state_dist<ESB, GW, PASS, D>(a, s, lane, lds[wv]);
   }
   if (lane == 0) gapw[wv] = gap;
   __syncthreads();
@@ -791,9 +1062,9 @@ hipError_t launch_sb_dist(const SweepArgs& a, int pass, int64_t max_box, int32_t
   const dim3 g((unsigned)blocks), bl(64 * kSbWaves);
 #define SBW(E1, G1)                                                              \
   if (pass == 0)                                                                 \
-    hipLaunchKernelGGL((k_sweep_sb<E1, G1, 0, D, true>), g, bl, 0, st, a);       \
+    hipLaunchKernelGGL((k_sweep_sb_dist<E1, G1, 0, D>), g, bl, 0, st, a);       \
   else                                                                           \
-    hipLaunchKernelGGL((k_sweep_sb<E1, G1, 1, D, true>), g, bl, 0, st, a);
+    hipLaunchKernelGGL((k_sweep_sb_dist<E1, G1, 1, D>), g, bl, 0, st, a);
   IMPACT_SB_SWITCH(SBW)
 #undef SBW
   return hipGetLastError();
