@@ -234,6 +234,12 @@ typedef struct {
  *   safety: lo = 1 - V1 of pass 1, hi = 1 - V0 of pass 2 (safety probability);
  *   target cells lo = hi = 1, avoid cells lo = hi = 0;
  *   policy = input index on SAFE cells, -1 elsewhere.
+ * That is the pessimistic policy.  With spec->pessimistic = 0 the two passes'
+ * LP directions swap and so do the outputs' sources: reach lo = V0 of pass 2,
+ * hi = V1 of pass 1; safety lo = 1 - V1 of pass 2, hi = 1 - V0 of pass 1.
+ * spec->horizon selects the finite or automatic horizon (see impact_spec);
+ * a handle from impact_build_imdp_dist values each input by its worst
+ * disturbance row in both passes.
  * Returns IMPACT_OK, IMPACT_NOT_CONVERGED (a cap fired; outputs valid), or an
  * error (E_INVAL, E_NOMEM, E_UNSUPPORTED, E_HIP).
  */
