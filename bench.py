@@ -106,9 +106,11 @@ FP64_PEAK_TFLOPS = 78.6
 
 def kernel_source_hash():
     """Digest of what the state-box sweep kernels are compiled from (their
-    sources, the headers they include and the build flags): identifies the
-    build whose hardware counters are recorded under profiles/."""
+    sources, the headers they include and the build flags), comments and
+    blank space removed: identifies the build whose hardware counters are
+    recorded under profiles/, and ignores edits to documentation only."""
     import hashlib
+    import re
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2401_03555_amd")
     csrc = os.path.join(pkg, "csrc")
@@ -117,8 +119,12 @@ def kernel_source_hash():
     files = [os.path.join(csrc, n) for n in names] + [
         os.path.join(ROOT, "include", "impact.h"), os.path.join(pkg, "build_lib.py")]
     for f in files:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f) as fh:
+            text = fh.read()
+        if not f.endswith(".py"):
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
