@@ -128,22 +128,39 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel, storage, workload):
-    """HBM bytes per launch of ``kernel`` from the FETCH_SIZE / WRITE_SIZE
-    summaries under profiles/ (lines ``traffic: key=value ...``), or None when
-    none was recorded for this kernel build."""
+def _recorded(tag, field, kernel, storage, workload):
+    """A per-launch figure of ``kernel`` recorded under profiles/ (lines
+    ``<tag>: key=value ...``) for this kernel build, or None."""
     import glob
     src = kernel_source_hash()
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(f) as fh:
             for line in fh:
-                if not line.startswith("traffic:"):
+                if not line.startswith(tag + ":"):
                     continue
                 kv = dict(x.split("=", 1) for x in line.split()[1:] if "=" in x)
                 if (kv.get("kernel") == kernel and kv.get("storage") == storage
                         and kv.get("workload") == workload and kv.get("src") == src):
-                    return int(kv["bytes_per_launch"])
+                    return float(kv[field])
     return None
+
+
+def recorded_traffic(kernel, storage, workload):
+    """HBM bytes per launch of ``kernel`` from the FETCH_SIZE / WRITE_SIZE
+    summaries under profiles/ (lines ``traffic: ...``), or None."""
+    v = _recorded("traffic", "bytes_per_launch", kernel, storage, workload)
+    return None if v is None else int(v)
+
+
+# wave64 VALU instructions per second the chip can issue: one per SIMD every
+# 4 cycles, 1,024 SIMDs (256 CUs x 4), 2.4 GHz
+VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
+
+
+def recorded_valu(kernel, storage, workload):
+    """Wave64 VALU instructions per launch of ``kernel`` from the SQ counter
+    summary under profiles/ (lines ``valu: ...``), or None."""
+    return _recorded("valu", "valu_per_launch", kernel, storage, workload)
 
 
 def build_roofline(imdp, d):
@@ -528,6 +545,11 @@ def main():
             "avg_launch_ms": avg_launch_ms,
             "launches": launches0,
             "sweeps": sweeps0,
+            # what binds it instead: VALU issue, from the recorded SQ_INSTS_VALU
+            # of this kernel build over the live launch time
+            "valu_issue_frac": (lambda v: None if v is None else
+                                v / (avg_launch_ms * 1e-3) / VALU_ISSUE_PEAK)(
+                recorded_valu("k_sweep_sb" if box else "k_sweep", storage, args.workload)),
         },
     }
     imdp.free()
