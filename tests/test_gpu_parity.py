@@ -661,6 +661,12 @@ def test_disturbance_rejections(I):
     uni = dict(W.unicycle3d(n=(6, 6, 4))[0], D=np.eye(3), disturbances=[[0.0, 0.0, 0.0]])
     with pytest.raises(I.ImpactError, match="affine"):
         I.build_imdp(uni)
+    bad = dict(system, disturbances=np.array([[0.0, np.nan], [0.1, 0.2]]))
+    with pytest.raises(I.ImpactError, match="non-finite"):
+        I.build_imdp(bad)
+    many = dict(system, disturbances=np.zeros((90, 2)))   # 3 inputs x 90 > 256 rows per state
+    with pytest.raises(I.ImpactError, match="256"):
+        I.build_imdp(many)
 
 
 def test_disturbance_robot2d_state_box_equals_per_row(I):
