@@ -8,7 +8,13 @@ namespace impact {
 hipError_t launch_sweep_sb(const SweepArgs& a, int64_t max_box, int32_t max_row, hipStream_t st) {
   if (a.n_safe == 0) return hipSuccess;
   // a disturbance player: items of several rows, boxes up to the state's
-  if (a.nw > 1) return launch_sb_dist<0>(a, a.pass, max_box, max_row, st);
+  if (a.nw > 1) {
+    switch (a.d) {
+      case 2: return launch_sb_dist<2>(a, a.pass, max_box, max_row, st);
+      case 3: return launch_sb_dist<3>(a, a.pass, max_box, max_row, st);
+      default: return launch_sb_dist<0>(a, a.pass, max_box, max_row, st);
+    }
+  }
   // pass 2 uses one row per state: its box is the row's own window
   const int64_t box = a.pass == 0 ? max_box : max_row;
   switch (a.d) {

@@ -1049,8 +1049,8 @@ hipError_t launch_sb_d(const SweepArgs& a, int pass, int64_t max_box, int32_t ma
   return hipGetLastError();
 }
 
-// With a disturbance player (a.nw > 1): the generic-dimension kernels that
-// value each item by its worst disturbance row.  Every item's box (the union
+// With a disturbance player (a.nw > 1): the kernels that value each item by
+// its worst disturbance row (instantiated for dimensions 2, 3 and any other).  Every item's box (the union
 // of its rows' windows) must fit the capacity: the caller passes the largest
 // state box, at most 512 cells.
 template <int D>
@@ -1099,6 +1099,10 @@ IMPACT_SB_DECLARE(5)
 IMPACT_SB_DECLARE(0)
 #undef IMPACT_SB_DECLARE
 extern template hipError_t launch_sb_dist<0>(const SweepArgs&, int, int64_t, int32_t,
+                                             hipStream_t);
+extern template hipError_t launch_sb_dist<2>(const SweepArgs&, int, int64_t, int32_t,
+                                             hipStream_t);
+extern template hipError_t launch_sb_dist<3>(const SweepArgs&, int, int64_t, int32_t,
                                              hipStream_t);
 
 }  // namespace impact

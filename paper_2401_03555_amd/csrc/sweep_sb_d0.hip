@@ -1,5 +1,5 @@
 // sweep_sb_d0.hip -- state-box sweep kernels for grid dimensions other than 2, 3 and 5,
-// and the kernels with a disturbance player (any dimension).
+// with and without a disturbance player (for the latter: any dimension but 2 and 3).
 #include "sweep_sb.hpp"
 
 namespace impact {
