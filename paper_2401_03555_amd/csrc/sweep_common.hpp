@@ -231,11 +231,41 @@ __device__ __forceinline__ void intra_stages(uint64_t (&key)[E], V (&val)[E], in
   }
 }
 
+// Lane exchange at a compile-time xor distance M (< 64).
+template <int M>
+__device__ __forceinline__ uint64_t xor_lane_c(uint64_t x) {
+  if constexpr (M == 1) return dpp_u64<kDppXor1>(x);
+  else if constexpr (M == 2) return dpp_u64<kDppXor2>(x);
+  else if constexpr (M == 4 || M == 8 || M == 16) return swz_u64<swz_xor(M)>(x);
+  else return (uint64_t)__shfl_xor((long long)x, M);
+}
+
+// One merge stage across lanes at xor distance M: each key meets the key of
+// the same slot on lane tid ^ M; selects, not branches.
+template <int E, class V, int M>
+__device__ __forceinline__ void lane_stage(uint64_t (&key)[E], V (&val)[E], int tid, int k) {
+  const bool lower = (tid & M) == 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const bool asc = ((tid * E + e) & k) == 0;
+    const uint64_t pk = xor_lane_c<M>(key[e]);
+    const V pv = from_bits<V>(xor_lane_c<M>(to_bits(val[e])));
+    const bool take = (asc == lower) ? !(key[e] < pk) : !(key[e] > pk);
+    key[e] = take ? pk : key[e];
+    val[e] = take ? pv : val[e];
+  }
+}
+
 // Bitonic sort of P = 64 * NW * E keys, thread t holding positions
 // [t*E, t*E + E) ("blocked" layout), ascending by key; val travels along.
+// Stages between lanes of one wavefront pick their exchange primitive once
+// per stage (the distance is uniform); stages between wavefronts go through
+// xk (at least P words) in element-major order, xk[e * 64 * NW + t], so that
+// a wavefront's accesses fall on consecutive words.
 template <int E, int NW, class V, bool UNROLL = true>
 __device__ void bitonic_sort(uint64_t (&key)[E], V (&val)[E], int tid, uint64_t* xk) {
   constexpr int P = 64 * NW * E;
+  constexpr int T = 64 * NW;
   // fully unrolled (compile-time partner distances) up to 4 keys per thread;
   // larger networks, and every network of a kernel that also holds the large
   // ones (UNROLL false), keep their loops, which holds the register footprint
@@ -245,39 +275,35 @@ __device__ void bitonic_sort(uint64_t (&key)[E], V (&val)[E], int tid, uint64_t*
 #pragma unroll kUnroll
     for (int j = k >> 1; j >= E; j >>= 1) {
       const int tm = j / E;  // partner thread = tid ^ tm
-      const bool lower = (tid & tm) == 0;
       if (tm < 64) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const bool asc = ((tid * E + e) & k) == 0;
-          const uint64_t pk = xor_lane_u64(key[e], tm);
-          const V pv = xor_lane<V>(val[e], tm);
-          const bool take = (asc == lower) ? !(key[e] < pk) : !(key[e] > pk);
-          if (take) {
-            key[e] = pk;
-            val[e] = pv;
-          }
+        switch (tm) {
+          case 1: lane_stage<E, V, 1>(key, val, tid, k); break;
+          case 2: lane_stage<E, V, 2>(key, val, tid, k); break;
+          case 4: lane_stage<E, V, 4>(key, val, tid, k); break;
+          case 8: lane_stage<E, V, 8>(key, val, tid, k); break;
+          case 16: lane_stage<E, V, 16>(key, val, tid, k); break;
+          default: lane_stage<E, V, 32>(key, val, tid, k); break;
         }
       } else {
+        const bool lower = (tid & tm) == 0;
+        const int pt = tid ^ tm;
         uint64_t pk[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) xk[tid * E + e] = key[e];
+        for (int e = 0; e < E; ++e) xk[e * T + tid] = key[e];
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < E; ++e) pk[e] = xk[(tid ^ tm) * E + e];
+        for (int e = 0; e < E; ++e) pk[e] = xk[e * T + pt];
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < E; ++e) xk[tid * E + e] = to_bits(val[e]);
+        for (int e = 0; e < E; ++e) xk[e * T + tid] = to_bits(val[e]);
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           const bool asc = ((tid * E + e) & k) == 0;
           const bool take = (asc == lower) ? !(key[e] < pk[e]) : !(key[e] > pk[e]);
-          const V pv = from_bits<V>(xk[(tid ^ tm) * E + e]);
-          if (take) {
-            key[e] = pk[e];
-            val[e] = pv;
-          }
+          const V pv = from_bits<V>(xk[e * T + pt]);
+          key[e] = take ? pk[e] : key[e];
+          val[e] = take ? pv : val[e];
         }
         __syncthreads();
       }
