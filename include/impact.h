@@ -47,7 +47,8 @@ extern "C" {
 #endif
 
 #define IMPACT_MAX_DIM 8
-#define IMPACT_MAX_ROW 4096 /* longest supported row (entries incl. OUT/TAIL) */
+#define IMPACT_MAX_ROW 16384 /* longest supported row (entries incl. OUT/TAIL); the
+                                multi-query engine takes rows of up to 4096 */
 
 /* Status codes.  > 0: success with a flag; < 0: failure. */
 enum {

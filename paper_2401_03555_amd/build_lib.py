@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libimpact.so")
 SOURCES = ["sweep_sb_d3.hip", "sweep_sb_d2.hip", "sweep_sb_d5.hip", "sweep_sb_d0.hip",
-           "sweep.hip", "abi.hip", "build.hip", "sweep_sb.hip", "mq.hip", "probe.hip"]
+           "sweep.hip", "sweep_sel.hip", "abi.hip", "build.hip", "sweep_sb.hip", "mq.hip", "probe.hip"]
 
 
 def hipcc() -> str:
@@ -24,8 +24,19 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build the library)")
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    """Compile every source to an object (in parallel), then link the library."""
+def _stale(src: str, obj: str, headers) -> bool:
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(f) > t for f in (src, *headers))
+
+
+def build(verbose: bool = False, extra=(), incremental: bool = False) -> str:
+    """Compile every source to an object (in parallel), then link the library.
+
+    incremental: recompile only sources whose object is older than the source
+    or any header of the library (a development convenience; the default
+    rebuilds everything)."""
     flags = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", "-Wno-unused-parameter",
@@ -34,8 +45,14 @@ def build(verbose: bool = False, extra=()) -> str:
     os.makedirs(objdir, exist_ok=True)
     objs = [os.path.join(objdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
 
+    headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    headers.append(os.path.join(ROOT, "include", "impact.h"))
+
     def compile_one(k):
-        cmd = [hipcc(), *flags, "-c", os.path.join(CSRC, SOURCES[k]), "-o", objs[k]]
+        src = os.path.join(CSRC, SOURCES[k])
+        if incremental and not _stale(src, objs[k], headers):
+            return subprocess.CompletedProcess([], 0, "", "")
+        cmd = [hipcc(), *flags, "-c", src, "-o", objs[k]]
         if verbose:
             print(" ".join(cmd), flush=True)
         return subprocess.run(cmd, capture_output=True, text=True)
@@ -56,4 +73,5 @@ def build(verbose: bool = False, extra=()) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True, extra=[a for a in sys.argv[1:] if a != "-v"])
+    build(verbose=True, extra=[a for a in sys.argv[1:] if a not in ("-v", "-i")],
+          incremental="-i" in sys.argv)

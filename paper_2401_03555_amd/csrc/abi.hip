@@ -630,6 +630,16 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
     int32_t* pi = tmp.get<int32_t>(N);
     Ctrl* ctrl = tmp.get<Ctrl>(1);
     double* gap_part = tmp.get<double>(std::max<int64_t>(1, N));
+    // rows longer than a wavefront's sort: selection sweep, which needs the
+    // value vector sorted per sweep and keeps a per-row hint
+    const bool sel = h->max_row > 512;
+    double* vs_buf[2] = {nullptr, nullptr};
+    int32_t* hint = nullptr;
+    if (sel) {
+      vs_buf[0] = tmp.get<double>(2 * N);
+      vs_buf[1] = tmp.get<double>(2 * N);
+      hint = tmp.get<int32_t>(2 * h->n_rows);
+    }
     h->store->hip_used = true;
 
     if (spec->n_target > 0)
@@ -698,6 +708,10 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       a.storage = h->storage;
       a.out_val = safety ? 1.0 : 0.0;
       a.inputs_per_state = (pass == 0 ? h->nu : 1) * h->nw;  // rows swept per state
+      a.n_cells = N;
+      a.hint = hint;
+      double* vsorted = sel ? vs_buf[value_sort_passes(N) & 1] : nullptr;
+      a.vsort = vsorted;
       int G = 1;
       if (h->max_row <= 512) G = std::max(1, 4 / a.inputs_per_state);
       while (G > 1 && G * a.inputs_per_state > 256) --G;
@@ -706,7 +720,9 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
       // the fixed-input pass sorting per row runs several rows per wavefront
       if (pass == 1 && !use_box && h->nw == 1 && rows_g_states_per_block(h->max_row) > 0)
         G = rows_g_states_per_block(h->max_row);
+      if (sel) G = 1;  // one workgroup per state
       a.states_per_block = G;
+      if (sel) HIP_TRY(hipMemsetAsync(hint, 0xff, sizeof(int32_t) * 2 * h->n_rows, h->st));
 
       HIP_TRY(launch_init_values(cls, N, safety, vb[0], vb[1], pass == 0 ? pi : nullptr, h->st));
       // finite horizon: the device stop test never fires (gap >= 0 > -1) and
@@ -738,6 +754,10 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
             const int64_t idx = launched + k;
             a.vin = vb[idx & 1];
             a.vout = vb[(idx + 1) & 1];
+            // the sort is outside the timed pair: the events bracket the sweep kernel
+            if (sel)
+              HIP_TRY(launch_value_sort(ctrl, a.vin, N, a.maximise ? -1.0 : 1.0, vs_buf[0],
+                                        vs_buf[1], h->st));
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (h->timing) {
               e0 = new_event();
@@ -746,6 +766,8 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
             }
             if (use_box)
               HIP_TRY(launch_sweep_sb(a, h->max_box, h->max_row, h->st));
+            else if (sel)
+              HIP_TRY(launch_sweep_sel(a, h->max_row, h->st));
             else
               HIP_TRY(launch_sweep(a, h->max_row, h->st));
             if (h->timing) {

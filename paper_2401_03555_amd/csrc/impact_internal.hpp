@@ -37,6 +37,11 @@ struct SweepArgs {
   int32_t nw;              // disturbances per (state, input), 0 or 1: none;
                            // rows of (s, u) are (s * nu + u) * nw + w
   double out_val;          // objective value of OUT
+  // selection sweep (rows longer than 512 entries)
+  const double* vsort;     // both components of vin, negated for a maximising LP, sorted
+                           // ascending: [V0 | V1], n_cells each
+  int32_t* hint;           // per (row, vector): a cell that held the critical value, or -1
+  int64_t n_cells;         // cells of the grid (length of vin)
 };
 
 // One interval-iteration query of the multi-query engine (device table).
@@ -117,6 +122,15 @@ hipError_t launch_sweep(const SweepArgs& a, int32_t max_row, hipStream_t st);
 hipError_t launch_sweep_sb(const SweepArgs& a, int64_t max_box, int32_t max_row, hipStream_t st);
 hipError_t launch_state_box_max(const BuildTable& T, int64_t n_states, const int32_t* win,
                                 unsigned long long* out, hipStream_t st);
+// Selection sweep for long rows: the value vector sorted per sweep
+// (launch_value_sort writes both components of vin times sg, sorted
+// ascending, to buf0 after an even and to buf1 after an odd number of merge
+// passes; sg = -1 for a maximising LP), then one workgroup per SAFE state
+// (rows of up to kMaxRow entries).
+int value_sort_passes(int64_t n);
+hipError_t launch_value_sort(const Ctrl* c, const double2* vin, int64_t n, double sg,
+                             double* buf0, double* buf1, hipStream_t st);
+hipError_t launch_sweep_sel(const SweepArgs& a, int32_t max_row, hipStream_t st);
 hipError_t launch_finish(Ctrl* c, const double* part, int64_t n_part, hipStream_t st);
 // part[0, n_part) = per-workgroup max(|V0' - V0|, |V1' - V1|) over the SAFE
 // states of one sweep from vin to vout (n_part workgroups of 256 threads;

@@ -421,6 +421,9 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
       if (!(spec->avoid_boxes[b * 2 * d + i] <= spec->avoid_boxes[b * 2 * d + d + i]))
         return mq_fail(IMPACT_E_INVAL, "avoid box with lo > hi");
   if (v.nu > 256) return mq_fail(IMPACT_E_UNSUPPORTED, "more than 256 inputs per state");
+  if (v.max_row > kMaxRowBlock)
+    return mq_fail(IMPACT_E_UNSUPPORTED, "rows longer than " + std::to_string(kMaxRowBlock) +
+                                             " entries run through impact_interval_iterate");
   // a free slot
   int32_t k = -1;
   for (int32_t i = 0; i < m->cap; ++i)

@@ -362,7 +362,7 @@ hipError_t launch_mq_sweep_block(const QueryDesc* desc, const QueryCtrl* ctrl, c
     MB(8, 4);
   else if (max_row <= 2048)
     MB(8, 8);
-  else if (max_row <= kMaxRow)
+  else if (max_row <= kMaxRowBlock)
     MB(8, 16);
   else
     return hipErrorInvalidValue;
@@ -558,14 +558,8 @@ static hipError_t launch_sweep_pass_d(const SweepArgs& a, int32_t max_row, hipSt
     hipLaunchKernelGGL((k_sweep<4, 0, PASS, D>), g, b, 0, st, a);
   else if (max_row <= 512)
     hipLaunchKernelGGL((k_sweep<8, 0, PASS, D>), g, b, 0, st, a);
-  else if (max_row <= 1024)
-    hipLaunchKernelGGL((k_sweep<8, 4, PASS, D>), g, b, 0, st, a);
-  else if (max_row <= 2048)
-    hipLaunchKernelGGL((k_sweep<8, 8, PASS, D>), g, b, 0, st, a);
-  else if (max_row <= kMaxRow)
-    hipLaunchKernelGGL((k_sweep<8, 16, PASS, D>), g, b, 0, st, a);
   else
-    return hipErrorInvalidValue;
+    return hipErrorInvalidValue;  // longer rows: the selection sweep
   return hipGetLastError();
 }
 

@@ -25,6 +25,10 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t x) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+__device__ __forceinline__ double uniform_f64(double x) {
+  return __longlong_as_double(uniform_i64(__double_as_longlong(x)));
+}
+
 __device__ __forceinline__ uint64_t to_bits(double x) { return dbits(x); }
 __device__ __forceinline__ uint64_t to_bits(int32_t x) { return (uint64_t)(uint32_t)x; }
 template <class V>

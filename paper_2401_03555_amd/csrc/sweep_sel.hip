@@ -1,0 +1,566 @@
+// sweep_sel.hip -- interval-iteration sweep for long rows (more than 512
+// entries) by selection of the critical value instead of a sort per row.
+//
+// The sorting method of Section 6.2 hands the free mass r = 1 - sum(lo) to the
+// entries of a row in value order (ascending for a minimising LP, descending
+// for a maximising one), each up to its width hi - lo, until r runs out.  All
+// entries before the one where r runs out receive their full width and all
+// entries after it nothing, so the LP value (eq. (5.1)) needs only that
+// critical value v*.  For a minimising LP, with F(x) the summed width of the
+// entries of value <= x and F<(x) that of the entries of value < x:
+//   v* = the smallest entry value with F(v*) > r,
+//   q  = sum(lo v) + sum_{v < v*} (hi - lo) v + (r - F<(v*)) v*;
+// entries tied at v* share the remainder and the value does not depend on how
+// (a maximising LP is the same on negated values).  Every entry value is a
+// value of the value vector, so v* is found by bisection over the value vector
+// sorted once per sweep (k_vsort_*, of the signed values): about log2(cells) rounds of one compare
+// and one masked add per entry.  The first round checks the critical cell of
+// the same row in the previous sweep, which most sweeps keep; a hit ends the
+// search at once.  The result does not depend on the search path.
+//
+// OUT and TAIL have the values 0 or 1, the two ends of every order, and are
+// handed their share before or after the window cells in closed form.
+//
+// One workgroup (NW wavefronts) per SAFE state; the state's rows (all inputs
+// in the policy pass, the policy's input in the fixed-input pass) are solved
+// one after another, each by the whole workgroup with E window cells per
+// thread held in registers (width and both values), cell slot e * 64NW + tid.
+#include "sweep_common.hpp"
+
+namespace impact {
+
+constexpr int kSortChunk = 2048;  // keys per workgroup of the chunk sort
+
+// Chunk sort of both components of the value vector, times sg (+1, or -1
+// for a maximising LP): out[vec * n + i] holds sg * component vec of vin,
+// ascending within each chunk of kSortChunk.
+__global__ __launch_bounds__(256) void k_vsort_chunk(const Ctrl* __restrict__ c,
+                                                     const double2* __restrict__ vin, int64_t n,
+                                                     double sg, double* __restrict__ out) {
+  if (c && c->done) return;
+  __shared__ double s[kSortChunk];
+  const int vec = blockIdx.y;
+  const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+  for (int i = threadIdx.x; i < kSortChunk; i += 256) {
+    const int64_t g = base + i;
+    double v = __builtin_inf();
+    if (g < n) {
+      const double2 x = vin[g];
+      v = sg * (vec ? x.y : x.x) + 0.0;
+    }
+    s[i] = v;
+  }
+  __syncthreads();
+  for (int k = 2; k <= kSortChunk; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < kSortChunk / 2; i += 256) {
+        const int lo = 2 * i - (i & (j - 1)), hi = lo + j;
+        const bool asc = (lo & k) == 0;
+        const double x = s[lo], y = s[hi];
+        if ((x > y) == asc) {
+          s[lo] = y;
+          s[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < kSortChunk; i += 256) {
+    const int64_t g = base + i;
+    if (g < n) out[vec * n + g] = s[i];
+  }
+}
+
+// One merge pass: sorted runs of length L (pairs [2pL, 2pL + L), [2pL + L,
+// 2pL + 2L)) into runs of 2L.  Each key finds its place by a binary search in
+// the other run; ties keep the first run's keys first.
+__global__ __launch_bounds__(256) void k_vsort_merge(const Ctrl* __restrict__ c,
+                                                     const double* __restrict__ in, int64_t n,
+                                                     int64_t L, double* __restrict__ out) {
+  if (c && c->done) return;
+  const int vec = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double* src = in + vec * n;
+  const int64_t start = (i / (2 * L)) * (2 * L);
+  const int64_t mid = start + L < n ? start + L : n;
+  const int64_t end = start + 2 * L < n ? start + 2 * L : n;
+  const double key = src[i];
+  int64_t pos;
+  if (i < mid) {
+    int64_t lo = mid, hi = end;  // keys of the second run below key
+    while (lo < hi) {
+      const int64_t m = (lo + hi) >> 1;
+      if (src[m] < key)
+        lo = m + 1;
+      else
+        hi = m;
+    }
+    pos = i + (lo - mid);
+  } else {
+    int64_t lo = start, hi = mid;  // keys of the first run not above key
+    while (lo < hi) {
+      const int64_t m = (lo + hi) >> 1;
+      if (src[m] <= key)
+        lo = m + 1;
+      else
+        hi = m;
+    }
+    pos = (i - mid) + lo;
+  }
+  out[vec * n + pos] = key;
+}
+
+int value_sort_passes(int64_t n) {
+  int p = 0;
+  for (int64_t L = kSortChunk; L < n; L <<= 1) ++p;
+  return p;
+}
+
+hipError_t launch_value_sort(const Ctrl* c, const double2* vin, int64_t n, double sg,
+                             double* buf0, double* buf1, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const unsigned chunks = (unsigned)((n + kSortChunk - 1) / kSortChunk);
+  hipLaunchKernelGGL(k_vsort_chunk, dim3(chunks, 2), dim3(256), 0, st, c, vin, n, sg, buf0);
+  double* src = buf0;
+  double* dst = buf1;
+  for (int64_t L = kSortChunk; L < n; L <<= 1) {
+    hipLaunchKernelGGL(k_vsort_merge, dim3((unsigned)((n + 255) / 256), 2), dim3(256), 0, st, c,
+                       src, n, L, dst);
+    double* t = src;
+    src = dst;
+    dst = t;
+  }
+  return hipGetLastError();
+}
+
+template <int NW>
+struct SelLds {
+  double red[2][NW][6];        // block sums, double-buffered
+  double2 fac[kMaxFactors];    // the row's factors (FACTORS storage)
+  double qb0[kMaxItems], qb1[kMaxItems];
+  int32_t hit[2];              // a cell holding the critical value, per vector
+};
+
+// Sums over the workgroup of K per-thread values, the same on every thread
+// (wavefront butterflies, then the wavefronts' partials in a fixed order).
+template <int NW, int K>
+__device__ __forceinline__ void block_sums(double (&x)[K], SelLds<NW>& L, int tid, int& par) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] = wave_sum(x[k]);
+  if (NW == 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] = uniform_f64(x[k]);
+    return;
+  }
+  const int lane = tid & 63, wv = tid >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) L.red[par][wv][k] = x[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += L.red[par][w][k];
+    x[k] = uniform_f64(s);
+  }
+  par ^= 1;
+}
+
+// Critical values of both vectors of one row (signed values x0, x1 and widths
+// w of the first EC slots of every thread; later slots hold width 0): tc[v] =
+// the smallest value with F(tc) > r1, fl[v] = F<(tc), ql[v] = the summed
+// width * value of the entries below tc.  Starts from the row's hint cells
+// (the previous sweep's critical cells), else bisects over the sorted value
+// vector, and then stores cells holding the critical values as new hints.
+template <int NW, int EC, int E, int D>
+__device__ void sel_search(const SweepArgs& a, int64_t row, int tid, SelLds<NW>& L, int& par,
+                           const double (&w)[E], const double (&x0)[E], const double (&x1)[E],
+                           double r1, double (&tc)[2], double (&fl)[2], double (&ql)[2]) {
+  constexpr int T = 64 * NW;
+  const bool mx = a.maximise != 0;
+  const double sg = mx ? -1.0 : 1.0;
+  const int64_t N = a.n_cells;
+  const double* sv0 = a.vsort;
+  const double* sv1 = a.vsort + N;
+  // k-th smallest signed value (the sort was of the signed values)
+  auto pivot = [&](const double* sv, int64_t k) -> double { return sv[k]; };
+  // one pass at pivots (ta, tb): F<, F<= and the width * value below, per vector
+  double s[6];
+  auto check = [&](double ta, double tb) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s[k] = 0.0;
+#pragma unroll
+    for (int e = 0; e < EC; ++e) {
+      const bool a_lt = x0[e] < ta, a_le = x0[e] <= ta;
+      const bool b_lt = x1[e] < tb, b_le = x1[e] <= tb;
+      s[0] += a_lt ? w[e] : 0.0;
+      s[1] += a_le ? w[e] : 0.0;
+      s[2] += a_lt ? w[e] * x0[e] : 0.0;
+      s[3] += b_lt ? w[e] : 0.0;
+      s[4] += b_le ? w[e] : 0.0;
+      s[5] += b_lt ? w[e] * x1[e] : 0.0;
+    }
+    block_sums<NW, 6>(s, L, tid, par);
+  };
+  int32_t* hint = a.hint + row * 2;
+  const int32_t h0 = hint[0], h1 = hint[1];
+  bool found0 = false, found1 = false;
+  if (h0 >= 0 && h1 >= 0) {
+    tc[0] = sg * a.vin[h0].x;
+    tc[1] = sg * a.vin[h1].y;
+    check(tc[0], tc[1]);
+    found0 = s[0] <= r1 && s[1] > r1;
+    found1 = s[3] <= r1 && s[4] > r1;
+    fl[0] = s[0];
+    ql[0] = s[2];
+    fl[1] = s[3];
+    ql[1] = s[5];
+  }
+  if (found0 && found1) return;
+
+  // bisection over the sorted values: the smallest k with F(<= sv[k]) > r1
+  // (it exists: the largest sorted value counts every entry).  The pivots of
+  // both possible next rounds are fetched before the current round's sums.
+  int64_t lo0 = 0, hi0 = found0 ? 0 : N - 1, lo1 = 0, hi1 = found1 ? 0 : N - 1;
+  int64_t m0 = (lo0 + hi0) >> 1, m1 = (lo1 + hi1) >> 1;
+  double pa = pivot(sv0, m0), pb = pivot(sv1, m1);
+  while (lo0 < hi0 || lo1 < hi1) {
+    const int64_t a0 = (lo0 + m0) >> 1, b0 = (m0 + 1 + hi0) >> 1;
+    const int64_t a1 = (lo1 + m1) >> 1, b1 = (m1 + 1 + hi1) >> 1;
+    const double pa_lo = pivot(sv0, a0), pa_hi = pivot(sv0, b0);
+    const double pb_lo = pivot(sv1, a1), pb_hi = pivot(sv1, b1);
+    double b[2] = {0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < EC; ++e) {
+      b[0] += x0[e] <= pa ? w[e] : 0.0;
+      b[1] += x1[e] <= pb ? w[e] : 0.0;
+    }
+    block_sums<NW, 2>(b, L, tid, par);
+    if (lo0 < hi0) {
+      if (b[0] > r1) {
+        hi0 = m0;
+        m0 = a0;
+        pa = pa_lo;
+      } else {
+        lo0 = m0 + 1;
+        m0 = b0;
+        pa = pa_hi;
+      }
+    }
+    if (lo1 < hi1) {
+      if (b[1] > r1) {
+        hi1 = m1;
+        m1 = a1;
+        pb = pb_lo;
+      } else {
+        lo1 = m1 + 1;
+        m1 = b1;
+        pb = pb_hi;
+      }
+    }
+  }
+  if (!found0) tc[0] = pivot(sv0, lo0);
+  if (!found1) tc[1] = pivot(sv1, lo1);
+  check(tc[0], tc[1]);
+  if (!found0) {
+    fl[0] = s[0];
+    ql[0] = s[2];
+  }
+  if (!found1) {
+    fl[1] = s[3];
+    ql[1] = s[5];
+  }
+
+  // a cell holding each critical value (with positive width), for the next sweep
+  const SysParams& p = *a.sys;
+  const int d = D > 0 ? D : a.d;
+  const int32_t* wr = a.win + row * 2 * d;
+  const int nw = (int)(a.row_off[row + 1] - a.row_off[row]);
+  if (tid == 0) {
+    L.hit[0] = -1;
+    L.hit[1] = -1;
+  }
+  __syncthreads();
+  {
+    int W[kMaxDim], j[kMaxDim];
+    int32_t tt = 0;
+    int rem = tid;
+    IMPACT_FOR_DIMS_REV(i, d) {
+      W[i] = wr[d + i];
+      const int Wi = W[i] > 0 ? W[i] : 1;
+      j[i] = rem % Wi;
+      rem /= Wi;
+    }
+    IMPACT_FOR_DIMS(i, d) tt += (wr[i] + j[i]) * (int32_t)p.stride[i];
+    int dT[kMaxDim];
+    int32_t dt = 0, corr[kMaxDim];
+    {
+      int remT = T;
+      IMPACT_FOR_DIMS_REV(i, d) {
+        const int Wi = W[i] > 0 ? W[i] : 1;
+        dT[i] = remT % Wi;
+        remT /= Wi;
+      }
+      IMPACT_FOR_DIMS(i, d) {
+        const int32_t st = (int32_t)p.stride[i];
+        dt += dT[i] * st;
+        corr[i] = (i > 0 ? (int32_t)p.stride[i - 1] : 0) - W[i] * st;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EC; ++e) {
+      if (e * T + tid < nw && w[e] > 0.0) {
+        if (!found0 && x0[e] == tc[0]) L.hit[0] = tt;
+        if (!found1 && x1[e] == tc[1]) L.hit[1] = tt;
+      }
+      int cy = 0;
+      tt += dt;
+      IMPACT_FOR_DIMS_REV(i, d) {
+        const int ji = j[i] + dT[i] + cy;
+        cy = ji >= W[i];
+        j[i] = cy ? ji - W[i] : ji;
+        tt += cy ? corr[i] : 0;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (!found0) hint[0] = L.hit[0];
+    if (!found1) hint[1] = L.hit[1];
+  }
+}
+
+// Both LP values (V0 and V1) of one row.  Values are held signed (negated for
+// a maximising LP) so that both directions search for the smallest critical
+// value in ascending order.
+template <int NW, int E, int D>
+__device__ void sel_row(const SweepArgs& a, int64_t row, int tid, SelLds<NW>& L, int& par,
+                        double& q0, double& q1) {
+  constexpr int T = 64 * NW;
+  const SysParams& p = *a.sys;
+  const int d = D > 0 ? D : a.d;
+  const int64_t base = a.row_off[row];
+  const int nw = (int)(a.row_off[row + 1] - base);
+  const int32_t* wr = a.win + row * 2 * d;
+  const bool mx = a.maximise != 0;
+  const double sg = mx ? -1.0 : 1.0;
+  const bool factors = a.storage == IMPACT_STORE_FACTORS;
+
+  int W[kMaxDim], fo[kMaxDim], j[kMaxDim], dT[kMaxDim];
+  int32_t corr[kMaxDim];
+  int32_t t = 0, dt = 0;
+  {
+    int rem = tid, remT = T, tot = 0;
+    IMPACT_FOR_DIMS_REV(i, d) {
+      W[i] = wr[d + i];
+      const int Wi = W[i] > 0 ? W[i] : 1;
+      j[i] = rem % Wi;
+      rem /= Wi;
+      dT[i] = remT % Wi;
+      remT /= Wi;
+    }
+    IMPACT_FOR_DIMS(i, d) {
+      const int32_t st = (int32_t)p.stride[i];
+      t += (wr[i] + j[i]) * st;
+      dt += dT[i] * st;
+      corr[i] = (i > 0 ? (int32_t)p.stride[i - 1] : 0) - W[i] * st;
+      fo[i] = tot;
+      tot += W[i];
+    }
+    if (factors) {
+      __syncthreads();  // the previous row's readers are done with L.fac
+      const double2* fr = a.fac + row * (int64_t)a.fs;
+      for (int k = tid; k < tot; k += T) L.fac[k] = fr[k];
+      __syncthreads();
+    }
+  }
+
+  // load the window cells: width and both values per slot
+  double w[E], x0[E], x1[E];
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // sum lo, sum w, lo v0, lo v1, w v0, w v1
+  const int Erow = (nw + T - 1) / T;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    w[e] = 0.0;
+    x0[e] = 0.0;
+    x1[e] = 0.0;
+    if (e < Erow) {
+      const int slot = e * T + tid;
+      if (slot < nw) {
+        double lo, hi;
+        if (factors) {
+          lo = 1.0;
+          hi = 1.0;
+          IMPACT_FOR_DIMS(i, d) {
+            const double2 f = L.fac[fo[i] + j[i]];
+            lo *= f.x;
+            hi *= f.y;
+          }
+        } else {
+          const double2 b = a.ent[base + slot];
+          lo = b.x;
+          hi = b.y;
+        }
+        const double2 V = a.vin[t];
+        w[e] = hi - lo;
+        x0[e] = sg * V.x;
+        x1[e] = sg * V.y;
+        acc[0] += lo;
+        acc[1] += w[e];
+        acc[2] += lo * V.x;
+        acc[3] += lo * V.y;
+        acc[4] += w[e] * V.x;
+        acc[5] += w[e] * V.y;
+      }
+      // next slot of this thread: add the digits of T, last dimension fastest
+      int cy = 0;
+      t += dt;
+      IMPACT_FOR_DIMS_REV(i, d) {
+        const int ji = j[i] + dT[i] + cy;
+        cy = ji >= W[i];
+        j[i] = cy ? ji - W[i] : ji;
+        t += cy ? corr[i] : 0;
+      }
+    }
+  }
+  block_sums<NW, 6>(acc, L, tid, par);
+
+  // OUT and TAIL: value out_val and the end value of the order
+  const double4 o = a.ot[row];
+  const double v_first = mx ? 1.0 : 0.0;  // the value visited first
+  const double tail_w = a.windowed ? o.w - o.z : 0.0;
+  const double tail_lo = a.windowed ? o.z : 0.0;
+  double r = 1.0 - ((acc[0] + o.x) + tail_lo);
+  if (r < 0.0) r = 0.0;
+  // handed out before the cells: TAIL (value v_first) and OUT if it has
+  // that value; OUT otherwise after them
+  const bool out_first = a.out_val == v_first;
+  double r1 = r, qf = 0.0;
+  {
+    double dl = tail_w < r1 ? tail_w : r1;
+    r1 -= dl;
+    qf += dl * v_first;
+    if (out_first) {
+      const double ow = o.y - o.x;
+      dl = ow < r1 ? ow : r1;
+      r1 -= dl;
+      qf += dl * a.out_val;
+    }
+  }
+  const double base0 = acc[2] + o.x * a.out_val + tail_lo * v_first + qf;
+  const double base1 = acc[3] + o.x * a.out_val + tail_lo * v_first + qf;
+  const double sw = acc[1];
+  if (!(sw > r1)) {
+    // every cell gets its full width; what is left goes to OUT if it comes last
+    double ql = 0.0;
+    if (!out_first) {
+      const double r2 = r1 - sw, ow = o.y - o.x;
+      ql = (ow < r2 ? ow : r2) * a.out_val;
+    }
+    q0 = base0 + acc[4] + ql;
+    q1 = base1 + acc[5] + ql;
+    return;
+  }
+
+  // search for the critical values of both vectors over the first EC slots of
+  // every thread (slots past the row's cells have width 0 and count nothing)
+  double tc[2], fl[2], ql[2];
+  if (E <= 4 || Erow <= 4)
+    sel_search<NW, (E < 4 ? E : 4), E, D>(a, row, tid, L, par, w, x0, x1, r1, tc, fl, ql);
+  else if (E <= 8 || Erow <= 8)
+    sel_search<NW, (E < 8 ? E : 8), E, D>(a, row, tid, L, par, w, x0, x1, r1, tc, fl, ql);
+  else if (E <= 12 || Erow <= 12)
+    sel_search<NW, (E < 12 ? E : 12), E, D>(a, row, tid, L, par, w, x0, x1, r1, tc, fl, ql);
+  else
+    sel_search<NW, E, E, D>(a, row, tid, L, par, w, x0, x1, r1, tc, fl, ql);
+  q0 = base0 + sg * (ql[0] + (r1 - fl[0]) * tc[0]);
+  q1 = base1 + sg * (ql[1] + (r1 - fl[1]) * tc[1]);
+}
+
+// PASS 0: all inputs (policy pass); PASS 1: the input fixed by the policy.
+// With a disturbance player (nw > 1) every (state, input) has nw rows and is
+// valued by its worst one (eq. (5.1)).
+template <int NW, int E, int PASS, int D>
+__global__ __launch_bounds__(64 * NW) void k_sweep_sel(SweepArgs a) {
+  if (a.ctrl->done) return;
+  __shared__ SelLds<NW> L;
+  const int tid = threadIdx.x;
+  const int64_t si = blockIdx.x;
+  const int64_t s = a.safe[si];
+  const int U = PASS == 0 ? a.nu : 1;
+  const int NWD = a.nw > 1 ? a.nw : 1;
+  int par = 0;
+  for (int m = 0; m < U * NWD; ++m) {
+    const int ui = m / NWD, wi = m - ui * NWD;
+    const int u = PASS == 0 ? ui : a.pi[s];
+    double q0, q1;
+    sel_row<NW, E, D>(a, (s * a.nu + u) * NWD + wi, tid, L, par, q0, q1);
+    if (tid == 0) {
+      L.qb0[m] = q0;
+      L.qb1[m] = q1;
+    }
+  }
+  if (tid == 0) {
+    // an input is worth its worst row over the disturbances: the minimum for
+    // reach, the maximum of the bad mass for safety
+    auto worst = [&](const double* q, int ui) {
+      double v = q[ui * NWD];
+      for (int w = 1; w < NWD; ++w) {
+        const double x = q[ui * NWD + w];
+        v = a.reach ? fmin(v, x) : fmax(v, x);
+      }
+      return v;
+    };
+    double b0 = worst(L.qb0, 0), b1 = worst(L.qb1, 0);
+    int arg = 0;
+    for (int ui = 1; ui < U; ++ui) {
+      const double q0 = worst(L.qb0, ui), q1 = worst(L.qb1, ui);
+      if (a.reach ? (q0 > b0) : (q0 < b0)) {
+        b0 = q0;
+        arg = ui;
+      }
+      if (a.reach ? (q1 > b1) : (q1 < b1)) b1 = q1;
+    }
+    a.vout[s] = make_double2(b0, b1);
+    if (PASS == 0) a.pi[s] = arg;
+    const double g = b1 - b0;
+    a.gap_part[si] = g > 0.0 ? g : 0.0;
+  }
+}
+
+template <int PASS, int D>
+static hipError_t launch_sel_pd(const SweepArgs& a, int32_t max_row, hipStream_t st) {
+  const dim3 g((unsigned)a.n_safe);
+  const int cells = max_row;  // upper bound on window cells per row
+  if (cells <= 256 * 8)
+    hipLaunchKernelGGL((k_sweep_sel<4, 8, PASS, D>), g, dim3(256), 0, st, a);
+  else if (cells <= 256 * 16)
+    hipLaunchKernelGGL((k_sweep_sel<4, 16, PASS, D>), g, dim3(256), 0, st, a);
+  else if (cells <= 512 * 16)
+    hipLaunchKernelGGL((k_sweep_sel<8, 16, PASS, D>), g, dim3(512), 0, st, a);
+  else if (cells <= 1024 * 16)
+    hipLaunchKernelGGL((k_sweep_sel<16, 16, PASS, D>), g, dim3(1024), 0, st, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <int PASS>
+static hipError_t launch_sel_p(const SweepArgs& a, int32_t max_row, hipStream_t st) {
+  switch (a.d) {
+    case 5: return launch_sel_pd<PASS, 5>(a, max_row, st);
+    default: return launch_sel_pd<PASS, 0>(a, max_row, st);
+  }
+}
+
+hipError_t launch_sweep_sel(const SweepArgs& a, int32_t max_row, hipStream_t st) {
+  if (a.n_safe == 0) return hipSuccess;
+  if ((int64_t)a.nu * (a.nw > 1 ? a.nw : 1) > kMaxItems || !a.vsort || !a.hint)
+    return hipErrorInvalidValue;
+  return a.pass == 0 ? launch_sel_p<0>(a, max_row, st) : launch_sel_p<1>(a, max_row, st);
+}
+
+}  // namespace impact

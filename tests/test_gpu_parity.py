@@ -321,24 +321,38 @@ def test_rows_leaving_the_domain_have_only_out_and_tail(I):
     assert r["status"] == 0 and bool((r["hi"].abs() < 1e-12).all())
 
 
-def test_longest_supported_row_and_rejection(I):
-    import paper_2401_03555_amd.impact as imp
-    ok = dict(kind="affine", A=np.eye(2) * 0.5, B=np.zeros((2, 1)), c=np.zeros(2),
-              lb=[-1.0, -1.0], ub=[1.0, 1.0], n=[63, 64], inputs=[[0.0]], sigma=[0.4, 0.4],
-              k_sigma=0.0)
-    g = gpu_build(I, ok)
-    assert g.info()["max_row"] == 63 * 64 + 1
-    spec = dict(kind="reach_avoid", target=[[[0.5, 0.5], [1.0, 1.0]]],
-                avoid=[[[-1.0, -1.0], [-0.5, -0.5]]], eps=1e-8, max_sweeps=2)
+def _dense_rows(n0, n1):
+    # dense rows of n0 * n1 cells + OUT (one input): every row is as long as the grid
+    return dict(kind="affine", A=np.eye(2) * 0.5, B=np.zeros((2, 1)), c=np.zeros(2),
+                lb=[-1.0, -1.0], ub=[1.0, 1.0], n=[n0, n1], inputs=[[0.0]], sigma=[0.4, 0.4],
+                k_sigma=0.0)
+
+
+DENSE_SPEC = dict(kind="reach_avoid", target=[[[0.5, 0.5], [1.0, 1.0]]],
+                  avoid=[[[-1.0, -1.0], [-0.5, -0.5]]], eps=1e-8)
+
+
+# row lengths of each long-row kernel class: 4,033 entries (4 wavefronts,
+# 16 cells per thread), 4,097 (8 wavefronts) and 8,282 (16 wavefronts)
+@pytest.mark.parametrize("n0,n1,K", [(63, 64, 3), (64, 64, 3), (91, 91, 2)])
+def test_long_dense_rows_match_oracle(I, n0, n1, K):
+    system = _dense_rows(n0, n1)
+    say(f"dense rows {n0}x{n1}: {n0 * n1 + 1} entries, {K} sweeps per pass")
+    g = gpu_build(I, system)
+    assert g.info()["max_row"] == n0 * n1 + 1
+    spec = dict(DENSE_SPEC, max_sweeps=K)
     rg = g.iterate(spec)
-    m = oracle.build(ok, 0.0)
-    cls = oracle.label(ok, spec["target"], spec["avoid"])
+    m = oracle.build(system, 0.0)
+    cls = oracle.label(system, spec["target"], spec["avoid"])
     ro = oracle.iterate(m["n_states"], 1, m["row_ptr"], m["target"], m["lo"], m["hi"], cls,
-                        "reach_avoid", 1e-8, 2)
-    compare_iter(rg, ro, cls, True, "4033-entry rows")
-    too_long = dict(ok, n=[64, 64])
+                        "reach_avoid", 1e-8, K)
+    compare_iter(rg, ro, cls, True, f"{n0 * n1 + 1}-entry rows")
+
+
+def test_rows_beyond_the_longest_supported_are_rejected(I):
+    import paper_2401_03555_amd.impact as imp
     with pytest.raises(imp.ImpactError) as ei:
-        gpu_build(I, too_long)
+        gpu_build(I, _dense_rows(128, 128))  # 16,385 entries
     assert ei.value.code == imp.E_UNSUPPORTED
 
 
