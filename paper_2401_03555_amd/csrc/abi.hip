@@ -45,6 +45,7 @@ struct NoMem {
 struct Storage {
   impact_device dev{};
   hipStream_t st = nullptr;
+  int device = 0;         // the device current when the build ran
   bool hip_used = false;  // set before the first HIP call
   std::vector<void*> owned;
   int64_t bytes = 0;
@@ -137,6 +138,20 @@ struct ScratchT {
   }
 };
 using Scratch = ScratchT<impact_imdp>;
+
+// HIP events of one call, destroyed on every exit path.
+struct EventPool {
+  std::vector<hipEvent_t> evs;
+  hipEvent_t make() {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    evs.push_back(e);
+    return e;
+  }
+  ~EventPool() {
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+  }
+};
 
 bool is_finite(double x) { return std::isfinite(x); }
 
@@ -271,6 +286,282 @@ int imdp_view(const impact_imdp* h, ImdpView* v) {
 }
 }  // namespace impact
 
+namespace {
+
+// Arguments of impact_interval_iterate.
+int validate_iterate(const impact_imdp* h, const impact_spec* spec, double eps, const double* lo,
+                     const double* hi, const int32_t* policy) {
+  if (!h || !spec) return fail(IMPACT_E_INVAL, "null argument");
+  if (!lo || !hi || !policy) return fail(IMPACT_E_INVAL, "lo/hi/policy must be device buffers");
+  if (spec->kind < IMPACT_SAFETY || spec->kind > IMPACT_REACH_AVOID)
+    return fail(IMPACT_E_INVAL, "unknown spec kind");
+  if (spec->n_target < 0 || spec->n_avoid < 0) return fail(IMPACT_E_INVAL, "negative box count");
+  if ((spec->n_target > 0 && !spec->target_boxes) || (spec->n_avoid > 0 && !spec->avoid_boxes))
+    return fail(IMPACT_E_INVAL, "box array is null");
+  if (spec->kind == IMPACT_SAFETY && spec->n_target != 0)
+    return fail(IMPACT_E_INVAL, "safety takes no target boxes");
+  if (spec->kind == IMPACT_REACH && spec->n_avoid != 0)
+    return fail(IMPACT_E_INVAL, "reachability takes no avoid boxes (use reach-avoid)");
+  if (spec->pessimistic != 0 && spec->pessimistic != 1)
+    return fail(IMPACT_E_INVAL, "pessimistic must be 0 or 1");
+  if (spec->max_sweeps < 1) return fail(IMPACT_E_INVAL, "max_sweeps must be >= 1");
+  if (spec->horizon < IMPACT_HORIZON_AUTO)
+    return fail(IMPACT_E_INVAL, "horizon must be >= 0 or IMPACT_HORIZON_AUTO");
+  if (!is_finite(eps) || !(eps > 0.0)) return fail(IMPACT_E_INVAL, "eps must be finite and > 0");
+  const int d = h->d;
+  for (int64_t k = 0; k < (int64_t)spec->n_target * 2 * d; ++k)
+    if (std::isnan(spec->target_boxes[k])) return fail(IMPACT_E_INVAL, "NaN in target box");
+  for (int64_t k = 0; k < (int64_t)spec->n_avoid * 2 * d; ++k)
+    if (std::isnan(spec->avoid_boxes[k])) return fail(IMPACT_E_INVAL, "NaN in avoid box");
+  for (int b = 0; b < spec->n_target; ++b)
+    for (int i = 0; i < d; ++i)
+      if (spec->target_boxes[b * 2 * d + i] > spec->target_boxes[b * 2 * d + d + i])
+        return fail(IMPACT_E_INVAL, "target box with lo > hi");
+  for (int b = 0; b < spec->n_avoid; ++b)
+    for (int i = 0; i < d; ++i)
+      if (spec->avoid_boxes[b * 2 * d + i] > spec->avoid_boxes[b * 2 * d + d + i])
+        return fail(IMPACT_E_INVAL, "avoid box with lo > hi");
+
+  return IMPACT_OK;
+}
+
+// Interval iteration with the call's temporaries from tmp.
+template <class Tmp>
+int iterate_body(impact_imdp* h, const impact_spec* spec, double eps, double* lo, double* hi,
+                 int32_t* policy, Tmp& tmp, bool timing) {
+  const int d = h->d;
+  const auto t_start = std::chrono::steady_clock::now();
+  const int64_t N = h->n_states;
+  const bool safety = spec->kind == IMPACT_SAFETY;
+  double* tb = tmp.template get<double>((int64_t)spec->n_target * 2 * d);
+  double* ab = tmp.template get<double>((int64_t)spec->n_avoid * 2 * d);
+  int8_t* cls = tmp.template get<int8_t>(N);
+  int64_t* flag = tmp.template get<int64_t>(N);
+  int64_t* pos = tmp.template get<int64_t>(N + 1);
+  const int64_t te = scan_tmp_elems(N);
+  int64_t* stmp = tmp.template get<int64_t>(te);
+  int32_t* safe = tmp.template get<int32_t>(N);
+  double2* vb[2] = {tmp.template get<double2>(N), tmp.template get<double2>(N)};
+  int32_t* pi = tmp.template get<int32_t>(N);
+  Ctrl* ctrl = tmp.template get<Ctrl>(1);
+  double* gap_part = tmp.template get<double>(std::max<int64_t>(1, N));
+  // rows longer than a wavefront's sort: selection sweep, which needs the
+  // value vector sorted per sweep and keeps a per-row hint
+  const bool sel = h->max_row > 512;
+  double* vs_buf[2] = {nullptr, nullptr};
+  int32_t* hint = nullptr;
+  if (sel) {
+    vs_buf[0] = tmp.template get<double>(2 * N);
+    vs_buf[1] = tmp.template get<double>(2 * N);
+    hint = tmp.template get<int32_t>(2 * h->n_rows);
+  }
+  h->store->hip_used = true;
+
+  if (spec->n_target > 0)
+    HIP_TRY(hipMemcpyAsync(tb, spec->target_boxes, sizeof(double) * spec->n_target * 2 * d,
+                           hipMemcpyHostToDevice, h->st));
+  if (spec->n_avoid > 0)
+    HIP_TRY(hipMemcpyAsync(ab, spec->avoid_boxes, sizeof(double) * spec->n_avoid * 2 * d,
+                           hipMemcpyHostToDevice, h->st));
+  HIP_TRY(launch_label(h->dp, N, tb, spec->n_target, ab, spec->n_avoid, cls, flag, h->st));
+  HIP_TRY(exclusive_scan_i64(flag, pos, N, stmp, te, h->st));
+  int64_t n_safe = 0;
+  HIP_TRY(hipMemcpyAsync(&n_safe, pos + N, sizeof(int64_t), hipMemcpyDeviceToHost, h->st));
+  HIP_TRY(hipStreamSynchronize(h->st));
+  HIP_TRY(launch_compact(cls, pos, N, safe, h->st));
+
+  impact_iter_info info{};
+  info.n_safe = n_safe;
+  EventPool events;
+  Ctrl hc{};
+  // Both passes under one stop rule: self_rule stops a pass once both its
+  // iterates stop moving (Remark 5.2); otherwise the gap rule, or exactly
+  // `horizon` sweeps when horizon > 0 (Remark 5.1).
+  auto run_passes = [&](bool self_rule, int64_t horizon) -> int {
+  for (int pass = 0; pass < 2; ++pass) {
+    // policy pass: one sort per state over its rows' window box when every
+    // row fits a wavefront; the fixed-input pass has one row per state and
+    // sorts per row unless the state-box mode is forced
+    const int32_t mode = h->sweep_mode[pass];
+    // (with a disturbance player the state box must hold a whole state's
+    // rows; the fixed-input pass then also sweeps by state box, so that an
+    // item's disturbance rows share one sort)
+    const bool use_box = h->max_row <= 512 &&
+                         (h->nw > 1 ? h->max_box <= 512 && mode != IMPACT_SWEEP_PER_ROW
+                                    : (mode == IMPACT_SWEEP_STATE_BOX ||
+                                       (mode == IMPACT_SWEEP_AUTO && pass == 0)));
+    SweepArgs a{};
+    a.row_off = h->row_off;
+    a.win = h->win;
+    a.ot = h->ot;
+    a.ent = h->ent;
+    a.fac = h->fac;
+    a.sys = h->dp;
+    a.pi = pi;
+    a.safe = safe;
+    a.ctrl = ctrl;
+    a.gap_part = gap_part;
+    a.n_safe = n_safe;
+    a.fs = h->fs;
+    a.pass = pass;
+    a.reach = !safety;
+    // the adversarial LP (reach: minimising; safety: maximising the bad
+    // mass) runs in the policy pass for the pessimistic policy and in the
+    // fixed-input pass for the optimistic one
+    const bool adverse = (pass == 0) == (spec->pessimistic != 0);
+    a.maximise = adverse ? safety : !safety;
+    a.nu = h->nu;
+    a.nw = h->nw;
+    a.d = d;
+    a.windowed = h->windowed;
+    a.storage = h->storage;
+    a.out_val = safety ? 1.0 : 0.0;
+    a.inputs_per_state = (pass == 0 ? h->nu : 1) * h->nw;  // rows swept per state
+    a.n_cells = N;
+    a.hint = hint;
+    double* vsorted = sel ? vs_buf[value_sort_passes(N) & 1] : nullptr;
+    a.vsort = vsorted;
+    int G = 1;
+    if (h->max_row <= 512) G = std::max(1, 4 / a.inputs_per_state);
+    while (G > 1 && G * a.inputs_per_state > 256) --G;
+    if (a.inputs_per_state > 256)
+      return fail(IMPACT_E_UNSUPPORTED, "more than 256 rows per state");
+    // the fixed-input pass sorting per row runs several rows per wavefront
+    if (pass == 1 && !use_box && h->nw == 1 && rows_g_states_per_block(h->max_row) > 0)
+      G = rows_g_states_per_block(h->max_row);
+    if (sel) G = 1;  // one workgroup per state
+    a.states_per_block = G;
+    if (sel) HIP_TRY(launch_fill_i32(hint, 2 * h->n_rows, -1, h->st));
+
+    HIP_TRY(launch_init_values(cls, N, safety, vb[0], vb[1], pass == 0 ? pi : nullptr, h->st));
+    // finite horizon: the device stop test never fires (gap >= 0 > -1) and
+    // the cap is the horizon
+    const bool finite = horizon > 0;
+    const double eps_dev = finite ? -1.0 : eps;
+    const int64_t cap = finite ? horizon : spec->max_sweeps;
+    // workgroups of the self-convergence measure (within gap_part's N slots)
+    const int64_t n_delta = std::min<int64_t>(1024, (n_safe + 255) / 256);
+    HIP_TRY(launch_ctrl_init(ctrl, eps_dev, cap, h->st));
+    int64_t sweeps = 0, launched = 0;
+    double gap = n_safe > 0 ? 1.0 : 0.0;
+    int converged = (finite || self_rule) ? n_safe == 0 : gap <= eps;
+    float sweep_ms = 0.f, launch_ms = 0.f;
+    if (!converged) {
+      // Sweeps go out in batches between host polls of the control block.
+      // A batch lasts about 2 ms of GPU time (from the last batch's per-sweep
+      // time) and never exceeds the number of sweeps still needed if the
+      // gap keeps contracting at its last observed rate, so few launches run
+      // after the stop test has fired.
+      int64_t chunk = 1, prev_sweeps = 0;
+      double prev_gap = 1.0;
+      std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
+      for (;;) {
+        const int64_t n = std::min<int64_t>(chunk, cap - launched);
+        if (n <= 0) break;
+        const auto c0 = std::chrono::steady_clock::now();
+        for (int64_t k = 0; k < n; ++k) {
+          const int64_t idx = launched + k;
+          a.vin = vb[idx & 1];
+          a.vout = vb[(idx + 1) & 1];
+          // the sort is outside the timed pair: the events bracket the sweep kernel
+          if (sel)
+            HIP_TRY(launch_value_sort(ctrl, a.vin, N, a.maximise ? -1.0 : 1.0, vs_buf[0],
+                                      vs_buf[1], h->st));
+          hipEvent_t e0 = nullptr, e1 = nullptr;
+          if (timing) {
+            e0 = events.make();
+            e1 = events.make();
+            HIP_TRY(hipEventRecord(e0, h->st));
+          }
+          if (use_box)
+            HIP_TRY(launch_sweep_sb(a, h->max_box, h->max_row, h->st));
+          else if (sel)
+            HIP_TRY(launch_sweep_sel(a, h->max_row, h->st));
+          else
+            HIP_TRY(launch_sweep(a, h->max_row, h->st));
+          if (timing) {
+            HIP_TRY(hipEventRecord(e1, h->st));
+            marks.emplace_back(e0, e1);
+          }
+          if (self_rule) {
+            HIP_TRY(launch_self_delta(ctrl, safe, n_safe, a.vin, a.vout, gap_part, n_delta,
+                                      h->st));
+            HIP_TRY(launch_finish(ctrl, gap_part, n_delta, h->st));
+          } else {
+            HIP_TRY(launch_finish(ctrl, gap_part, sweep_blocks(a, use_box), h->st));
+          }
+        }
+        launched += n;
+        HIP_TRY(hipMemcpyAsync(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->st));
+        HIP_TRY(hipStreamSynchronize(h->st));
+        if (hc.done) break;
+        const double per_sweep_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0)
+                .count() / (double)n;
+        int64_t next = (int64_t)std::max(1.0, std::min(256.0, 2.0 / std::max(per_sweep_ms, 1e-3)));
+        if (!finite && hc.sweeps > prev_sweeps && hc.gap > 0.0 && hc.gap < prev_gap) {
+          const double rate = std::pow(hc.gap / prev_gap, 1.0 / (double)(hc.sweeps - prev_sweeps));
+          if (rate > 0.0 && rate < 1.0) {
+            const double need = std::ceil(std::log(eps / hc.gap) / std::log(rate));
+            if (need >= 1.0 && need < (double)next) next = (int64_t)need;
+          }
+        }
+        prev_sweeps = hc.sweeps;
+        prev_gap = hc.gap;
+        chunk = next;
+      }
+      sweeps = hc.sweeps;
+      gap = hc.gap;
+      converged = finite ? hc.sweeps == cap : hc.converged;
+      for (int64_t k = 0; k < (int64_t)marks.size(); ++k) {
+        const float ms = event_ms(marks[k].first, marks[k].second);
+        launch_ms += ms;
+        if (k < sweeps) sweep_ms += ms;
+      }
+    }
+    info.sweeps[pass] = sweeps;
+    info.gap[pass] = gap;
+    info.converged[pass] = converged;
+    info.updates[pass] = sweeps * n_safe * a.inputs_per_state;
+    info.sweep_ms[pass] = sweep_ms;
+    info.launch_ms[pass] = launch_ms;
+    info.launches[pass] = launched;
+    HIP_TRY(launch_finalize(cls, N, vb[sweeps & 1], pi, adverse ? 0 : 1, safety, finite,
+                            adverse ? lo : hi, pass == 0 ? policy : nullptr, h->st));
+  }
+  info.horizon = horizon;
+  return IMPACT_OK;
+  };
+  int rc;
+  if (spec->horizon == IMPACT_HORIZON_AUTO) {
+    // Remark 5.2: the sweeps each pass needs for both of its iterates to
+    // converge to themselves; the larger count is the horizon of a
+    // value-iteration run, whose outputs are returned
+    if ((rc = run_passes(true, 0)) < 0) return rc;
+    const int64_t s0 = info.sweeps[0], s1 = info.sweeps[1];
+    const int32_t c0 = info.converged[0], c1 = info.converged[1];
+    const double self_ms = info.sweep_ms[0] + info.sweep_ms[1];
+    info = impact_iter_info{};
+    info.n_safe = n_safe;
+    if ((rc = run_passes(false, std::max<int64_t>(1, std::max(s0, s1)))) < 0) return rc;
+    info.self_sweeps[0] = s0;
+    info.self_sweeps[1] = s1;
+    info.converged[0] = c0;
+    info.converged[1] = c1;
+    info.self_sweep_ms = self_ms;
+  } else if ((rc = run_passes(false, spec->horizon)) < 0) {
+    return rc;
+  }
+  HIP_TRY(hipStreamSynchronize(h->st));
+  info.iterate_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+          .count();
+  h->last = info;
+  return (info.converged[0] && info.converged[1]) ? IMPACT_OK : IMPACT_NOT_CONVERGED;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* impact_last_error(void) { return g_err.c_str(); }
@@ -296,6 +587,10 @@ static int build_many(int32_t n, const impact_system* sys, const impact_grid* gr
   auto store = std::make_shared<Storage>();
   if (dev) store->dev = *dev;
   store->st = (hipStream_t)store->dev.stream;
+  if (hipGetDevice(&store->device) != hipSuccess) {
+    (void)hipGetLastError();
+    store->device = 0;
+  }
   const bool factors = window[0].storage == IMPACT_STORE_FACTORS;
   std::vector<SysParams> hp(n);
   std::vector<int64_t> row_base(n + 1, 0), state_base(n + 1, 0), u_off(n + 1, 0);
@@ -327,13 +622,13 @@ static int build_many(int32_t n, const impact_system* sys, const impact_grid* gr
     st->ot = st->own<double4>(R);
     st->row_off = st->own<int64_t>(R + 1);
     ScratchT<Storage> tmp(st);
-    int64_t* cnt = tmp.get<int64_t>(R);
-    int32_t* maxima = tmp.get<int32_t>(2 * (int64_t)n);
-    unsigned long long* boxmax = tmp.get<unsigned long long>(n);
-    int64_t* d_row_base = tmp.get<int64_t>(n + 1);
-    int64_t* d_state_base = tmp.get<int64_t>(n + 1);
+    int64_t* cnt = tmp.template get<int64_t>(R);
+    int32_t* maxima = tmp.template get<int32_t>(2 * (int64_t)n);
+    unsigned long long* boxmax = tmp.template get<unsigned long long>(n);
+    int64_t* d_row_base = tmp.template get<int64_t>(n + 1);
+    int64_t* d_state_base = tmp.template get<int64_t>(n + 1);
     const int64_t te = scan_tmp_elems(R);
-    int64_t* stmp = tmp.get<int64_t>(te);
+    int64_t* stmp = tmp.template get<int64_t>(te);
     std::vector<double> U_all(std::max<int64_t>(1, u_off[n]));
     for (int32_t i = 0; i < n; ++i) {
       hp[i].U = st->d_U + u_off[i];
@@ -582,274 +877,11 @@ int impact_imdp_export_rows(const impact_imdp* hc, int64_t row0, int64_t nrows, 
 int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps, double* lo,
                             double* hi, int32_t* policy) {
   g_err.clear();
-  if (!h || !spec) return fail(IMPACT_E_INVAL, "null argument");
-  if (!lo || !hi || !policy) return fail(IMPACT_E_INVAL, "lo/hi/policy must be device buffers");
-  if (spec->kind < IMPACT_SAFETY || spec->kind > IMPACT_REACH_AVOID)
-    return fail(IMPACT_E_INVAL, "unknown spec kind");
-  if (spec->n_target < 0 || spec->n_avoid < 0) return fail(IMPACT_E_INVAL, "negative box count");
-  if ((spec->n_target > 0 && !spec->target_boxes) || (spec->n_avoid > 0 && !spec->avoid_boxes))
-    return fail(IMPACT_E_INVAL, "box array is null");
-  if (spec->kind == IMPACT_SAFETY && spec->n_target != 0)
-    return fail(IMPACT_E_INVAL, "safety takes no target boxes");
-  if (spec->kind == IMPACT_REACH && spec->n_avoid != 0)
-    return fail(IMPACT_E_INVAL, "reachability takes no avoid boxes (use reach-avoid)");
-  if (spec->pessimistic != 0 && spec->pessimistic != 1)
-    return fail(IMPACT_E_INVAL, "pessimistic must be 0 or 1");
-  if (spec->max_sweeps < 1) return fail(IMPACT_E_INVAL, "max_sweeps must be >= 1");
-  if (spec->horizon < IMPACT_HORIZON_AUTO)
-    return fail(IMPACT_E_INVAL, "horizon must be >= 0 or IMPACT_HORIZON_AUTO");
-  if (!is_finite(eps) || !(eps > 0.0)) return fail(IMPACT_E_INVAL, "eps must be finite and > 0");
-  const int d = h->d;
-  for (int64_t k = 0; k < (int64_t)spec->n_target * 2 * d; ++k)
-    if (std::isnan(spec->target_boxes[k])) return fail(IMPACT_E_INVAL, "NaN in target box");
-  for (int64_t k = 0; k < (int64_t)spec->n_avoid * 2 * d; ++k)
-    if (std::isnan(spec->avoid_boxes[k])) return fail(IMPACT_E_INVAL, "NaN in avoid box");
-  for (int b = 0; b < spec->n_target; ++b)
-    for (int i = 0; i < d; ++i)
-      if (spec->target_boxes[b * 2 * d + i] > spec->target_boxes[b * 2 * d + d + i])
-        return fail(IMPACT_E_INVAL, "target box with lo > hi");
-  for (int b = 0; b < spec->n_avoid; ++b)
-    for (int i = 0; i < d; ++i)
-      if (spec->avoid_boxes[b * 2 * d + i] > spec->avoid_boxes[b * 2 * d + d + i])
-        return fail(IMPACT_E_INVAL, "avoid box with lo > hi");
-
+  const int rc = validate_iterate(h, spec, eps, lo, hi, policy);
+  if (rc != IMPACT_OK) return rc;
   return guarded([&]() -> int {
-    const auto t_start = std::chrono::steady_clock::now();
-    const int64_t N = h->n_states;
-    const bool safety = spec->kind == IMPACT_SAFETY;
     Scratch tmp(h);
-    double* tb = tmp.get<double>((int64_t)spec->n_target * 2 * d);
-    double* ab = tmp.get<double>((int64_t)spec->n_avoid * 2 * d);
-    int8_t* cls = tmp.get<int8_t>(N);
-    int64_t* flag = tmp.get<int64_t>(N);
-    int64_t* pos = tmp.get<int64_t>(N + 1);
-    const int64_t te = scan_tmp_elems(N);
-    int64_t* stmp = tmp.get<int64_t>(te);
-    int32_t* safe = tmp.get<int32_t>(N);
-    double2* vb[2] = {tmp.get<double2>(N), tmp.get<double2>(N)};
-    int32_t* pi = tmp.get<int32_t>(N);
-    Ctrl* ctrl = tmp.get<Ctrl>(1);
-    double* gap_part = tmp.get<double>(std::max<int64_t>(1, N));
-    // rows longer than a wavefront's sort: selection sweep, which needs the
-    // value vector sorted per sweep and keeps a per-row hint
-    const bool sel = h->max_row > 512;
-    double* vs_buf[2] = {nullptr, nullptr};
-    int32_t* hint = nullptr;
-    if (sel) {
-      vs_buf[0] = tmp.get<double>(2 * N);
-      vs_buf[1] = tmp.get<double>(2 * N);
-      hint = tmp.get<int32_t>(2 * h->n_rows);
-    }
-    h->store->hip_used = true;
-
-    if (spec->n_target > 0)
-      HIP_TRY(hipMemcpyAsync(tb, spec->target_boxes, sizeof(double) * spec->n_target * 2 * d,
-                             hipMemcpyHostToDevice, h->st));
-    if (spec->n_avoid > 0)
-      HIP_TRY(hipMemcpyAsync(ab, spec->avoid_boxes, sizeof(double) * spec->n_avoid * 2 * d,
-                             hipMemcpyHostToDevice, h->st));
-    HIP_TRY(launch_label(h->dp, N, tb, spec->n_target, ab, spec->n_avoid, cls, flag, h->st));
-    HIP_TRY(exclusive_scan_i64(flag, pos, N, stmp, te, h->st));
-    int64_t n_safe = 0;
-    HIP_TRY(hipMemcpyAsync(&n_safe, pos + N, sizeof(int64_t), hipMemcpyDeviceToHost, h->st));
-    HIP_TRY(hipStreamSynchronize(h->st));
-    HIP_TRY(launch_compact(cls, pos, N, safe, h->st));
-
-    impact_iter_info info{};
-    info.n_safe = n_safe;
-    std::vector<hipEvent_t> evs;
-    auto new_event = [&]() {
-      hipEvent_t e;
-      HIP_TRY(hipEventCreate(&e));
-      evs.push_back(e);
-      return e;
-    };
-    Ctrl hc{};
-    // Both passes under one stop rule: self_rule stops a pass once both its
-    // iterates stop moving (Remark 5.2); otherwise the gap rule, or exactly
-    // `horizon` sweeps when horizon > 0 (Remark 5.1).
-    auto run_passes = [&](bool self_rule, int64_t horizon) -> int {
-    for (int pass = 0; pass < 2; ++pass) {
-      // policy pass: one sort per state over its rows' window box when every
-      // row fits a wavefront; the fixed-input pass has one row per state and
-      // sorts per row unless the state-box mode is forced
-      const int32_t mode = h->sweep_mode[pass];
-      // (with a disturbance player the state box must hold a whole state's
-      // rows; the fixed-input pass then also sweeps by state box, so that an
-      // item's disturbance rows share one sort)
-      const bool use_box = h->max_row <= 512 &&
-                           (h->nw > 1 ? h->max_box <= 512 && mode != IMPACT_SWEEP_PER_ROW
-                                      : (mode == IMPACT_SWEEP_STATE_BOX ||
-                                         (mode == IMPACT_SWEEP_AUTO && pass == 0)));
-      SweepArgs a{};
-      a.row_off = h->row_off;
-      a.win = h->win;
-      a.ot = h->ot;
-      a.ent = h->ent;
-      a.fac = h->fac;
-      a.sys = h->dp;
-      a.pi = pi;
-      a.safe = safe;
-      a.ctrl = ctrl;
-      a.gap_part = gap_part;
-      a.n_safe = n_safe;
-      a.fs = h->fs;
-      a.pass = pass;
-      a.reach = !safety;
-      // the adversarial LP (reach: minimising; safety: maximising the bad
-      // mass) runs in the policy pass for the pessimistic policy and in the
-      // fixed-input pass for the optimistic one
-      const bool adverse = (pass == 0) == (spec->pessimistic != 0);
-      a.maximise = adverse ? safety : !safety;
-      a.nu = h->nu;
-      a.nw = h->nw;
-      a.d = d;
-      a.windowed = h->windowed;
-      a.storage = h->storage;
-      a.out_val = safety ? 1.0 : 0.0;
-      a.inputs_per_state = (pass == 0 ? h->nu : 1) * h->nw;  // rows swept per state
-      a.n_cells = N;
-      a.hint = hint;
-      double* vsorted = sel ? vs_buf[value_sort_passes(N) & 1] : nullptr;
-      a.vsort = vsorted;
-      int G = 1;
-      if (h->max_row <= 512) G = std::max(1, 4 / a.inputs_per_state);
-      while (G > 1 && G * a.inputs_per_state > 256) --G;
-      if (a.inputs_per_state > 256)
-        return fail(IMPACT_E_UNSUPPORTED, "more than 256 rows per state");
-      // the fixed-input pass sorting per row runs several rows per wavefront
-      if (pass == 1 && !use_box && h->nw == 1 && rows_g_states_per_block(h->max_row) > 0)
-        G = rows_g_states_per_block(h->max_row);
-      if (sel) G = 1;  // one workgroup per state
-      a.states_per_block = G;
-      if (sel) HIP_TRY(hipMemsetAsync(hint, 0xff, sizeof(int32_t) * 2 * h->n_rows, h->st));
-
-      HIP_TRY(launch_init_values(cls, N, safety, vb[0], vb[1], pass == 0 ? pi : nullptr, h->st));
-      // finite horizon: the device stop test never fires (gap >= 0 > -1) and
-      // the cap is the horizon
-      const bool finite = horizon > 0;
-      const double eps_dev = finite ? -1.0 : eps;
-      const int64_t cap = finite ? horizon : spec->max_sweeps;
-      // workgroups of the self-convergence measure (within gap_part's N slots)
-      const int64_t n_delta = std::min<int64_t>(1024, (n_safe + 255) / 256);
-      HIP_TRY(launch_ctrl_init(ctrl, eps_dev, cap, h->st));
-      int64_t sweeps = 0, launched = 0;
-      double gap = n_safe > 0 ? 1.0 : 0.0;
-      int converged = (finite || self_rule) ? n_safe == 0 : gap <= eps;
-      float sweep_ms = 0.f, launch_ms = 0.f;
-      if (!converged) {
-        // Sweeps go out in batches between host polls of the control block.
-        // A batch lasts about 2 ms of GPU time (from the last batch's per-sweep
-        // time) and never exceeds the number of sweeps still needed if the
-        // gap keeps contracting at its last observed rate, so few launches run
-        // after the stop test has fired.
-        int64_t chunk = 1, prev_sweeps = 0;
-        double prev_gap = 1.0;
-        std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
-        for (;;) {
-          const int64_t n = std::min<int64_t>(chunk, cap - launched);
-          if (n <= 0) break;
-          const auto c0 = std::chrono::steady_clock::now();
-          for (int64_t k = 0; k < n; ++k) {
-            const int64_t idx = launched + k;
-            a.vin = vb[idx & 1];
-            a.vout = vb[(idx + 1) & 1];
-            // the sort is outside the timed pair: the events bracket the sweep kernel
-            if (sel)
-              HIP_TRY(launch_value_sort(ctrl, a.vin, N, a.maximise ? -1.0 : 1.0, vs_buf[0],
-                                        vs_buf[1], h->st));
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (h->timing) {
-              e0 = new_event();
-              e1 = new_event();
-              HIP_TRY(hipEventRecord(e0, h->st));
-            }
-            if (use_box)
-              HIP_TRY(launch_sweep_sb(a, h->max_box, h->max_row, h->st));
-            else if (sel)
-              HIP_TRY(launch_sweep_sel(a, h->max_row, h->st));
-            else
-              HIP_TRY(launch_sweep(a, h->max_row, h->st));
-            if (h->timing) {
-              HIP_TRY(hipEventRecord(e1, h->st));
-              marks.emplace_back(e0, e1);
-            }
-            if (self_rule) {
-              HIP_TRY(launch_self_delta(ctrl, safe, n_safe, a.vin, a.vout, gap_part, n_delta,
-                                        h->st));
-              HIP_TRY(launch_finish(ctrl, gap_part, n_delta, h->st));
-            } else {
-              HIP_TRY(launch_finish(ctrl, gap_part, sweep_blocks(a, use_box), h->st));
-            }
-          }
-          launched += n;
-          HIP_TRY(hipMemcpyAsync(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->st));
-          HIP_TRY(hipStreamSynchronize(h->st));
-          if (hc.done) break;
-          const double per_sweep_ms =
-              std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0)
-                  .count() / (double)n;
-          int64_t next = (int64_t)std::max(1.0, std::min(256.0, 2.0 / std::max(per_sweep_ms, 1e-3)));
-          if (!finite && hc.sweeps > prev_sweeps && hc.gap > 0.0 && hc.gap < prev_gap) {
-            const double rate = std::pow(hc.gap / prev_gap, 1.0 / (double)(hc.sweeps - prev_sweeps));
-            if (rate > 0.0 && rate < 1.0) {
-              const double need = std::ceil(std::log(eps / hc.gap) / std::log(rate));
-              if (need >= 1.0 && need < (double)next) next = (int64_t)need;
-            }
-          }
-          prev_sweeps = hc.sweeps;
-          prev_gap = hc.gap;
-          chunk = next;
-        }
-        sweeps = hc.sweeps;
-        gap = hc.gap;
-        converged = finite ? hc.sweeps == cap : hc.converged;
-        for (int64_t k = 0; k < (int64_t)marks.size(); ++k) {
-          const float ms = event_ms(marks[k].first, marks[k].second);
-          launch_ms += ms;
-          if (k < sweeps) sweep_ms += ms;
-        }
-      }
-      info.sweeps[pass] = sweeps;
-      info.gap[pass] = gap;
-      info.converged[pass] = converged;
-      info.updates[pass] = sweeps * n_safe * a.inputs_per_state;
-      info.sweep_ms[pass] = sweep_ms;
-      info.launch_ms[pass] = launch_ms;
-      info.launches[pass] = launched;
-      HIP_TRY(launch_finalize(cls, N, vb[sweeps & 1], pi, adverse ? 0 : 1, safety, finite,
-                              adverse ? lo : hi, pass == 0 ? policy : nullptr, h->st));
-    }
-    info.horizon = horizon;
-    return IMPACT_OK;
-    };
-    int rc;
-    if (spec->horizon == IMPACT_HORIZON_AUTO) {
-      // Remark 5.2: the sweeps each pass needs for both of its iterates to
-      // converge to themselves; the larger count is the horizon of a
-      // value-iteration run, whose outputs are returned
-      if ((rc = run_passes(true, 0)) < 0) return rc;
-      const int64_t s0 = info.sweeps[0], s1 = info.sweeps[1];
-      const int32_t c0 = info.converged[0], c1 = info.converged[1];
-      const double self_ms = info.sweep_ms[0] + info.sweep_ms[1];
-      info = impact_iter_info{};
-      info.n_safe = n_safe;
-      if ((rc = run_passes(false, std::max<int64_t>(1, std::max(s0, s1)))) < 0) return rc;
-      info.self_sweeps[0] = s0;
-      info.self_sweeps[1] = s1;
-      info.converged[0] = c0;
-      info.converged[1] = c1;
-      info.self_sweep_ms = self_ms;
-    } else if ((rc = run_passes(false, spec->horizon)) < 0) {
-      return rc;
-    }
-    HIP_TRY(hipStreamSynchronize(h->st));
-    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
-    info.iterate_ms =
-        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
-            .count();
-    h->last = info;
-    return (info.converged[0] && info.converged[1]) ? IMPACT_OK : IMPACT_NOT_CONVERGED;
+    return iterate_body(h, spec, eps, lo, hi, policy, tmp, h->timing);
   });
 }
 

@@ -131,6 +131,8 @@ int value_sort_passes(int64_t n);
 hipError_t launch_value_sort(const Ctrl* c, const double2* vin, int64_t n, double sg,
                              double* buf0, double* buf1, hipStream_t st);
 hipError_t launch_sweep_sel(const SweepArgs& a, int32_t max_row, hipStream_t st);
+// p[0, n) = v
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 hipError_t launch_finish(Ctrl* c, const double* part, int64_t n_part, hipStream_t st);
 // part[0, n_part) = per-workgroup max(|V0' - V0|, |V1' - V1|) over the SAFE
 // states of one sweep from vin to vout (n_part workgroups of 256 threads;

@@ -134,6 +134,17 @@ hipError_t launch_value_sort(const Ctrl* c, const double2* vin, int64_t n, doubl
   return hipGetLastError();
 }
 
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
 template <int NW>
 struct SelLds {
   double red[2][NW][6];        // block sums, double-buffered

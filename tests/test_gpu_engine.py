@@ -3,8 +3,10 @@
 A query run by the engine must equal the same query run alone by
 impact_interval_iterate with the same sweep kernels (bitwise: the engine runs
 the state-box kernel for the policy pass and the per-row kernel for the
-fixed-input pass), must not depend on which other queries share its launches
-(bitwise), and must match the CPU oracle at the parity tolerances.
+fixed-input pass; rows longer than 512 entries, which the two sweep
+differently, are held to the oracle), must not depend on which other queries
+share its launches (bitwise), and must match the CPU oracle at the parity
+tolerances.
 """
 import numpy as np
 import pytest
@@ -38,6 +40,47 @@ def _same(a, b, label):
     for x, y, k in zip(_np(a), _np(b), ("lo", "hi", "policy")):
         assert np.array_equal(x, y), f"{label}: {k} differs (max {np.abs(x - y).max()})"
     assert tuple(a["info"]["sweeps"]) == tuple(b["info"]["sweeps"]), label
+
+
+def _same_or_oracle(eng_res, plain, name, system, spec):
+    """Bitwise equal to the plain solve when both run the same sweep kernels;
+    for rows longer than 512 entries the plain solve runs the selection sweep
+    and the engine its workgroup sort, so both are held to the oracle instead
+    (values within 1e-9, policies equal up to ties, the same sweep counts)."""
+    if name != "long_rows":
+        _same(eng_res, plain, name)
+        return
+    ref = oracle.solve(system, system["k_sigma"], spec["kind"], spec["target"], spec["avoid"],
+                       spec["eps"], spec["max_sweeps"], want_q0=True,
+                       optimistic=not spec.get("pessimistic", True),
+                       horizon=spec.get("horizon", 0))
+    reach = spec["kind"] != "safety"
+    optimistic = not spec.get("pessimistic", True)
+    kp, kf = ("hi", "lo") if optimistic else ("lo", "hi")
+    m, cls = ref["imdp"], ref["cls"]
+    for r, label in ((eng_res, "engine"), (plain, "plain")):
+        lo, hi, pol = _np(r)
+        got = dict(lo=lo, hi=hi)
+        assert np.abs(got[kp] - ref[kp]).max() <= 1e-9, f"{name} {label} {kp}"
+        assert r["info"]["sweeps"][0] == ref["sweeps"][0], f"{name} {label} sweeps"
+        safe = cls == 0
+        for s_ in np.where(safe & (pol != ref["policy"]))[0]:
+            q = ref["q0"][s_]
+            ok = q[pol[s_]] >= q.max() - 1e-12 if reach else q[pol[s_]] <= q.min() + 1e-12
+            assert ok, f"{name} {label}: policy at {s_} is not a tie"
+        fixed = ref
+        if not np.array_equal(pol, ref["policy"]):
+            # the fixed-input pass of the interval Markov chain the policy induces
+            N, U = m["n_states"], m["n_inputs"]
+            rows = np.arange(N) * U + np.maximum(pol, 0)
+            rp = m["row_ptr"]
+            idx = np.concatenate([np.arange(rp[k], rp[k + 1]) for k in rows])
+            new_rp = np.concatenate([[0], np.cumsum(rp[rows + 1] - rp[rows])]).astype(np.int64)
+            fixed = oracle.iterate(N, 1, new_rp, m["target"][idx], m["lo"][idx], m["hi"][idx],
+                                   cls, spec["kind"], spec["eps"], spec["max_sweeps"],
+                                   optimistic=optimistic, horizon=spec.get("horizon", 0))
+        assert np.abs(got[kf] - fixed[kf]).max() <= 1e-9, f"{name} {label} {kf}"
+        assert r["info"]["sweeps"][1] == fixed["sweeps"][1], f"{name} {label} sweeps"
 
 
 def _affine2():
@@ -81,7 +124,7 @@ def test_engine_query_equals_plain_iterate(I, name, make, spec, pessimistic):
     qid = eng.submit(imdp, spec)
     res = eng.run_all()
     assert set(res) == {qid}
-    _same(res[qid], plain, name)
+    _same_or_oracle(res[qid], plain, name, system, spec)
     assert res[qid]["status"] == plain["status"]
 
 
@@ -179,7 +222,7 @@ def test_engine_finite_horizon_equals_plain_iterate(I, pessimistic):
     eng = I.Engine(max_queries=len(CASES))
     ids = [eng.submit(im, sp) for im, sp in zip(imdps, specs)]
     res = eng.run_all()
-    for qid, p, (name, _, _), sp in zip(ids, plain, CASES, specs):
-        _same(res[qid], p, f"{name} T={sp['horizon']}")
+    for qid, p, (name, make, _), sp in zip(ids, plain, CASES, specs):
+        _same_or_oracle(res[qid], p, name, make(), sp)
         assert res[qid]["status"] == p["status"] == 0
         assert tuple(res[qid]["info"]["sweeps"]) == (sp["horizon"], sp["horizon"])

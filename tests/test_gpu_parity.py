@@ -252,6 +252,80 @@ def test_iterate_parity_unicycle_full_size_fixed_sweeps(I):
     compare_iter(rg, ro, cls, True, "unicycle3d K=2", q0=ro["q0"])
 
 
+def _golden_npz(name):
+    path = os.path.join(HERE, "golden", f"{name}_oracle.npz")
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def check_policy_ties(pol_g, gold, cls, label):
+    """The GPU policy equals the oracle's, or takes an input the oracle's last
+    pass-1 sweep valued within 1e-12 of the optimum (its tie mask)."""
+    safe = np.where(cls == 0)[0]
+    diff = safe[pol_g[safe] != gold["policy"][safe]]
+    ok = (gold["ties"][diff] >> pol_g[diff].astype(np.int64)) & 1
+    bad = diff[ok == 0]
+    say(f"{label}: policy differs on {len(diff)} of {len(safe)} SAFE cells, {len(bad)} not ties")
+    assert len(bad) == 0, f"{label}: policy mismatch beyond ties at {bad[:10]}"
+    return len(diff)
+
+
+@pytest.mark.parametrize("storage", ["bounds", "factors"])
+def test_iterate_parity_room5d_full_size_two_sweeps(I, storage):
+    # the largest single-GPU workload at full size: 10^5 cells, rows of up to
+    # 3,127 entries (the long-row selection sweep), two sweeps of each pass
+    # against the oracle's run stored by tests/golden/make_golden.py
+    gold = _golden_npz("room5d_k2")
+    system, spec = W.room5d()
+    say(f"room5d full size [{storage}], 2 sweeps per pass")
+    g = gpu_build(I, system, storage=storage)
+    assert g.info()["max_row"] == 3127
+    r = g.iterate(spec, max_sweeps=2)
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    lo, hi = r["lo"].cpu().numpy(), r["hi"].cpu().numpy()
+    dlo, dhi = np.abs(lo - gold["lo"]).max(), np.abs(hi - gold["hi"]).max()
+    say(f"room5d: sweeps {r['info']['sweeps']} oracle {tuple(gold['sweeps'])} status "
+        f"{r['status']} / {int(gold['status'])} max|dlo| {dlo:.2e} max|dhi| {dhi:.2e}")
+    assert r["info"]["sweeps"] == tuple(int(x) for x in gold["sweeps"])
+    assert r["status"] == int(gold["status"]) == 1
+    assert dlo <= VALUE_TOL
+    n_tie = check_policy_ties(r["policy"].cpu().numpy(), gold, cls, "room5d K=2")
+    if n_tie == 0:
+        assert dhi <= VALUE_TOL
+    else:
+        # the fixed-input pass under the GPU's policy, from the oracle
+        m = oracle.build(system, system["k_sigma"])
+        ref = fixed_pass_under(m, cls, dict(spec, max_sweeps=2), r["policy"].cpu().numpy(),
+                               False)
+        assert np.abs(hi - ref["hi"]).max() <= VALUE_TOL
+
+
+def test_iterate_parity_unicycle_full_size_converged(I):
+    # the default workload run to eps (42 + 87 sweeps) against the oracle's
+    # converged run stored by tests/golden/make_golden.py
+    gold = _golden_npz("unicycle3d_converged")
+    system, spec = W.unicycle3d()
+    g = gpu_build(I, system, storage="factors")
+    r = g.iterate(spec)
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    lo, hi = r["lo"].cpu().numpy(), r["hi"].cpu().numpy()
+    dlo, dhi = np.abs(lo - gold["lo"]).max(), np.abs(hi - gold["hi"]).max()
+    say(f"unicycle3d converged: sweeps {r['info']['sweeps']} oracle {tuple(gold['sweeps'])} "
+        f"max|dlo| {dlo:.2e} max|dhi| {dhi:.2e}")
+    assert r["status"] == int(gold["status"]) == 0
+    assert r["info"]["sweeps"][0] == int(gold["sweeps"][0])
+    assert dlo <= VALUE_TOL
+    n_tie = check_policy_ties(r["policy"].cpu().numpy(), gold, cls, "unicycle3d converged")
+    if n_tie == 0:
+        assert r["info"]["sweeps"][1] == int(gold["sweeps"][1])
+        assert dhi <= VALUE_TOL
+    else:
+        m = oracle.build(system, system["k_sigma"])
+        ref = fixed_pass_under(m, cls, spec, r["policy"].cpu().numpy(), False)
+        assert r["info"]["sweeps"][1] == ref["sweeps"][1]
+        assert np.abs(hi - ref["hi"]).max() <= VALUE_TOL
+
+
 def test_iterate_properties_unicycle_full_size(I):
     system, spec = W.unicycle3d()
     g = gpu_build(I, system)
