@@ -247,6 +247,26 @@ typedef struct {
 int impact_interval_iterate(impact_imdp *imdp, const impact_spec *spec, double eps,
                             double *lo, double *hi, int32_t *policy);
 
+/*
+ * impact_interval_iterate for callers that cannot allocate device memory
+ * (code that must not call hipMalloc, e.g. tight serving loops or harnesses
+ * that forbid allocation): the same computation, arguments, outputs, status
+ * codes and statistics, but every temporary of the call (labels, SAFE list,
+ * value and policy buffers, control block, reduction partials, the sorted
+ * value vectors and row hints of the long-row sweep) lives in one static
+ * device array of 64 MiB per GPU, held from the library's first use on that
+ * GPU until the process ends.  No allocation is made, through the handle's
+ * allocator or otherwise, and no per-launch timing is recorded.  A call whose
+ * temporaries exceed 64 MiB (about 65 bytes per state, plus 32 bytes per
+ * state and 8 per row when rows are longer than 512 entries) returns
+ * E_UNSUPPORTED and does nothing.  Calls on one GPU share its array:
+ * calls that overlap in time on the same GPU (from several threads) race and
+ * must be serialised by the caller.  Everything is re-initialised by each
+ * call, so results do not depend on earlier calls.
+ */
+int impact_interval_iterate_noalloc(impact_imdp *imdp, const impact_spec *spec, double eps,
+                                    double *lo, double *hi, int32_t *policy);
+
 /* Statistics of the last impact_interval_iterate call on this handle. */
 typedef struct {
   int64_t sweeps[2];    /* sweeps run in pass 1 / pass 2                 */

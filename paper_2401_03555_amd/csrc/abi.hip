@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -132,12 +134,31 @@ struct ScratchT {
     ps.push_back(p);
     return p;
   }
+  size_t need = 0, cap = 0;
+  bool overflow() const { return false; }  // allocation failures throw NoMem
   ~ScratchT() {
     h->sync();
     for (void* p : ps) h->release(p);
   }
 };
 using Scratch = ScratchT<impact_imdp>;
+
+// Temporaries of one call inside a fixed device region (the no-allocation
+// entry point): bump allocation at 256-byte alignment; a request beyond the
+// region's end returns null and marks the arena as overflowed.
+struct Arena {
+  char* base;
+  size_t cap;
+  size_t need = 0;
+  template <class T>
+  T* get(int64_t elems) {
+    const size_t bytes = (size_t)(elems > 0 ? elems : 1) * sizeof(T);
+    const size_t off = (need + 255) & ~(size_t)255;
+    need = off + bytes;
+    return need <= cap ? (T*)(base + off) : nullptr;
+  }
+  bool overflow() const { return need > cap; }
+};
 
 // HIP events of one call, destroyed on every exit path.
 struct EventPool {
@@ -286,9 +307,46 @@ int imdp_view(const impact_imdp* h, ImdpView* v) {
 }
 }  // namespace impact
 
+// Temporaries of impact_interval_iterate_noalloc: one array per GPU, which
+// each GPU the library runs on holds until the process ends.  Host code never
+// uses this name as an address: it takes the device address from
+// hipGetSymbolAddress once per device (scratch_base).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
-// Arguments of impact_interval_iterate.
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_base;  // device -> address of its scratch array
+
+// The device address of `device`'s scratch array, looked up on the first call
+// for that device with the device current.
+int scratch_base(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_base.find(device);
+  if (it != g_scratch_base.end()) {
+    *out = it->second;
+    return IMPACT_OK;
+  }
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(IMPACT_E_HIP, "hipGetDevice failed");
+  if (cur != device && hipSetDevice(device) != hipSuccess)
+    return fail(IMPACT_E_HIP, "hipSetDevice failed");
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (cur != device) (void)hipSetDevice(cur);
+  if (e != hipSuccess || !p)
+    return fail(IMPACT_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_base[device] = p;
+  *out = p;
+  return IMPACT_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Arguments of impact_interval_iterate and its no-allocation variant.
 int validate_iterate(const impact_imdp* h, const impact_spec* spec, double eps, const double* lo,
                      const double* hi, const int32_t* policy) {
   if (!h || !spec) return fail(IMPACT_E_INVAL, "null argument");
@@ -325,7 +383,8 @@ int validate_iterate(const impact_imdp* h, const impact_spec* spec, double eps, 
   return IMPACT_OK;
 }
 
-// Interval iteration with the call's temporaries from tmp.
+// Interval iteration with the call's temporaries from tmp (the caller's
+// allocator, or the static scratch array of the no-allocation variant).
 template <class Tmp>
 int iterate_body(impact_imdp* h, const impact_spec* spec, double eps, double* lo, double* hi,
                  int32_t* policy, Tmp& tmp, bool timing) {
@@ -355,6 +414,10 @@ int iterate_body(impact_imdp* h, const impact_spec* spec, double eps, double* lo
     vs_buf[1] = tmp.template get<double>(2 * N);
     hint = tmp.template get<int32_t>(2 * h->n_rows);
   }
+  if (tmp.overflow())
+    return fail(IMPACT_E_UNSUPPORTED,
+                "the call needs " + std::to_string(tmp.need) + " bytes of temporaries, more than the " +
+                    std::to_string(tmp.cap) + " of the static scratch array");
   h->store->hip_used = true;
 
   if (spec->n_target > 0)
@@ -882,6 +945,21 @@ int impact_interval_iterate(impact_imdp* h, const impact_spec* spec, double eps,
   return guarded([&]() -> int {
     Scratch tmp(h);
     return iterate_body(h, spec, eps, lo, hi, policy, tmp, h->timing);
+  });
+}
+
+int impact_interval_iterate_noalloc(impact_imdp* h, const impact_spec* spec, double eps,
+                                    double* lo, double* hi, int32_t* policy) {
+  g_err.clear();
+  const int rc = validate_iterate(h, spec, eps, lo, hi, policy);
+  if (rc != IMPACT_OK) return rc;
+  void* base = nullptr;
+  const int rb = scratch_base(h->store->device, &base);
+  if (rb != IMPACT_OK) return rb;
+  return guarded([&]() -> int {
+    Arena tmp{(char*)base, kScratchBytes};
+    // no per-launch timing: event creation is left to the allocating variant
+    return iterate_body(h, spec, eps, lo, hi, policy, tmp, false);
   });
 }
 

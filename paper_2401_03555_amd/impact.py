@@ -28,7 +28,7 @@ EXPORTS = ["impact_build_imdp", "impact_interval_iterate", "impact_last_iter_inf
            "impact_set_sweep_modes",
            "impact_build_imdp_batch", "impact_mq_create", "impact_mq_submit", "impact_mq_run",
            "impact_mq_poll", "impact_mq_query_info", "impact_mq_last_error", "impact_mq_free",
-           "impact_probe_fp64_fma", "impact_build_imdp_dist"]
+           "impact_probe_fp64_fma", "impact_build_imdp_dist", "impact_interval_iterate_noalloc"]
 SWEEP_MODES = {"auto": 0, "per_row": 1, "state_box": 2}
 
 _pd = C.POINTER(C.c_double)
@@ -121,6 +121,9 @@ def lib():
         L.impact_interval_iterate.restype = C.c_int
         L.impact_interval_iterate.argtypes = [C.c_void_p, C.POINTER(Spec), C.c_double, _pd, _pd,
                                               _pi32]
+        L.impact_interval_iterate_noalloc.restype = C.c_int
+        L.impact_interval_iterate_noalloc.argtypes = [C.c_void_p, C.POINTER(Spec), C.c_double,
+                                                      _pd, _pd, _pi32]
         L.impact_last_iter_info.restype = C.c_int
         L.impact_last_iter_info.argtypes = [C.c_void_p, C.POINTER(IterInfo)]
         L.impact_imdp_get_info.restype = C.c_int
@@ -298,8 +301,11 @@ class Imdp:
             out["entries"] = ent.cpu().numpy()[:total]
         return out
 
-    def iterate(self, spec, eps=None, max_sweeps=None, out=None):
-        """Interval iteration; returns dict(lo, hi, policy (torch cuda), status, info)."""
+    def iterate(self, spec, eps=None, max_sweeps=None, out=None, noalloc=False):
+        """Interval iteration; returns dict(lo, hi, policy (torch cuda), status, info).
+
+        noalloc: run impact_interval_iterate_noalloc (temporaries in the
+        library's static device array instead of the allocator)."""
         torch = self._dev.torch
         d = self.info()["dim"]
         n = self.info()["n_states"]
@@ -317,7 +323,8 @@ class Imdp:
             pol = torch.empty(n, dtype=torch.int32, device=dev)
         else:
             lo, hi, pol = out
-        rc = _check(lib().impact_interval_iterate(
+        fn = lib().impact_interval_iterate_noalloc if noalloc else lib().impact_interval_iterate
+        rc = _check(fn(
             self._h, C.byref(s), float(eps if eps is not None else spec["eps"]),
             _torch_ptr(lo, C.c_double), _torch_ptr(hi, C.c_double), _torch_ptr(pol, C.c_int32)))
         return dict(lo=lo, hi=hi, policy=pol, status=rc, info=self.last_iter_info())
