@@ -4,25 +4,29 @@
 One step = the whole path on one batch of synthetic input: build the
 abstraction (bounds in HBM) and run interval iteration (both passes, to eps
 or the sweep cap) for the workload's specification.  The default workload is
-the 3D unicycle reach-avoid system (50x50x24 cells, 20 inputs, +-6 sigma
-windows, eps 1e-8).
+the largest single-GPU configuration: the 5D room safety system (10^5 cells,
+4 inputs, rows of up to 3,127 entries, 50 sweeps per pass since its second
+pass does not converge); the 3D unicycle reach-avoid system (50x50x24 cells,
+20 inputs, eps 1e-8, run to convergence) is measured beside it under
+``components``.
 
 Prints one JSON line.  ``value`` is (state, input)-row LP updates per second
 over the whole timed step (build included); the line also carries the bound
 construction rate, the roofline of the dominant kernel (the policy-pass sweep,
-timed with HIP events on the library's stream) and the CPU oracle timed on a
-bounded sample of the same workload.  The storage mode and the per-pass entry
-order come from the autotuner unless given.
+timed with HIP events on the library's stream), a bounded served leg (p50 /
+p99 latency and queries/s of the continuous-batching loop at a sustainable
+arrival rate, against serial plain solves) and the CPU oracle timed on a
+bounded sample of the same workload on one core and on all of the host's
+cores (at most 16).  The storage mode and the per-pass entry order come from
+the autotuner unless given.
 
-``--forms`` adds the two systems forms to the same line, each against its
-plain counterpart on the same GPU at the same eps:
+``--forms`` adds the systems forms at full size, each against its plain
+counterpart on the same GPU at the same eps:
   batched: seeded random 2D/3D linear instances built with one batch build
            and iterated together by the graph-captured engine, against a
            loop of plain build + iterate calls, one instance at a time;
-  served : a Poisson request trace over a 64-system pool served by the
-           continuous-batching loop, against serial plain solves.
-``--forms disturbed`` adds the disturbance player (the 2D robot with 11
-disturbances) with its own roofline and oracle sample.
+  served : the Poisson request trace of the served configuration;
+  disturbed: the disturbance player (the 2D robot with 11 disturbances).
 """
 import argparse
 import json
@@ -42,8 +46,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="unicycle3d",
+    ap.add_argument("--workload", default="room5d",
                     choices=["unicycle3d", "robot2d", "room5d"])
+    ap.add_argument("--components", default="unicycle3d",
+                    help="comma list of further workloads measured beside the headline one")
+    ap.add_argument("--no-served", action="store_true",
+                    help="skip the bounded served leg of the default line")
+    ap.add_argument("--served-rate", type=float, default=20.0,
+                    help="arrivals per second of the bounded served leg")
+    ap.add_argument("--served-seconds", type=float, default=3.0,
+                    help="length of the bounded served leg's trace")
+    ap.add_argument("--served-max-sweeps", type=int, default=1000)
+    ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--storage", default="tuned", choices=["tuned", "bounds", "factors"])
     ap.add_argument("--sweep-mode", default="tuned",
                     choices=["tuned", "auto", "per_row", "state_box"])
@@ -163,25 +177,40 @@ def recorded_valu(kernel, storage, workload):
     return _recorded("valu", "valu_per_launch", kernel, storage, workload)
 
 
-def build_roofline(imdp, d):
-    """Construction against both of its ceilings.
+def recorded_build_flops(storage, workload):
+    """FP64 operations per build (k_row_geom + k_expand) counted by the SQ
+    counters recorded under profiles/ (lines ``fp64: ...``), or None."""
+    return _recorded("fp64", "flops_per_build", "build", storage, workload)
+
+
+def build_roofline(imdp, d, workload):
+    """Construction against its two ceilings.
 
     HBM: bytes the build must write -- per row 8*d B window + 32 B OUT/TAIL +
     8 B row offset, plus 16 B per entry (bounds storage) or 16 B per factor
-    (sum of the window widths; factor storage).  FP64: the 2(d-1) multiplies
-    that form each entry's (lo, hi) from its factors (the erfc evaluations,
-    ~sum_i (4 W_i + 2) per row, are not counted as flops).  Entries are counted
-    as implied entries whatever the storage.
+    (sum of the window widths; factor storage).  FP64: the work the chosen
+    storage performs -- the erfc evaluations at both ends of every window edge
+    of every dimension (2 (W_i + 1) per dimension and row), and, with bounds
+    storage only, the 2(d-1) multiplies that form each entry's (lo, hi) from
+    its factors (factor storage leaves them to the sweeps) -- and, when the
+    SQ counters of this build are recorded, the fraction of the FP64 vector
+    peak they give.  Entries are counted as implied entries whatever the
+    storage.
     """
     info = imdp.info()
     ex = imdp.export_rows(0, info["n_rows"], entries=False)
     cells = int(ex["counts"].sum())
     rows = info["n_rows"]
-    fac = int(ex["win"][:, d:].sum())
-    payload = 16 * (fac if info["storage"] == 2 else cells)
+    widths = ex["win"][:, d:]
+    fac = int(widths.sum())
+    bounds = info["storage"] != 2
+    payload = 16 * (cells if bounds else fac)
     nbytes = payload + rows * (8 * d + 32 + 8)
     t = info["build_ms"] * 1e-3
-    muls = 2 * max(0, d - 1) * cells
+    products = 2 * max(0, d - 1) * cells if bounds else 0
+    erfc = int(2 * (widths + 1).sum())
+    storage = "bounds" if bounds else "factors"
+    flops = recorded_build_flops(storage, workload)
     return {
         "kernels": "k_row_geom + scan + k_expand",
         "build_ms": info["build_ms"],
@@ -189,37 +218,100 @@ def build_roofline(imdp, d):
         "hbm_bytes": nbytes,
         "hbm_gbs": nbytes / t / 1e9,
         "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS,
-        "fp64_mul_per_s": muls / t,
-        "fp64_frac": muls / t / (FP64_PEAK_TFLOPS * 1e12),
-        "binding": "hbm" if nbytes / HBM_PEAK_GBS / 1e9 > muls / (FP64_PEAK_TFLOPS * 1e12)
-                   else "fp64",
+        "fp64_products": products,
+        "erfc_evals": erfc,
+        "erfc_per_s": erfc / t,
+        "fp64_frac": None if flops is None else flops / t / (FP64_PEAK_TFLOPS * 1e12),
     }
 
 
-def cpu_baseline(system, spec, budget_s=25.0):
-    """The oracle as it stands, single-threaded, on a bounded sample."""
+# states of the bounded CPU-oracle sample per workload (about 10-15 s of
+# single-core oracle work: its build of the sample's rows and one sweep of
+# each pass over them)
+CPU_SAMPLE_STATES = {"room5d": 12000, "unicycle3d": 30000, "robot2d": 400}
+
+
+def cpu_worker(job):
+    """Child process of cpu_baseline: the oracle on one shard of the sample.
+
+    Builds the rows of states [s0, s1) and times one sweep of each pass over
+    them (the states outside the shard are labelled unsafe and carry no rows,
+    so every row the oracle solves is a row of the workload).
+    """
     import numpy as np
     import oracle
+    from paper_2401_03555_amd import workloads as W
+    system, spec = getattr(W, job["workload"])()
+    s0, s1 = job["states"]
+    nu = len(system["inputs"])
+    N = int(np.prod(system["n"]))
+    states = np.arange(s0, s1, dtype=np.int64)
+    rows = (states[:, None] * nu + np.arange(nu)[None, :]).ravel()
     t0 = time.perf_counter()
-    m = oracle.build(system, system["k_sigma"])
+    m = oracle.build(system, system["k_sigma"], rows=rows)
     t_build = time.perf_counter() - t0
-    cls = oracle.label(system, spec["target"], spec["avoid"])
+    counts = np.zeros(N * nu, dtype=np.int64)
+    counts[rows] = np.diff(m["row_ptr"])
+    row_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    cls = np.full(N, 2, dtype=np.int8)   # outside the shard: unsafe, never swept
+    cls[states] = 0
     t1 = time.perf_counter()
-    r = oracle.iterate(m["n_states"], m["n_inputs"], m["row_ptr"], m["target"], m["lo"],
-                       m["hi"], cls, spec["kind"], spec["eps"], 1)
-    t_it = time.perf_counter() - t1
+    r = oracle.iterate(N, nu, row_ptr, m["target"], m["lo"], m["hi"], cls, spec["kind"],
+                       spec["eps"], 1)
+    t_sweep = time.perf_counter() - t1
     n_safe = int(r["n_safe"])
-    updates = n_safe * m["n_inputs"] + n_safe  # one sweep of each pass
+    return {"build_s": t_build, "sweep_s": t_sweep, "entries": int(m["row_ptr"][-1]),
+            "updates": n_safe * nu + n_safe}
+
+
+def _run_workers(jobs):
+    """Run cpu_worker jobs in concurrent child processes; (results, wall s)."""
+    import subprocess
+    t0 = time.perf_counter()
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker",
+                               json.dumps(j)], stdout=subprocess.PIPE, text=True) for j in jobs]
+    out = []
+    for p in procs:
+        o, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle worker failed ({p.returncode})")
+        out.append(json.loads(o.strip().splitlines()[-1]))
+    return out, time.perf_counter() - t0
+
+
+def cpu_baseline(workload):
+    """The oracle as it stands on a bounded sample of the workload: one core,
+    then the same sample split over all of the host's cores (at most 16), each
+    shard in its own process."""
+    from paper_2401_03555_amd import workloads as W
+    system, _ = getattr(W, workload)()
+    import numpy as np
+    N = int(np.prod(system["n"]))
+    S = min(N, CPU_SAMPLE_STATES.get(workload, 10000))
+    s0 = (N - S) // 2                      # a block of states from the middle of the grid
+    one, _ = _run_workers([{"workload": workload, "states": [s0, s0 + S]}])
+    one = one[0]
+    host = os.cpu_count() or 1
+    P = max(1, min(16, host))
+    cuts = [s0 + (S * k) // P for k in range(P + 1)]
+    shards, wall = _run_workers([{"workload": workload, "states": [cuts[k], cuts[k + 1]]}
+                                 for k in range(P)])
+    upd = sum(x["updates"] for x in shards)
+    sweep_wall = max(x["sweep_s"] for x in shards)
+    build_wall = max(x["build_s"] for x in shards)
     return {
-        "value": updates / t_it,
+        "value": upd / sweep_wall,
         "unit": "(s,u)-updates/s",
-        "cores": 1,
+        "cores": P,
         "kind": "oracle",
-        "sample": (f"oracle build of all {m['row_ptr'].size - 1} rows "
-                   f"({m['row_ptr'][-1]} entries, {t_build:.1f} s, "
-                   f"{m['row_ptr'][-1] / t_build:.3g} entries/s) then one sweep of each pass "
-                   f"({updates} updates, {t_it:.1f} s)"),
-        "build_entries_per_s": m["row_ptr"][-1] / t_build,
+        "sample": (f"{S} of {N} states ({one['entries']} entries): oracle build of their rows, "
+                   f"then one sweep of each pass over them; single core {one['build_s']:.1f} s "
+                   f"+ {one['sweep_s']:.1f} s, {P} processes {build_wall:.1f} s + "
+                   f"{sweep_wall:.1f} s"),
+        "host_cores": host,
+        "single_core": {"value": one["updates"] / one["sweep_s"], "cores": 1,
+                        "build_entries_per_s": one["entries"] / one["build_s"]},
+        "build_entries_per_s": sum(x["entries"] for x in shards) / build_wall,
     }
 
 
@@ -431,8 +523,130 @@ def measured_peaks(impact, mib=1024, reps=5):
             "fp64_fma_tflops": fp64, "fp64_frac_of_peak": fp64 / 78.6}
 
 
+def sweep_kernel_name(binfo, modes):
+    """The kernel family of the policy-pass sweep for this abstraction."""
+    if binfo["max_row"] > 512:
+        return "k_sweep_sel"
+    if modes[0] in ("state_box", "auto"):
+        return "k_sweep_sb"
+    return "k_sweep"
+
+
+def measure_plain(args, tuner, name, steps, warmup):
+    """Steps of one workload (build + iterate, timed as a whole) and the
+    roofline of its policy-pass sweep from one instrumented step."""
+    import torch
+    from paper_2401_03555_amd import impact
+    system, spec, desc = workload(name)
+    max_sweeps = spec["max_sweeps"]
+    storage, modes, choice = args.storage, (args.sweep_mode, args.sweep_mode), None
+    if "tuned" in (args.storage, args.sweep_mode):
+        # measured per-sweep times, weighted by the sweeps each pass runs on
+        # this query (from one untimed solve under the equal-weight choice)
+        choice = tuner.choose(system)
+        im = impact.build_imdp(system, storage=choice["storage"])
+        im.set_sweep_modes(choice["policy_pass"], choice["fixed_pass"])
+        sw = im.iterate(spec, max_sweeps=max_sweeps)["info"]["sweeps"]
+        im.free()
+        choice = tuner.choose(system, weights=sw)
+        if args.storage == "tuned":
+            storage = choice["storage"]
+        if args.sweep_mode == "tuned":
+            modes = (choice["policy_pass"], choice["fixed_pass"])
+    print(f"# {name}: storage {storage}, sweep modes {modes}", file=sys.stderr, flush=True)
+
+    def step(timing=False):
+        imdp = impact.build_imdp(system, storage=storage, timing=timing)
+        imdp.set_sweep_modes(*modes)
+        r = imdp.iterate(spec, max_sweeps=max_sweeps)
+        return imdp, r
+
+    for _ in range(warmup):
+        imdp, r = step()
+        imdp.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        imdp, r = step()
+        imdp.free()
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / max(1, steps)
+
+    # one instrumented step (HIP events around every sweep launch), outside the timed region
+    imdp, r = step(timing=True)
+    binfo, iinfo = imdp.info(), r["info"]
+    policy = r["policy"].cpu().numpy()
+    d = binfo["dim"]
+    bytes_sweep, cells, rows = algorithmic_bytes(imdp, policy, binfo["n_states"], d)
+    sweeps0, launches0 = iinfo["sweeps"][0], iinfo["launches"][0]
+    avg_launch_ms = iinfo["launch_ms"][0] / max(1, launches0)
+    achieved = bytes_sweep * sweeps0 / max(1, launches0) / (avg_launch_ms * 1e-3) / 1e9
+    updates = sum(iinfo["updates"])
+    kernel = sweep_kernel_name(binfo, modes)
+    st_name = "bounds" if binfo["storage"] != 2 else "factors"
+    out = {
+        "workload": desc,
+        "ms_per_step": ms_per_step,
+        "value": updates / (ms_per_step * 1e-3),
+        "config": {
+            "workload": desc,
+            "storage": storage,
+            "sweep_modes": list(modes),
+            "tuner": choice,
+            "max_row": binfo["max_row"],
+            "max_box": binfo["max_box"],
+            "n_states": binfo["n_states"],
+            "n_inputs": binfo["n_inputs"],
+            "n_entries": binfo["n_entries"],
+            "n_safe": iinfo["n_safe"],
+            "sweeps": list(iinfo["sweeps"]),
+            "converged": list(iinfo["converged"]),
+            "status": r["status"],
+        },
+        "bound_entries_per_s": binfo["n_entries"] / (binfo["build_ms"] * 1e-3),
+        "build_ms": binfo["build_ms"],
+        "iter_updates_per_s": updates / (iinfo["iterate_ms"] * 1e-3),
+        "iterate_ms": iinfo["iterate_ms"],
+        "fixed_pass_launch_ms": iinfo["launch_ms"][1] / max(1, iinfo["launches"][1]),
+        "build_roofline": build_roofline(imdp, d, name),
+        "roofline": {
+            "kernel": kernel + " policy pass (all inputs per SAFE state)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": recorded_traffic(kernel, st_name, name),
+            "bytes_per_sweep": bytes_sweep,
+            "avg_launch_ms": avg_launch_ms,
+            "launches": launches0,
+            "sweeps": sweeps0,
+            # what binds it instead: VALU issue, from the recorded SQ_INSTS_VALU
+            # of this kernel build over the live launch time
+            "valu_issue_frac": (lambda v: None if v is None else
+                                v / (avg_launch_ms * 1e-3) / VALU_ISSUE_PEAK)(
+                recorded_valu(kernel, st_name, name)),
+        },
+    }
+    imdp.free()
+    return out
+
+
+def run_served_leg(args):
+    """The bounded served leg of the default line: a short Poisson trace over
+    the served pool at an arrival rate the GPU sustains, served by the
+    continuous-batching loop and by serial plain solves."""
+    a = argparse.Namespace(**vars(args))
+    a.serve_rate, a.serve_seconds, a.serve_max_sweeps = (args.served_rate, args.served_seconds,
+                                                         args.served_max_sweeps)
+    return run_served(a)
+
+
 def main():
     args = parse()
+    if args.cpu_worker is not None:
+        print(json.dumps(cpu_worker(json.loads(args.cpu_worker))), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
               "is a design note, not built", file=sys.stderr)
@@ -451,109 +665,40 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     tuner = Autotuner(path=args.tune_cache)
-    system, spec, desc = workload(args.workload)
-    max_sweeps = spec["max_sweeps"]
-
-    # schedule choice (untimed)
-    storage, modes, choice = args.storage, (args.sweep_mode, args.sweep_mode), None
-    if "tuned" in (args.storage, args.sweep_mode):
-        choice = tuner.choose(system)
-        if args.storage == "tuned":
-            storage = choice["storage"]
-        if args.sweep_mode == "tuned":
-            modes = (choice["policy_pass"], choice["fixed_pass"])
-    print(f"# plain: storage {storage}, sweep modes {modes}", file=sys.stderr, flush=True)
-
-    def step(timing=False):
-        imdp = impact.build_imdp(system, storage=storage, timing=timing)
-        imdp.set_sweep_modes(*modes)
-        r = imdp.iterate(spec, max_sweeps=max_sweeps)
-        return imdp, r
-
-    for _ in range(args.warmup):
-        imdp, r = step()
-        imdp.free()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        imdp, r = step()
-        imdp.free()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-
-    # one instrumented step (HIP events around every kernel launch), outside the timed region
-    imdp, r = step(timing=True)
-    binfo, iinfo = imdp.info(), r["info"]
-    policy = r["policy"].cpu().numpy()
-    d = binfo["dim"]
-    bytes_sweep, cells, rows = algorithmic_bytes(imdp, policy, binfo["n_states"], d)
-    sweeps0, launches0 = iinfo["sweeps"][0], iinfo["launches"][0]
-    avg_launch_ms = iinfo["launch_ms"][0] / max(1, launches0)
-    achieved = bytes_sweep * sweeps0 / max(1, launches0) / (avg_launch_ms * 1e-3) / 1e9
-    updates = sum(iinfo["updates"])
-    value = updates / (ms_per_step * 1e-3)
-    box = modes[0] in ("state_box", "auto") and binfo["max_row"] <= 512
-
+    head = measure_plain(args, tuner, args.workload, args.steps, args.warmup)
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "(s,u)-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {
-            "workload": desc,
-            "storage": storage,
-            "sweep_modes": list(modes),
-            "tuner": choice,
-            "max_row": binfo["max_row"],
-            "max_box": binfo["max_box"],
-            "n_states": binfo["n_states"],
-            "n_inputs": binfo["n_inputs"],
-            "n_entries": binfo["n_entries"],
-            "n_safe": iinfo["n_safe"],
-            "sweeps": list(iinfo["sweeps"]),
-            "converged": list(iinfo["converged"]),
-            "status": r["status"],
-        },
+        "config": head["config"],
         "components": {
-            "bound_entries_per_s": binfo["n_entries"] / (binfo["build_ms"] * 1e-3),
-            "build_ms": binfo["build_ms"],
-            "iter_updates_per_s": updates / (iinfo["iterate_ms"] * 1e-3),
-            "iterate_ms": iinfo["iterate_ms"],
+            "bound_entries_per_s": head["bound_entries_per_s"],
+            "build_ms": head["build_ms"],
+            "iter_updates_per_s": head["iter_updates_per_s"],
+            "iterate_ms": head["iterate_ms"],
+            "fixed_pass_launch_ms": head["fixed_pass_launch_ms"],
             "served_p99_ms": None,
-            "build_roofline": build_roofline(imdp, d),
+            "build_roofline": head["build_roofline"],
         },
-        "roofline": {
-            "kernel": ("k_sweep_sb" if box else "k_sweep") +
-                      " policy pass (all inputs per SAFE state)",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": recorded_traffic("k_sweep_sb" if box else "k_sweep", storage,
-                                        args.workload),
-            "bytes_per_sweep": bytes_sweep,
-            "avg_launch_ms": avg_launch_ms,
-            "launches": launches0,
-            "sweeps": sweeps0,
-            # what binds it instead: VALU issue, from the recorded SQ_INSTS_VALU
-            # of this kernel build over the live launch time
-            "valu_issue_frac": (lambda v: None if v is None else
-                                v / (avg_launch_ms * 1e-3) / VALU_ISSUE_PEAK)(
-                recorded_valu("k_sweep_sb" if box else "k_sweep", storage, args.workload)),
-        },
+        "roofline": head["roofline"],
     }
-    imdp.free()
+    for name in [c for c in args.components.split(",") if c and c != args.workload]:
+        line["components"][name] = measure_plain(args, tuner, name, max(1, args.steps),
+                                                 max(1, args.warmup))
     line["measured_peaks"] = measured_peaks(impact)
+    if not args.no_served:
+        leg = run_served_leg(args)
+        line["components"]["served"] = leg
+        line["components"]["served_p99_ms"] = leg["served"]["p99_ms"]
     forms = [f for f in args.forms.split(",") if f]
     if forms:
         line["forms"] = {}
@@ -563,9 +708,8 @@ def main():
         line["forms"]["disturbed"] = run_disturbed(args)
     if "served" in forms:
         line["forms"]["served"] = run_served(args)
-        line["components"]["served_p99_ms"] = line["forms"]["served"]["served"]["p99_ms"]
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(system, dict(spec))
+        line["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(line), flush=True)
     return 0
 

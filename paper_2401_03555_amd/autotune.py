@@ -76,45 +76,57 @@ class Autotuner:
         return int(torch.cuda.mem_get_info()[0] * 0.5)
 
     def _time_modes(self, imdp, d):
-        """Mean ms per sweep of each pass under every entry order."""
+        """Mean ms per sweep of each pass under every entry order (rows beyond
+        512 entries sweep by selection whatever the order: one measurement)."""
         imdp.set_timing(True)
         out = {}
-        for mode in MODES:
+        modes = MODES if imdp.info()["max_row"] <= 512 else MODES[:1]
+        for mode in modes:
             imdp.set_sweep_modes(mode, mode)
             imdp.iterate(_probe_spec(d, 1))          # first-use costs out of the timing
             r = imdp.iterate(_probe_spec(d, self.sweeps))
-            out[mode] = tuple(float(x) for x in r["info"]["sweep_ms"])
+            i = r["info"]
+            out[mode] = tuple(float(i["sweep_ms"][p]) / max(1, i["sweeps"][p]) for p in (0, 1))
+        for mode in MODES:
+            out.setdefault(mode, out[modes[0]])
         imdp.set_timing(False)
         return out
 
-    def choose(self, system):
-        """The tuned choice for ``system``: storage and per-pass sweep modes."""
+    def choose(self, system, weights=(1.0, 1.0)):
+        """The tuned choice for ``system``: storage and per-pass sweep modes.
+
+        The measured per-sweep times of the two passes are weighted by
+        ``weights``, the sweeps each pass is expected to run (e.g. the counts
+        of an earlier solve of the same query; equal by default)."""
         probe = impact.build_imdp(system, storage="factors")
         info = probe.info()
         key = imdp_key(info)
-        if key in self.table:
+        cached = key in self.table
+        if cached:
             probe.free()
-            return dict(self.table[key], key=key, cached=True)
-        d = info["dim"]
-        cands = {"factors": self._time_modes(probe, d)}
-        probe.free()
-        if _bounds_bytes(info) <= self._budget():
-            im = impact.build_imdp(system, storage="bounds")
-            cands["bounds"] = self._time_modes(im, d)
-            im.free()
+            measured = self.table[key]["measured"]
+        else:
+            d = info["dim"]
+            cands = {"factors": self._time_modes(probe, d)}
+            probe.free()
+            if _bounds_bytes(info) <= self._budget():
+                im = impact.build_imdp(system, storage="bounds")
+                cands["bounds"] = self._time_modes(im, d)
+                im.free()
+            measured = {s: {m: list(v) for m, v in t.items()} for s, t in cands.items()}
+            self.table[key] = {"measured": measured}
+            self.log.append((key, measured))
+            self._save()
+        w0, w1 = (float(x) for x in weights)
         best = None
-        for storage, t in cands.items():
+        for storage, t in measured.items():
             p1 = min(MODES, key=lambda m: t[m][0])
             p2 = min(MODES, key=lambda m: t[m][1])
-            cost = t[p1][0] + t[p2][1]
-            if best is None or cost < best["ms_per_sweep_pair"]:
-                best = dict(storage=storage, policy_pass=p1, fixed_pass=p2,
-                            ms_per_sweep_pair=cost)
-        best["measured"] = {s: {m: list(v) for m, v in t.items()} for s, t in cands.items()}
-        self.table[key] = best
-        self.log.append((key, best))
-        self._save()
-        return dict(best, key=key, cached=False)
+            cost = w0 * t[p1][0] + w1 * t[p2][1]
+            if best is None or cost < best["weighted_ms"]:
+                best = dict(storage=storage, policy_pass=p1, fixed_pass=p2, weighted_ms=cost,
+                            ms_per_sweep=[t[p1][0], t[p2][1]])
+        return dict(best, weights=[w0, w1], measured=measured, key=key, cached=cached)
 
     def build(self, system, **kw):
         """Build ``system`` with its tuned storage and sweep modes."""

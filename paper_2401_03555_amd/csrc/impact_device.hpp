@@ -13,7 +13,7 @@ namespace impact {
 
 constexpr int kMaxDim = 8;
 constexpr int kMaxRow = 16384;     // longest row (entries incl. OUT / TAIL)
-constexpr int kMaxRowBlock = 4096; // longest row of the engine's workgroup sweep
+constexpr int kMaxRowBlock = 4096; // longest row of the multi-query engine
 constexpr int kMaxFactors = 1024;  // longest per-row factor list (sum of window widths)
 
 constexpr double kRsqrt2 = 0.70710678118654752440;

@@ -59,19 +59,26 @@ struct QueryDesc {
   int32_t max_lp[2];        // LP direction of each pass (1: maximising)
   int32_t upper_first;      // 1: the policy pass yields the upper output (optimistic policy)
   int32_t finite;           // 1: finite horizon (cap sweeps per pass, no stop test)
+  int32_t auto_h;           // 1: the horizon of Remark 5.2 (self-convergence stage, then
+                            // a finite-horizon stage of the larger self sweep count)
   double eps;
   int64_t cap;
   int64_t work_begin, work_end;  // its items in its class's work list
+  double* vs[2];             // rows beyond 512 entries: sort buffers (2 * n_cells each);
+                             // a.vsort is the one the step's last merge pass writes
 };
 
 // Phase machine of one query: 0 policy pass, 1 close pass 1 (write lo and the
 // policy, reset values), 2 fixed-input pass, 3 close pass 2 (write hi), 4 done.
 struct QueryCtrl {
-  int32_t phase, pad;
+  int32_t phase, stage;  // stage: 0, or 1 for the finite-horizon stage of Remark 5.2
   int32_t converged[2];
   int64_t step;       // value-buffer steps applied (ping-pong parity)
   int64_t sweeps[2];
   double gap[2];
+  int64_t horizon;          // Remark 5.2: the finite stage's horizon K
+  int64_t self_sweeps[2];   // Remark 5.2: sweeps until each pass's iterates stopped moving
+  int32_t self_conv[2];     // ... and whether they stopped before the cap
 };
 
 }  // namespace impact
@@ -151,9 +158,21 @@ int rows_g_states_per_block(int32_t max_row);
 hipError_t launch_mq_sweep_row(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
                                const int32_t* ws, int64_t n_items, double* gap_item,
                                int32_t max_row, int32_t d, hipStream_t st);
-hipError_t launch_mq_sweep_block(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
-                                 const int32_t* ws, int64_t n_items, double* gap_item,
-                                 int32_t max_row, hipStream_t st);
+// Queries with rows beyond 512 entries (selection sweep): the value vectors of
+// the listed query slots sorted (qlist in device memory, nq slots, max_cells
+// their largest n_cells; the result lands in vs[p & 1], p =
+// value_sort_passes(max_cells)), then one workgroup per item.
+hipError_t launch_mq_value_sort(const QueryDesc* desc, const QueryCtrl* ctrl,
+                                const int32_t* qlist, int32_t nq, int64_t max_cells,
+                                hipStream_t st);
+hipError_t launch_mq_sweep_sel(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
+                               const int32_t* ws, int64_t n_items, double* gap_item,
+                               int32_t max_row, int32_t d, hipStream_t st);
+// Items of queries in the self-convergence stage of Remark 5.2: gap_item =
+// max(|V0' - V0|, |V1' - V1|) of the item's state over this step's sweep.
+hipError_t launch_mq_self_delta(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
+                                const int32_t* ws, int64_t n_items, double* gap_item,
+                                hipStream_t st);
 // out = the lower (upper = 0) or upper (upper = 1) satisfaction bound of
 // every cell (finite = 1: from the V0 iterate of a finite-horizon pass);
 // policy (may be null) = pi on SAFE cells, -1 elsewhere.

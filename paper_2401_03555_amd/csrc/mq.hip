@@ -46,28 +46,79 @@ __global__ __launch_bounds__(256) void k_mq_finish(const QueryDesc* __restrict__
   }
   if (threadIdx.x != 0) return;
   QueryCtrl& c = ctrl[q];
+  // Remark 5.2: a self-convergence stage (the items' partials are the moves
+  // of the iterates, stop once they are <= eps), then a finite stage whose
+  // horizon is the larger of its two sweep counts
+  const bool self_stage = D.auto_h && c.stage == 0;
+  const bool finite = D.finite || (D.auto_h && c.stage == 1);
+  const double eps = finite ? -1.0 : D.eps;
+  const int64_t cap = (D.auto_h && c.stage == 1) ? c.horizon : D.cap;
   if (phase == 0 || phase == 2) {
     const int pass = phase >> 1;
     c.sweeps[pass] += 1;
     c.gap[pass] = g;
     c.step += 1;
-    if (g <= D.eps) {
+    if (g <= eps) {
       c.converged[pass] = 1;
       c.phase = phase + 1;
-    } else if (c.sweeps[pass] >= D.cap) {
-      c.converged[pass] = D.finite;
+    } else if (c.sweeps[pass] >= cap) {
+      c.converged[pass] = finite;
       c.phase = phase + 1;
     }
   } else if (phase == 1) {
     c.step += 1;
     // the fixed-input pass starts from a gap of 1: it runs no sweep if eps >= 1
-    c.phase = 1.0 <= D.eps ? 3 : 2;
+    // (the self rule and a finite horizon always sweep)
+    const bool skip = !self_stage && 1.0 <= eps;
+    c.phase = skip ? 3 : 2;
     c.gap[1] = 1.0;
-    c.converged[1] = 1.0 <= D.eps;
+    c.converged[1] = skip;
+  } else if (self_stage) {
+    // the close wrote the reset values: the finite stage starts
+    c.step += 1;
+    c.self_sweeps[0] = c.sweeps[0];
+    c.self_sweeps[1] = c.sweeps[1];
+    c.self_conv[0] = c.converged[0];
+    c.self_conv[1] = c.converged[1];
+    const int64_t K = c.sweeps[0] > c.sweeps[1] ? c.sweeps[0] : c.sweeps[1];
+    c.horizon = K > 1 ? K : 1;
+    c.stage = 1;
+    c.sweeps[0] = c.sweeps[1] = 0;
+    c.converged[0] = c.converged[1] = 0;
+    c.gap[0] = c.gap[1] = 1.0;
+    c.phase = 0;
   } else {
     c.phase = 4;
     atomicAdd(done_count, 1);
   }
+}
+
+// Remark 5.2's stop rule: for items of queries in the self-convergence stage,
+// replace the sweep's partial by the state's largest move of either iterate.
+__global__ void k_mq_self_delta(const QueryDesc* __restrict__ desc,
+                                const QueryCtrl* __restrict__ ctrl, const int32_t* __restrict__ wq,
+                                const int32_t* __restrict__ ws, int64_t n_items,
+                                double* __restrict__ gap_item) {
+  const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= n_items) return;
+  const int q = wq[item];
+  const QueryDesc& D = desc[q];
+  const QueryCtrl& c = ctrl[q];
+  if (!D.auto_h || c.stage != 0 || (c.phase != 0 && c.phase != 2)) return;
+  const int64_t s = ws[item];
+  const double2* vin = (c.step & 1) ? D.vb1 : D.vb0;
+  const double2* vout = (c.step & 1) ? D.vb0 : D.vb1;
+  const double2 o = vin[s], n = vout[s];
+  gap_item[item] = fmax(fabs(n.x - o.x), fabs(n.y - o.y));
+}
+
+hipError_t launch_mq_self_delta(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
+                                const int32_t* ws, int64_t n_items, double* gap_item,
+                                hipStream_t st) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mq_self_delta, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, st,
+                     desc, ctrl, wq, ws, n_items, gap_item);
+  return hipGetLastError();
 }
 
 // Work-list fill: segment k copies its query's SAFE list to [dst, dst + n).
@@ -105,9 +156,10 @@ struct MqNoMem {};
 // beyond 512 cells are split into input groups) and the lane-group width of
 // the longest row (16, 32, 64): the policy pass runs the state-box kernel,
 // the fixed-input pass the per-row kernel.  Workgroup classes for rows beyond
-// 512 entries (by the longest row).
+// 512 entries, which run the selection sweep (by grid dimension, 5 or other,
+// and the longest row, up to 2048 or 4096 entries).
 constexpr int kMqBoxClasses = 4 * 4 * 3;
-constexpr int kMqClasses = kMqBoxClasses + 3;
+constexpr int kMqClasses = kMqBoxClasses + 4;
 constexpr int kMqDims[4] = {2, 3, 5, 0};
 
 int elems_for(int64_t n) { return n <= 64 ? 1 : n <= 128 ? 2 : n <= 256 ? 4 : n <= 512 ? 8 : 0; }
@@ -151,6 +203,12 @@ struct impact_mq {
   double* gap = nullptr;
   int64_t cap_items = 0, n_items = 0;
   MqClass cls[kMqClasses];
+  // query slots with rows beyond 512 entries (their value vectors are sorted
+  // every step) and the largest of their grids
+  int32_t* d_long = nullptr;
+  int32_t n_long = 0;
+  int32_t n_auto = 0;  // live queries under Remark 5.2's horizon
+  int64_t long_cells = 0;
   int32_t n_slots_used = 0;
   bool dirty = true;
   // captured chunk of steps
@@ -198,7 +256,7 @@ struct impact_mq {
     for (auto& q : slots)
       for (void* p : q.bufs) release(p);
     for (void* p : {(void*)d_desc, (void*)d_ctrl, (void*)d_done, (void*)wq, (void*)ws,
-                    (void*)gap})
+                    (void*)gap, (void*)d_long})
       release(p);
     if (st) (void)hipStreamDestroy(st);
   }
@@ -249,7 +307,7 @@ int class_of(const MqQuery& q) {
     eb = std::max(eb, gs == 0 ? 1 : gs == 1 ? 2 : 4);  // the box holds a whole row
     return (ds * 4 + elems_slot(eb)) * 3 + gs;
   }
-  return kMqBoxClasses + (q.max_row <= 1024 ? 0 : q.max_row <= 2048 ? 1 : 2);
+  return kMqBoxClasses + (q.d == 5 ? 2 : 0) + (q.max_row <= 2048 ? 0 : 1);
 }
 
 // Rebuild the work list from the live (unfinished) queries, grouped by class.
@@ -272,6 +330,30 @@ void rebuild(impact_mq* m) {
     c.max_box = std::max(c.max_box, q.max_box);
     c.max_row = std::max(c.max_row, q.max_row);
     seg.push_back(S);
+  }
+  // long-row queries: one sort of every one of them per step, over the
+  // largest grid, so that all land in the same buffer of their pair
+  std::vector<int32_t> longs;
+  int64_t long_cells = 0;
+  for (const MqSegment& S : seg)
+    if (S.cls >= kMqBoxClasses) {
+      longs.push_back(S.slot);
+      long_cells = std::max(long_cells, m->slots[S.slot].n_states);
+    }
+  for (int32_t k : longs) {
+    QueryDesc& D = m->h_desc[k];
+    D.a.vsort = D.vs[value_sort_passes(long_cells) & 1];
+  }
+  if (m->d_long) m->release(m->d_long);
+  m->d_long = nullptr;
+  m->n_long = (int32_t)longs.size();
+  m->n_auto = 0;
+  for (const MqSegment& S : seg) m->n_auto += m->h_desc[S.slot].auto_h != 0;
+  m->long_cells = long_cells;
+  if (!longs.empty()) {
+    m->d_long = (int32_t*)m->alloc(sizeof(int32_t) * longs.size());
+    MQ_TRY(hipMemcpyAsync(m->d_long, longs.data(), sizeof(int32_t) * longs.size(),
+                          hipMemcpyHostToDevice, m->st));
   }
   int64_t total = 0;
   for (int c = 0; c < kMqClasses; ++c) {
@@ -311,6 +393,9 @@ void rebuild(impact_mq* m) {
 
 void enqueue_step(impact_mq* m) {
   if (m->n_slots_used == 0) return;
+  if (m->n_long > 0)
+    MQ_TRY(launch_mq_value_sort(m->d_desc, m->d_ctrl, m->d_long, m->n_long, m->long_cells,
+                                m->st));
   for (int c = 0; c < kMqClasses; ++c) {
     const MqClass& k = m->cls[c];
     if (k.n == 0) continue;
@@ -320,10 +405,14 @@ void enqueue_step(impact_mq* m) {
                                 m->gap + k.begin, k.max_box, k.max_row, d, m->st));
       MQ_TRY(launch_mq_sweep_row(m->d_desc, m->d_ctrl, m->wq + k.begin, m->ws + k.begin, k.n,
                                  m->gap + k.begin, k.max_row, d, m->st));
-    } else
-      MQ_TRY(launch_mq_sweep_block(m->d_desc, m->d_ctrl, m->wq + k.begin, m->ws + k.begin, k.n,
-                                   m->gap + k.begin, k.max_row, m->st));
+    } else {
+      MQ_TRY(launch_mq_sweep_sel(m->d_desc, m->d_ctrl, m->wq + k.begin, m->ws + k.begin, k.n,
+                                 m->gap + k.begin, k.max_row, (c - kMqBoxClasses) >= 2 ? 5 : 0,
+                                 m->st));
+    }
   }
+  if (m->n_auto > 0)
+    MQ_TRY(launch_mq_self_delta(m->d_desc, m->d_ctrl, m->wq, m->ws, m->n_items, m->gap, m->st));
   hipLaunchKernelGGL(k_mq_finish, dim3((unsigned)m->n_slots_used), dim3(256), 0, m->st,
                      (const QueryDesc*)m->d_desc, m->d_ctrl, (const double*)m->gap, m->d_done);
   MQ_TRY(hipGetLastError());
@@ -402,9 +491,8 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
   if (spec->pessimistic != 0 && spec->pessimistic != 1)
     return mq_fail(IMPACT_E_INVAL, "pessimistic must be 0 or 1");
   if (spec->max_sweeps < 1) return mq_fail(IMPACT_E_INVAL, "max_sweeps must be >= 1");
-  if (spec->horizon == IMPACT_HORIZON_AUTO)
-    return mq_fail(IMPACT_E_UNSUPPORTED, "IMPACT_HORIZON_AUTO runs through impact_interval_iterate");
-  if (spec->horizon < 0) return mq_fail(IMPACT_E_INVAL, "horizon must be >= 0");
+  if (spec->horizon < IMPACT_HORIZON_AUTO)
+    return mq_fail(IMPACT_E_INVAL, "horizon must be >= 0 or IMPACT_HORIZON_AUTO");
   if (!std::isfinite(eps) || !(eps > 0.0)) return mq_fail(IMPACT_E_INVAL, "eps must be > 0");
   ImdpView v;
   if (imdp_view(h, &v) != IMPACT_OK) return mq_fail(IMPACT_E_INVAL, "bad abstraction handle");
@@ -501,8 +589,18 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
     D.max_lp[0] = spec->pessimistic ? safety : !safety;
     D.max_lp[1] = spec->pessimistic ? !safety : safety;
     D.box_class = v.max_row <= 512;
+    if (!D.box_class) {
+      // selection sweep: two sort buffers of both value components, row hints
+      D.vs[0] = (double*)get(sizeof(double) * 2 * (size_t)std::max<int64_t>(1, N));
+      D.vs[1] = (double*)get(sizeof(double) * 2 * (size_t)std::max<int64_t>(1, N));
+      const int64_t rows = N * v.nu;
+      D.a.hint = (int32_t*)get(sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(1, rows));
+      D.a.n_cells = N;
+      MQ_TRY(launch_fill_i32(D.a.hint, 2 * rows, -1, m->st));
+    }
     // finite horizon: no stop test (gap >= 0 > -1), exactly `horizon` sweeps per pass
     D.finite = spec->horizon > 0;
+    D.auto_h = spec->horizon == IMPACT_HORIZON_AUTO;
     D.eps = D.finite ? -1.0 : eps;
     D.cap = D.finite ? spec->horizon : spec->max_sweeps;
     QueryCtrl c;
@@ -512,8 +610,10 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
       c.phase = 4;  // nothing to iterate: outputs are final
       c.converged[0] = c.converged[1] = 1;
     } else {
-      c.phase = 1.0 <= D.eps ? 1 : 0;
-      c.converged[0] = 1.0 <= D.eps;
+      // the self rule of Remark 5.2 and a finite horizon always sweep
+      const bool skip = !D.auto_h && 1.0 <= D.eps;
+      c.phase = skip ? 1 : 0;
+      c.converged[0] = skip;
     }
     MQ_TRY(hipMemcpyAsync(m->d_ctrl + k, &c, sizeof(c), hipMemcpyHostToDevice, m->st));
     MQ_TRY(hipStreamSynchronize(m->st));
@@ -538,7 +638,7 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
       m->finished_info[q.id] = impact_iter_info{};
       m->finished_info[q.id].n_safe = 0;
       m->finished_info[q.id].converged[0] = m->finished_info[q.id].converged[1] = 1;
-      m->finished_info[q.id].horizon = D.finite ? D.cap : 0;
+      m->finished_info[q.id].horizon = D.finite ? D.cap : (D.auto_h ? 1 : 0);
       m->slots[k].finished = true;
       m->unreported.push_back(q.id);
     } else {
@@ -597,6 +697,15 @@ int impact_mq_poll(impact_mq* m, int32_t* ids, int32_t cap, int32_t* n_out) {
       }
       info.n_safe = q.n_safe;
       info.horizon = m->h_desc[k].finite ? m->h_desc[k].cap : 0;
+      if (m->h_desc[k].auto_h) {
+        // Remark 5.2: the returned run is the finite stage; converged tells
+        // whether each pass's iterates stopped moving before the cap
+        info.horizon = c[k].horizon;
+        for (int p = 0; p < 2; ++p) {
+          info.self_sweeps[p] = c[k].self_sweeps[p];
+          info.converged[p] = c[k].self_conv[p];
+        }
+      }
       m->finished_info[q.id] = info;
       q.finished = true;
       m->unreported.push_back(q.id);

@@ -314,62 +314,6 @@ hipError_t launch_mq_sweep_row(const QueryDesc* desc, const QueryCtrl* ctrl, con
   return hipGetLastError();
 }
 
-// Multi-query workgroup sweep for long rows: one workgroup per (query, SAFE
-// state) item, each query at its own phase and step.
-template <int WAVE_E, int BLOCK_E>
-__global__ __launch_bounds__(kBlock) void k_mq_sweep_block(
-    const QueryDesc* __restrict__ desc, const QueryCtrl* __restrict__ ctrl,
-    const int32_t* __restrict__ wq, const int32_t* __restrict__ ws, int64_t n_items,
-    double* __restrict__ gap_item) {
-  __shared__ BlockLds<BLOCK_E> L;
-  const int64_t item = blockIdx.x;
-  if (item >= n_items) return;
-  const int q = wq[item];
-  const int phase = ctrl[q].phase;
-  const int64_t step = ctrl[q].step;
-  const QueryDesc& D = desc[q];
-  double g = 0.0;
-  if (phase == 0 || phase == 2) {
-    SweepArgs a = D.a;
-    a.vin = (step & 1) ? D.vb1 : D.vb0;
-    a.vout = (step & 1) ? D.vb0 : D.vb1;
-    a.reach = !D.safety;
-    if (phase == 0) {
-      a.pass = 0;
-      a.maximise = D.max_lp[0];
-      g = block_sweep_states<WAVE_E, BLOCK_E, 0, 0>(a, ws + item, 1, L);
-    } else {
-      a.pass = 1;
-      a.maximise = D.max_lp[1];
-      g = block_sweep_states<WAVE_E, BLOCK_E, 1, 0>(a, ws + item, 1, L);
-    }
-  } else if ((phase == 1 || phase == 3) && threadIdx.x == 0) {
-    mq_close_state(D, step, phase, ws[item]);
-  }
-  if (threadIdx.x == 0) gap_item[item] = g;
-}
-
-hipError_t launch_mq_sweep_block(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
-                                 const int32_t* ws, int64_t n_items, double* gap_item,
-                                 int32_t max_row, hipStream_t st) {
-  if (n_items == 0) return hipSuccess;
-  const dim3 g((unsigned)n_items), b(kBlock);
-#define MB(E1, E2) \
-  hipLaunchKernelGGL((k_mq_sweep_block<E1, E2>), g, b, 0, st, desc, ctrl, wq, ws, n_items, gap_item)
-  if (max_row <= 512)
-    MB(8, 0);
-  else if (max_row <= 1024)
-    MB(8, 4);
-  else if (max_row <= 2048)
-    MB(8, 8);
-  else if (max_row <= kMaxRowBlock)
-    MB(8, 16);
-  else
-    return hipErrorInvalidValue;
-#undef MB
-  return hipGetLastError();
-}
-
 // Close one sweep: reduce the workgroups' gap partials, count the sweep, stop
 // on eps or the cap.
 __global__ __launch_bounds__(1024) void k_finish(Ctrl* c, const double* __restrict__ part,

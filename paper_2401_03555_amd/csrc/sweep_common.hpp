@@ -554,18 +554,20 @@ __device__ __forceinline__ double bound_of(double2 V, bool upper, bool safety, b
 
 // Engine: close a pass for one state of a query (phase 1: the policy pass's
 // bound, the policy and the reset of the values for the fixed-input pass;
-// phase 3: the other bound).
-__device__ __forceinline__ void mq_close_state(const QueryDesc& D, int64_t step, int phase,
+// phase 3: the other bound, and under Remark 5.2's horizon at the end of the
+// self-convergence stage the reset of the values for the finite stage).
+__device__ __forceinline__ void mq_close_state(const QueryDesc& D, const QueryCtrl& c, int phase,
                                                int64_t s) {
+  const int64_t step = c.step;
+  const bool self_stage = D.auto_h && c.stage == 0;
+  const bool finite = D.finite || (D.auto_h && c.stage == 1);
   const double2* vin = (step & 1) ? D.vb1 : D.vb0;
   double2* vout = (step & 1) ? D.vb0 : D.vb1;
   const double2 V = vin[s];
   const bool upper = (phase == 1) == (D.upper_first != 0);
-  (upper ? D.hi : D.lo)[s] = bound_of(V, upper, D.safety != 0, D.finite != 0);
-  if (phase == 1) {
-    D.pol[s] = D.a.pi[s];
-    vout[s] = make_double2(0.0, 1.0);
-  }
+  (upper ? D.hi : D.lo)[s] = bound_of(V, upper, D.safety != 0, finite);
+  if (phase == 1) D.pol[s] = D.a.pi[s];
+  if (phase == 1 || self_stage) vout[s] = make_double2(0.0, 1.0);
 }
 
 }  // namespace impact

@@ -995,7 +995,7 @@ __global__ __launch_bounds__(64 * kSbWaves) void k_mq_sweep_sb(
     a.maximise = D.max_lp[0];
     g = sb_sweep_state<ESB, GW, 0, DIM>(a, s, lane, lds[wv]);
   } else if ((phase == 1 || phase == 3) && lane == 0) {
-    mq_close_state(D, step, phase, s);
+    mq_close_state(D, ctrl[q], phase, s);
   }
   if (lane == 0) gap_item[item] = g;
 }

@@ -491,16 +491,14 @@ __device__ void sel_row(const SweepArgs& a, int64_t row, int tid, SelLds<NW>& L,
   q1 = base1 + sg * (ql[1] + (r1 - fl[1]) * tc[1]);
 }
 
-// PASS 0: all inputs (policy pass); PASS 1: the input fixed by the policy.
-// With a disturbance player (nw > 1) every (state, input) has nw rows and is
-// valued by its worst one (eq. (5.1)).
+// One SAFE state s: its rows (all inputs in the policy pass, PASS 0; the
+// policy's input in the fixed-input pass, PASS 1) solved one after another by
+// the workgroup; writes vout[s] (and pi[s] in the policy pass) and returns
+// the state's V1 - V0 on every thread.  With a disturbance player (nw > 1)
+// every (state, input) has nw rows and is valued by its worst one (eq. (5.1)).
 template <int NW, int E, int PASS, int D>
-__global__ __launch_bounds__(64 * NW) void k_sweep_sel(SweepArgs a) {
-  if (a.ctrl->done) return;
-  __shared__ SelLds<NW> L;
+__device__ double sel_state(const SweepArgs& a, int64_t s, SelLds<NW>& L) {
   const int tid = threadIdx.x;
-  const int64_t si = blockIdx.x;
-  const int64_t s = a.safe[si];
   const int U = PASS == 0 ? a.nu : 1;
   const int NWD = a.nw > 1 ? a.nw : 1;
   int par = 0;
@@ -514,32 +512,43 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_sel(SweepArgs a) {
       L.qb1[m] = q1;
     }
   }
-  if (tid == 0) {
-    // an input is worth its worst row over the disturbances: the minimum for
-    // reach, the maximum of the bad mass for safety
-    auto worst = [&](const double* q, int ui) {
-      double v = q[ui * NWD];
-      for (int w = 1; w < NWD; ++w) {
-        const double x = q[ui * NWD + w];
-        v = a.reach ? fmin(v, x) : fmax(v, x);
-      }
-      return v;
-    };
-    double b0 = worst(L.qb0, 0), b1 = worst(L.qb1, 0);
-    int arg = 0;
-    for (int ui = 1; ui < U; ++ui) {
-      const double q0 = worst(L.qb0, ui), q1 = worst(L.qb1, ui);
-      if (a.reach ? (q0 > b0) : (q0 < b0)) {
-        b0 = q0;
-        arg = ui;
-      }
-      if (a.reach ? (q1 > b1) : (q1 < b1)) b1 = q1;
+  __syncthreads();
+  // an input is worth its worst row over the disturbances: the minimum for
+  // reach, the maximum of the bad mass for safety
+  auto worst = [&](const double* q, int ui) {
+    double v = q[ui * NWD];
+    for (int w = 1; w < NWD; ++w) {
+      const double x = q[ui * NWD + w];
+      v = a.reach ? fmin(v, x) : fmax(v, x);
     }
+    return v;
+  };
+  double b0 = worst(L.qb0, 0), b1 = worst(L.qb1, 0);
+  int arg = 0;
+  for (int ui = 1; ui < U; ++ui) {
+    const double q0 = worst(L.qb0, ui), q1 = worst(L.qb1, ui);
+    if (a.reach ? (q0 > b0) : (q0 < b0)) {
+      b0 = q0;
+      arg = ui;
+    }
+    if (a.reach ? (q1 > b1) : (q1 < b1)) b1 = q1;
+  }
+  __syncthreads();  // every thread has read qb before the next state writes it
+  if (tid == 0) {
     a.vout[s] = make_double2(b0, b1);
     if (PASS == 0) a.pi[s] = arg;
-    const double g = b1 - b0;
-    a.gap_part[si] = g > 0.0 ? g : 0.0;
   }
+  const double g = b1 - b0;
+  return g > 0.0 ? g : 0.0;
+}
+
+template <int NW, int E, int PASS, int D>
+__global__ __launch_bounds__(64 * NW) void k_sweep_sel(SweepArgs a) {
+  if (a.ctrl->done) return;
+  __shared__ SelLds<NW> L;
+  const int64_t si = blockIdx.x;
+  const double g = sel_state<NW, E, PASS, D>(a, a.safe[si], L);
+  if (threadIdx.x == 0) a.gap_part[si] = g;
 }
 
 template <int PASS, int D>
@@ -572,6 +581,172 @@ hipError_t launch_sweep_sel(const SweepArgs& a, int32_t max_row, hipStream_t st)
   if ((int64_t)a.nu * (a.nw > 1 ? a.nw : 1) > kMaxItems || !a.vsort || !a.hint)
     return hipErrorInvalidValue;
   return a.pass == 0 ? launch_sel_p<0>(a, max_row, st) : launch_sel_p<1>(a, max_row, st);
+}
+
+// ---- multi-query engine: queries whose rows exceed 512 entries ------------
+
+// The value vector of every listed query in a sweeping phase, both components
+// signed by the LP direction of its current pass, chunk-sorted into its
+// buffer vs[0] (queries in a closing or finished phase skip).
+__global__ __launch_bounds__(256) void k_mq_vsort_chunk(const QueryDesc* __restrict__ desc,
+                                                        const QueryCtrl* __restrict__ ctrl,
+                                                        const int32_t* __restrict__ qlist) {
+  __shared__ double s[kSortChunk];
+  const int q = qlist[blockIdx.y >> 1], vec = blockIdx.y & 1;
+  const int phase = ctrl[q].phase;
+  if (phase != 0 && phase != 2) return;
+  const QueryDesc& D = desc[q];
+  const int64_t n = D.a.n_cells;
+  const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+  if (base >= n) return;
+  const double2* vin = (ctrl[q].step & 1) ? D.vb1 : D.vb0;
+  const double sg = D.max_lp[phase >> 1] ? -1.0 : 1.0;
+  for (int i = threadIdx.x; i < kSortChunk; i += 256) {
+    const int64_t g = base + i;
+    double v = __builtin_inf();
+    if (g < n) {
+      const double2 x = vin[g];
+      v = sg * (vec ? x.y : x.x) + 0.0;
+    }
+    s[i] = v;
+  }
+  __syncthreads();
+  for (int k = 2; k <= kSortChunk; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < kSortChunk / 2; i += 256) {
+        const int lo = 2 * i - (i & (j - 1)), hi = lo + j;
+        const bool asc = (lo & k) == 0;
+        const double x = s[lo], y = s[hi];
+        if ((x > y) == asc) {
+          s[lo] = y;
+          s[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  double* out = D.vs[0] + vec * n;
+  for (int i = threadIdx.x; i < kSortChunk; i += 256) {
+    const int64_t g = base + i;
+    if (g < n) out[g] = s[i];
+  }
+}
+
+// One merge pass (runs of L into 2L) of every listed sweeping query, from
+// vs[from] to vs[1 - from]; a query whose value vector is no longer than L
+// is copied.
+__global__ __launch_bounds__(256) void k_mq_vsort_merge(const QueryDesc* __restrict__ desc,
+                                                        const QueryCtrl* __restrict__ ctrl,
+                                                        const int32_t* __restrict__ qlist,
+                                                        int64_t L, int from) {
+  const int q = qlist[blockIdx.y >> 1], vec = blockIdx.y & 1;
+  const int phase = ctrl[q].phase;
+  if (phase != 0 && phase != 2) return;
+  const QueryDesc& D = desc[q];
+  const int64_t n = D.a.n_cells;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double* src = D.vs[from] + vec * n;
+  double* dst = D.vs[1 - from] + vec * n;
+  const int64_t start = (i / (2 * L)) * (2 * L);
+  const int64_t mid = start + L < n ? start + L : n;
+  const int64_t end = start + 2 * L < n ? start + 2 * L : n;
+  const double key = src[i];
+  int64_t pos;
+  if (i < mid) {
+    int64_t lo = mid, hi = end;
+    while (lo < hi) {
+      const int64_t m = (lo + hi) >> 1;
+      if (src[m] < key)
+        lo = m + 1;
+      else
+        hi = m;
+    }
+    pos = i + (lo - mid);
+  } else {
+    int64_t lo = start, hi = mid;
+    while (lo < hi) {
+      const int64_t m = (lo + hi) >> 1;
+      if (src[m] <= key)
+        lo = m + 1;
+      else
+        hi = m;
+    }
+    pos = (i - mid) + lo;
+  }
+  dst[pos] = key;
+}
+
+hipError_t launch_mq_value_sort(const QueryDesc* desc, const QueryCtrl* ctrl,
+                                const int32_t* qlist, int32_t nq, int64_t max_cells,
+                                hipStream_t st) {
+  if (nq == 0 || max_cells == 0) return hipSuccess;
+  const unsigned chunks = (unsigned)((max_cells + kSortChunk - 1) / kSortChunk);
+  hipLaunchKernelGGL(k_mq_vsort_chunk, dim3(chunks, 2 * nq), dim3(256), 0, st, desc, ctrl, qlist);
+  int from = 0;
+  for (int64_t L = kSortChunk; L < max_cells; L <<= 1) {
+    hipLaunchKernelGGL(k_mq_vsort_merge, dim3((unsigned)((max_cells + 255) / 256), 2 * nq),
+                       dim3(256), 0, st, desc, ctrl, qlist, L, from);
+    from ^= 1;
+  }
+  return hipGetLastError();
+}
+
+// One workgroup per (query, SAFE state) item of the long-row queries, each
+// query at its own phase and step: a sweep of the state (phases 0 and 2) or
+// the close of a pass (phases 1 and 3).
+template <int NW, int E, int D>
+__global__ __launch_bounds__(64 * NW) void k_mq_sweep_sel(
+    const QueryDesc* __restrict__ desc, const QueryCtrl* __restrict__ ctrl,
+    const int32_t* __restrict__ wq, const int32_t* __restrict__ ws, int64_t n_items,
+    double* __restrict__ gap_item) {
+  __shared__ SelLds<NW> L;
+  const int64_t item = blockIdx.x;
+  if (item >= n_items) return;
+  const int q = wq[item];
+  const int phase = ctrl[q].phase;
+  const int64_t step = ctrl[q].step;
+  const QueryDesc& Dq = desc[q];
+  double g = 0.0;
+  if (phase == 0 || phase == 2) {
+    SweepArgs a = Dq.a;
+    a.vin = (step & 1) ? Dq.vb1 : Dq.vb0;
+    a.vout = (step & 1) ? Dq.vb0 : Dq.vb1;
+    a.reach = !Dq.safety;
+    a.pass = phase >> 1;
+    a.maximise = Dq.max_lp[phase >> 1];
+    if (phase == 0)
+      g = sel_state<NW, E, 0, D>(a, ws[item], L);
+    else
+      g = sel_state<NW, E, 1, D>(a, ws[item], L);
+  } else if ((phase == 1 || phase == 3) && threadIdx.x == 0) {
+    mq_close_state(Dq, ctrl[q], phase, ws[item]);
+  }
+  if (threadIdx.x == 0) gap_item[item] = g;
+}
+
+template <int D>
+static hipError_t launch_mq_sel_d(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
+                                  const int32_t* ws, int64_t n_items, double* gap_item,
+                                  int32_t max_row, hipStream_t st) {
+  const dim3 g((unsigned)n_items);
+  if (max_row <= 256 * 8)
+    hipLaunchKernelGGL((k_mq_sweep_sel<4, 8, D>), g, dim3(256), 0, st, desc, ctrl, wq, ws,
+                       n_items, gap_item);
+  else if (max_row <= 256 * 16)
+    hipLaunchKernelGGL((k_mq_sweep_sel<4, 16, D>), g, dim3(256), 0, st, desc, ctrl, wq, ws,
+                       n_items, gap_item);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_mq_sweep_sel(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
+                               const int32_t* ws, int64_t n_items, double* gap_item,
+                               int32_t max_row, int32_t d, hipStream_t st) {
+  if (n_items == 0) return hipSuccess;
+  return d == 5 ? launch_mq_sel_d<5>(desc, ctrl, wq, ws, n_items, gap_item, max_row, st)
+                : launch_mq_sel_d<0>(desc, ctrl, wq, ws, n_items, gap_item, max_row, st);
 }
 
 }  // namespace impact

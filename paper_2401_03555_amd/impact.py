@@ -442,7 +442,8 @@ class Engine:
                              status=0 if (i.converged[0] and i.converged[1]) else 1,
                              info=dict(sweeps=tuple(i.sweeps), gap=tuple(i.gap),
                                        converged=tuple(i.converged), n_safe=i.n_safe,
-                                       updates=tuple(i.updates), horizon=i.horizon)))
+                                       updates=tuple(i.updates), horizon=i.horizon,
+                                       self_sweeps=tuple(i.self_sweeps))))
         return done
 
     def run_all(self, chunk=64):

@@ -184,12 +184,16 @@ def _aligned_box(rng, system):
             [float(lb[i] + (start[i] + span[i]) * w[i]) for i in range(len(n))]]
 
 
-def served_trace(pool, rate=200.0, duration=2.0, seed=SEED + 2, max_sweeps=2000):
+def served_trace(pool, rate=200.0, duration=2.0, seed=SEED + 2, max_sweeps=2000,
+                 horizon="auto"):
     """Poisson arrivals at ``rate`` per second over ``duration`` seconds.
 
     Each request names a pool system (uniformly), a specification kind in
     {safety, reach, reach_avoid} (uniformly), grid-aligned random boxes (up to
-    a quarter of the cells per dimension) and eps in {1e-6, 1e-8}.
+    a quarter of the cells per dimension) and eps in {1e-6, 1e-8}; ``horizon``
+    is the specification's horizon field ("auto" by default: the horizon at
+    which each pass's iterates converge to themselves, the paper's remedy for
+    queries whose two bounds need not meet; 0 for the plain infinite horizon).
     """
     rng = np.random.default_rng(seed)
     keys = sorted(pool)
@@ -204,7 +208,8 @@ def served_trace(pool, rate=200.0, duration=2.0, seed=SEED + 2, max_sweeps=2000)
         avoid = [_aligned_box(rng, pool[key])] if kind != "reach" else []
         eps = (1e-6, 1e-8)[int(rng.integers(2))]
         trace.append(dict(t=t, key=key, spec=dict(kind=kind, target=target, avoid=avoid,
-                                                   eps=eps, max_sweeps=max_sweeps)))
+                                                   eps=eps, max_sweeps=max_sweeps,
+                                                   horizon=horizon)))
 
 
 CONFIGS = {

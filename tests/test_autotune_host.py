@@ -38,11 +38,19 @@ def test_cached_choice_skips_measurement(monkeypatch, tmp_path):
     monkeypatch.setattr(A.impact, "build_imdp", lambda system, storage="bounds": Probe())
     path = tmp_path / "tune.json"
     key = A.imdp_key(_info())
-    path.write_text(json.dumps({key: dict(storage="factors", policy_pass="state_box",
-                                          fixed_pass="per_row", ms_per_sweep_pair=1.0)}))
+    # measured per-sweep ms of (policy pass, fixed pass) per storage and entry order
+    measured = {"factors": {"state_box": [1.0, 0.5], "per_row": [3.0, 0.2]},
+                "bounds": {"state_box": [0.9, 0.6], "per_row": [2.0, 0.3]}}
+    path.write_text(json.dumps({key: {"measured": measured}}))
     t = A.Autotuner(path=str(path))
     c = t.choose({"n": [2, 2, 2]})
-    assert c["cached"] and c["storage"] == "factors" and c["fixed_pass"] == "per_row"
+    assert c["cached"] and c["policy_pass"] == "state_box" and c["fixed_pass"] == "per_row"
+    # equal weights: factors 1.0 + 0.2 = 1.2 beats bounds 0.9 + 0.3 = 1.2 only on ties; a
+    # policy pass that runs ten times as many sweeps favours bounds (9.3 < 10.2)
+    assert t.choose({"n": [2, 2, 2]}, weights=(10, 1))["storage"] == "bounds"
+    # a fixed pass that runs ten times as many sweeps favours factors (3.0 < 3.9)
+    c = t.choose({"n": [2, 2, 2]}, weights=(1, 10))
+    assert c["storage"] == "factors" and abs(c["weighted_ms"] - 3.0) < 1e-12
 
 
 def test_sample_takes_largest_and_seeded_rest():

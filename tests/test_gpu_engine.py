@@ -3,10 +3,9 @@
 A query run by the engine must equal the same query run alone by
 impact_interval_iterate with the same sweep kernels (bitwise: the engine runs
 the state-box kernel for the policy pass and the per-row kernel for the
-fixed-input pass; rows longer than 512 entries, which the two sweep
-differently, are held to the oracle), must not depend on which other queries
-share its launches (bitwise), and must match the CPU oracle at the parity
-tolerances.
+fixed-input pass, and the selection sweep for rows beyond 512 entries), must
+not depend on which other queries share its launches (bitwise), and must match
+the CPU oracle at the parity tolerances.
 """
 import numpy as np
 import pytest
@@ -42,53 +41,12 @@ def _same(a, b, label):
     assert tuple(a["info"]["sweeps"]) == tuple(b["info"]["sweeps"]), label
 
 
-def _same_or_oracle(eng_res, plain, name, system, spec):
-    """Bitwise equal to the plain solve when both run the same sweep kernels;
-    for rows longer than 512 entries the plain solve runs the selection sweep
-    and the engine its workgroup sort, so both are held to the oracle instead
-    (values within 1e-9, policies equal up to ties, the same sweep counts)."""
-    if name != "long_rows":
-        _same(eng_res, plain, name)
-        return
-    ref = oracle.solve(system, system["k_sigma"], spec["kind"], spec["target"], spec["avoid"],
-                       spec["eps"], spec["max_sweeps"], want_q0=True,
-                       optimistic=not spec.get("pessimistic", True),
-                       horizon=spec.get("horizon", 0))
-    reach = spec["kind"] != "safety"
-    optimistic = not spec.get("pessimistic", True)
-    kp, kf = ("hi", "lo") if optimistic else ("lo", "hi")
-    m, cls = ref["imdp"], ref["cls"]
-    for r, label in ((eng_res, "engine"), (plain, "plain")):
-        lo, hi, pol = _np(r)
-        got = dict(lo=lo, hi=hi)
-        assert np.abs(got[kp] - ref[kp]).max() <= 1e-9, f"{name} {label} {kp}"
-        assert r["info"]["sweeps"][0] == ref["sweeps"][0], f"{name} {label} sweeps"
-        safe = cls == 0
-        for s_ in np.where(safe & (pol != ref["policy"]))[0]:
-            q = ref["q0"][s_]
-            ok = q[pol[s_]] >= q.max() - 1e-12 if reach else q[pol[s_]] <= q.min() + 1e-12
-            assert ok, f"{name} {label}: policy at {s_} is not a tie"
-        fixed = ref
-        if not np.array_equal(pol, ref["policy"]):
-            # the fixed-input pass of the interval Markov chain the policy induces
-            N, U = m["n_states"], m["n_inputs"]
-            rows = np.arange(N) * U + np.maximum(pol, 0)
-            rp = m["row_ptr"]
-            idx = np.concatenate([np.arange(rp[k], rp[k + 1]) for k in rows])
-            new_rp = np.concatenate([[0], np.cumsum(rp[rows + 1] - rp[rows])]).astype(np.int64)
-            fixed = oracle.iterate(N, 1, new_rp, m["target"][idx], m["lo"][idx], m["hi"][idx],
-                                   cls, spec["kind"], spec["eps"], spec["max_sweeps"],
-                                   optimistic=optimistic, horizon=spec.get("horizon", 0))
-        assert np.abs(got[kf] - fixed[kf]).max() <= 1e-9, f"{name} {label} {kf}"
-        assert r["info"]["sweeps"][1] == fixed["sweeps"][1], f"{name} {label} sweeps"
-
-
 def _affine2():
     return W.tiny_affine(d=2, n=9, seed=2)
 
 
 def _long_rows():
-    # dense 2D rows of 26 x 26 + 1 = 677 entries: the workgroup kernel class
+    # dense 2D rows of 26 x 26 + 1 = 677 entries: the selection-sweep class
     return dict(kind="affine", A=np.eye(2) * 0.8, B=np.eye(2) * 0.5, c=np.zeros(2),
                 lb=[-2.0, -2.0], ub=[2.0, 2.0], n=[26, 26], inputs=[[0.5, 0.0], [0.0, 0.5]],
                 sigma=[0.3, 0.3], k_sigma=0.0)
@@ -124,7 +82,7 @@ def test_engine_query_equals_plain_iterate(I, name, make, spec, pessimistic):
     qid = eng.submit(imdp, spec)
     res = eng.run_all()
     assert set(res) == {qid}
-    _same_or_oracle(res[qid], plain, name, system, spec)
+    _same(res[qid], plain, name)
     assert res[qid]["status"] == plain["status"]
 
 
@@ -222,7 +180,57 @@ def test_engine_finite_horizon_equals_plain_iterate(I, pessimistic):
     eng = I.Engine(max_queries=len(CASES))
     ids = [eng.submit(im, sp) for im, sp in zip(imdps, specs)]
     res = eng.run_all()
-    for qid, p, (name, make, _), sp in zip(ids, plain, CASES, specs):
-        _same_or_oracle(res[qid], p, name, make(), sp)
+    for qid, p, (name, _, _), sp in zip(ids, plain, CASES, specs):
+        _same(res[qid], p, f"{name} T={sp['horizon']}")
         assert res[qid]["status"] == p["status"] == 0
         assert tuple(res[qid]["info"]["sweeps"]) == (sp["horizon"], sp["horizon"])
+
+
+@pytest.mark.parametrize("pessimistic", [True, False], ids=["pess", "opt"])
+def test_engine_auto_horizon_equals_plain_iterate(I, pessimistic):
+    # Remark 5.2 in the engine: a self-convergence stage, then the finite
+    # stage of the larger sweep count, the same run as the single-query call
+    imdps, specs = [], []
+    for name, make, spec in CASES:
+        imdps.append(_engine_modes(I.build_imdp(make())))
+        specs.append(dict(spec, horizon="auto", pessimistic=pessimistic))
+    plain = [im.iterate(sp) for im, sp in zip(imdps, specs)]
+    eng = I.Engine(max_queries=len(CASES))
+    ids = [eng.submit(im, sp) for im, sp in zip(imdps, specs)]
+    res = eng.run_all()
+    for qid, p, (name, _, _) in zip(ids, plain, CASES):
+        _same(res[qid], p, f"{name} auto")
+        assert res[qid]["status"] == p["status"]
+        assert res[qid]["info"]["horizon"] == p["info"]["horizon"]
+        assert tuple(res[qid]["info"]["self_sweeps"]) == tuple(p["info"]["self_sweeps"])
+
+
+def test_engine_auto_horizon_matches_oracle(I):
+    rng = np.random.default_rng(17)
+    insts = []
+    while len(insts) < 4:
+        system, spec = W.random_linear(rng, d=2)
+        if np.prod(system["n"]) <= 900:
+            insts.append((system, dict(spec, horizon="auto", max_sweeps=3000)))
+    views = I.build_imdp_batch([s for s, _ in insts], storage="factors")
+    eng = I.Engine(max_queries=8)
+    ids = [eng.submit(v, spec) for v, (_, spec) in zip(views, insts)]
+    res = eng.run_all()
+    for qid, (system, spec) in zip(ids, insts):
+        m = oracle.build(system, system["k_sigma"])
+        cls = oracle.label(system, spec["target"], spec["avoid"])
+        ref = oracle.iterate_auto_horizon(m["n_states"], m["n_inputs"], m["row_ptr"],
+                                          m["target"], m["lo"], m["hi"], cls, spec["kind"],
+                                          spec["eps"], spec["max_sweeps"], want_q0=True)
+        r = res[qid]
+        lo, hi, pol = _np(r)
+        assert tuple(r["info"]["self_sweeps"]) == tuple(ref["self_sweeps"])
+        assert r["info"]["horizon"] == ref["horizon"]
+        assert np.abs(lo - ref["lo"]).max() <= 1e-9
+        safe = cls == 0
+        diff = np.where(safe & (pol != ref["policy"]))[0]
+        for s_ in diff:
+            q = ref["q0"][s_]
+            assert q[pol[s_]] >= q.max() - 1e-12
+        if len(diff) == 0:
+            assert np.abs(hi - ref["hi"]).max() <= 1e-9

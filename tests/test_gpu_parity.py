@@ -660,13 +660,6 @@ def test_auto_horizon_matches_oracle(I, name, pessimistic):
                  spec=dict(spec, horizon=ro["horizon"]), optimistic=not pessimistic)
 
 
-def test_auto_horizon_is_rejected_by_the_engine(I):
-    imdp = I.build_imdp(SMALL_SYSTEMS["affine2_window"]())
-    eng = I.Engine(max_queries=2)
-    with pytest.raises(I.ImpactError, match="IMPACT_HORIZON_AUTO"):
-        eng.submit(imdp, dict(SPECS["affine2_window"], eps=1e-8, max_sweeps=10, horizon="auto"))
-
-
 # ---------------------------------------------------------------------------
 # disturbance player (eq. (5.1)): rows (s, u, w), worst over w, best over u
 # ---------------------------------------------------------------------------

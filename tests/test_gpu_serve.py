@@ -96,8 +96,70 @@ def test_served_matches_serial_plain_solves(S):
         la, ha, pa = _np(a)
         lb, hb, pb = _np(b)
         assert np.abs(la - lb).max() <= 1e-9 and np.abs(ha - hb).max() <= 1e-9
+        # the engine and the plain call run the same sweep kernels
+        assert np.array_equal(pa, pb)
         assert a["status"] == b["status"]
     st = serve.latency_stats(done, 1.0)
     assert st["n"] == len(trace) and st["p50_ms"] <= st["p99_ms"]
+    srv.free()
+    cache.clear()
+
+
+def _oracle_run(system, spec):
+    import oracle
+    m = oracle.build(system, system["k_sigma"])
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    args = (m["n_states"], m["n_inputs"], m["row_ptr"], m["target"], m["lo"], m["hi"], cls,
+            spec["kind"], spec["eps"], spec["max_sweeps"])
+    if spec.get("horizon") == "auto":
+        ref = oracle.iterate_auto_horizon(*args, want_q0=True)
+    else:
+        ref = oracle.iterate(*args, want_q0=True)
+    return m, cls, ref
+
+
+@pytest.mark.parametrize("horizon", [0, "auto"], ids=["infinite", "auto"])
+def test_served_results_match_oracle(S, horizon):
+    # every served result against the CPU oracle: values within 1e-9, sweep
+    # counts equal, policies equal up to ties (an input whose oracle value is
+    # within 1e-12 of the optimum), the fixed-input pass checked under the
+    # served policy where the two differ at ties
+    import oracle
+    impact, serve = S
+    pool = _pool()
+    trace = W.served_trace(pool, rate=2000.0, duration=1.0, seed=21, max_sweeps=80,
+                           horizon=horizon)[:10]
+    cache = serve.AbstractionCache(pool, 1 << 34)
+    srv = serve.Server(cache, max_active=4, steps=8)
+    done, _ = srv.run(trace, keep_outputs=True)
+    for d, req in zip(done, trace):
+        spec = req["spec"]
+        system = pool[req["key"]]
+        m, cls, ref = _oracle_run(system, spec)
+        lo, hi, pol = _np(d)
+        label = f"request {d['idx']} ({req['key']}, {spec['kind']}, eps {spec['eps']})"
+        reach = spec["kind"] != "safety"
+        assert tuple(d["info"]["sweeps"])[0] == ref["sweeps"][0], label
+        assert np.abs(lo - ref["lo"]).max() <= 1e-9, label
+        safe = cls == 0
+        diff = np.where(safe & (pol != ref["policy"]))[0]
+        for s_ in diff:
+            q = ref["q0"][s_]
+            ok = q[pol[s_]] >= q.max() - 1e-12 if reach else q[pol[s_]] <= q.min() + 1e-12
+            assert ok, f"{label}: policy at {s_} is not a tie"
+        if len(diff) == 0:
+            fixed = ref
+        else:
+            N, U = m["n_states"], m["n_inputs"]
+            rows = np.arange(N) * U + np.maximum(pol, 0)
+            rp = m["row_ptr"]
+            idx = np.concatenate([np.arange(rp[k], rp[k + 1]) for k in rows])
+            new_rp = np.concatenate([[0], np.cumsum(rp[rows + 1] - rp[rows])]).astype(np.int64)
+            h = ref.get("horizon", 0) if spec.get("horizon") == "auto" else 0
+            fixed = oracle.iterate(N, 1, new_rp, m["target"][idx], m["lo"][idx], m["hi"][idx],
+                                   cls, spec["kind"], spec["eps"], spec["max_sweeps"], horizon=h)
+        assert np.abs(hi - fixed["hi"]).max() <= 1e-9, label
+        if spec.get("horizon") == "auto":
+            assert d["info"]["horizon"] == ref["horizon"], label
     srv.free()
     cache.clear()
