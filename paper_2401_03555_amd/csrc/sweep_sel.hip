@@ -145,18 +145,24 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
+constexpr int kTail = 128;  // candidates left for the one-wavefront sort of the search
+
 template <int NW>
 struct SelLds {
-  double red[2][NW][6];        // block sums, double-buffered
+  double red[2][NW][12];       // block sums, double-buffered
   double2 fac[kMaxFactors];    // the row's factors (FACTORS storage)
   double qb0[kMaxItems], qb1[kMaxItems];
   int32_t hit[2];              // a cell holding the critical value, per vector
+  double cx[2][kTail], cw[2][kTail];  // gathered candidates (signed value, width)
+  int32_t tcnt[2][NW];         // candidates per wavefront
+  double tres[2];              // critical value found by the candidate sort
 };
 
 // Sums over the workgroup of K per-thread values, the same on every thread
 // (wavefront butterflies, then the wavefronts' partials in a fixed order).
 template <int NW, int K>
 __device__ __forceinline__ void block_sums(double (&x)[K], SelLds<NW>& L, int tid, int& par) {
+  static_assert(K <= 12, "block_sums holds at most 12 values per wavefront");
 #pragma unroll
   for (int k = 0; k < K; ++k) x[k] = wave_sum(x[k]);
   if (NW == 1) {
@@ -180,19 +186,68 @@ __device__ __forceinline__ void block_sums(double (&x)[K], SelLds<NW>& L, int ti
   par ^= 1;
 }
 
-// Critical values of both vectors of one row (signed values x0, x1 and widths
-// w of the first EC slots of every thread; later slots hold width 0): tc[v] =
-// the smallest value with F(tc) > r1, fl[v] = F<(tc), ql[v] = the summed
-// width * value of the entries below tc.  Starts from the row's hint cells
-// (the previous sweep's critical cells), else bisects over the sorted value
-// vector, and then stores cells holding the critical values as new hints.
+// The cells of one row as one thread walks them: slot tid, then every 64 NW
+// slots.  Holds the slot's window multi-index j, its cell index t, and the
+// digits of the stride (last dimension fastest) with the cell-index
+// correction of each carry; fo: offsets of the dimensions' factor lists.
+struct RowWalk {
+  int32_t W[kMaxDim], fo[kMaxDim], j[kMaxDim], dT[kMaxDim], corr[kMaxDim];
+  int32_t t, dt;
+};
+
+template <int D>
+__device__ __forceinline__ void walk_init(const SysParams& p, const int32_t* wr, int d, int tid,
+                                          int stride, RowWalk& rw, int& tot) {
+  int rem = tid, remT = stride;
+  tot = 0;
+  rw.t = 0;
+  rw.dt = 0;
+  IMPACT_FOR_DIMS_REV(i, d) {
+    rw.W[i] = wr[d + i];
+    const int Wi = rw.W[i] > 0 ? rw.W[i] : 1;
+    rw.j[i] = rem % Wi;
+    rem /= Wi;
+    rw.dT[i] = remT % Wi;
+    remT /= Wi;
+  }
+  IMPACT_FOR_DIMS(i, d) {
+    const int32_t st = (int32_t)p.stride[i];
+    rw.t += (wr[i] + rw.j[i]) * st;
+    rw.dt += rw.dT[i] * st;
+    rw.corr[i] = (i > 0 ? (int32_t)p.stride[i - 1] : 0) - rw.W[i] * st;
+    rw.fo[i] = tot;
+    tot += rw.W[i];
+  }
+}
+
+// Next slot of the thread: add the stride's digits with carries.
+template <int D>
+__device__ __forceinline__ void walk_step(RowWalk& rw, int d) {
+  int cy = 0;
+  rw.t += rw.dt;
+  IMPACT_FOR_DIMS_REV(i, d) {
+    const int ji = rw.j[i] + rw.dT[i] + cy;
+    cy = ji >= rw.W[i];
+    rw.j[i] = cy ? ji - rw.W[i] : ji;
+    rw.t += cy ? rw.corr[i] : 0;
+  }
+}
+
+// Critical values of the vectors not settled by the hint check (found[v]
+// false), from the signed values x0, x1 and widths w of the first EC slots of
+// every thread (later slots and slots past the row's cells hold width 0 and
+// value +inf): tc[v] = the smallest value with F(tc) > r1, fl[v] = F<(tc),
+// ql[v] = the summed width * value of the entries below tc.  Bisects over the
+// sorted value vector, then stores cells holding the critical values as the
+// row's hints for the next sweep.
 template <int NW, int EC, int E, int D>
-__device__ void sel_search(const SweepArgs& a, int64_t row, int tid, SelLds<NW>& L, int& par,
-                           const double (&w)[E], const double (&x0)[E], const double (&x1)[E],
-                           double r1, double (&tc)[2], double (&fl)[2], double (&ql)[2]) {
+__device__ __forceinline__ void sel_search(const SweepArgs& a, int64_t row, int tid, SelLds<NW>& L,
+                                           int& par, const RowWalk& rw0, int nw,
+                                           const double (&w)[E], const double (&x0)[E],
+                                           const double (&x1)[E], double r1, bool found0,
+                                           bool found1, double (&tc)[2], double (&fl)[2],
+                                           double (&ql)[2]) {
   constexpr int T = 64 * NW;
-  const bool mx = a.maximise != 0;
-  const double sg = mx ? -1.0 : 1.0;
   const int64_t N = a.n_cells;
   const double* sv0 = a.vsort;
   const double* sv1 = a.vsort + N;
@@ -216,65 +271,176 @@ __device__ void sel_search(const SweepArgs& a, int64_t row, int tid, SelLds<NW>&
     }
     block_sums<NW, 6>(s, L, tid, par);
   };
-  int32_t* hint = a.hint + row * 2;
-  const int32_t h0 = hint[0], h1 = hint[1];
-  bool found0 = false, found1 = false;
-  if (h0 >= 0 && h1 >= 0) {
-    tc[0] = sg * a.vin[h0].x;
-    tc[1] = sg * a.vin[h1].y;
-    check(tc[0], tc[1]);
-    found0 = s[0] <= r1 && s[1] > r1;
-    found1 = s[3] <= r1 && s[4] > r1;
-    fl[0] = s[0];
-    ql[0] = s[2];
-    fl[1] = s[3];
-    ql[1] = s[5];
-  }
-  if (found0 && found1) return;
 
-  // bisection over the sorted values: the smallest k with F(<= sv[k]) > r1
-  // (it exists: the largest sorted value counts every entry).  The pivots of
-  // both possible next rounds are fetched before the current round's sums.
-  int64_t lo0 = 0, hi0 = found0 ? 0 : N - 1, lo1 = 0, hi1 = found1 ? 0 : N - 1;
-  int64_t m0 = (lo0 + hi0) >> 1, m1 = (lo1 + hi1) >> 1;
-  double pa = pivot(sv0, m0), pb = pivot(sv1, m1);
-  while (lo0 < hi0 || lo1 < hi1) {
-    const int64_t a0 = (lo0 + m0) >> 1, b0 = (m0 + 1 + hi0) >> 1;
-    const int64_t a1 = (lo1 + m1) >> 1, b1 = (m1 + 1 + hi1) >> 1;
-    const double pa_lo = pivot(sv0, a0), pa_hi = pivot(sv0, b0);
-    const double pb_lo = pivot(sv1, a1), pb_hi = pivot(sv1, b1);
-    double b[2] = {0.0, 0.0};
+  // Bisection over the sorted values for the vectors still searching: the
+  // bracket [lo, hi] of sorted positions holds the smallest k with
+  // F(<= sv[k]) > r1 (the largest sorted value counts every entry).  The
+  // row's entries in the bracket -- values in (sv[lo - 1], sv[hi]] -- are its
+  // candidates, counted every round.  A vector stops when the bracket is one
+  // position, when every sorted value in it is the same, or when at most kTail
+  // candidates are left: those are gathered into LDS, and one wavefront sorts
+  // them and walks their widths from F(<= sv[lo - 1]).
+  const int lane = tid & 63, wv = tid >> 6;
+  const double* svv[2] = {sv0, sv1};
+  const bool found[2] = {found0, found1};
+  bool on[2], tail[2] = {false, false};
+  int64_t lo[2], hi[2];
+  double f_lo[2], n_lo[2], n_hi[2], pv_lo[2], pv_hi[2];
 #pragma unroll
-    for (int e = 0; e < EC; ++e) {
-      b[0] += x0[e] <= pa ? w[e] : 0.0;
-      b[1] += x1[e] <= pb ? w[e] : 0.0;
+  for (int v = 0; v < 2; ++v) {
+    on[v] = !found[v];
+    lo[v] = 0;
+    hi[v] = N - 1;
+    f_lo[v] = 0.0;
+    n_lo[v] = 0.0;
+    pv_lo[v] = -__builtin_inf();
+    pv_hi[v] = on[v] ? pivot(svv[v], N - 1) : 0.0;
+  }
+  {
+    // every cell of the row is a candidate at first (slots past the row's
+    // cells hold +inf)
+    double c[1];
+    int cnt = 0;
+#pragma unroll
+    for (int e = 0; e < EC; ++e) cnt += __popcll(__ballot(x0[e] < __builtin_inf()));
+    c[0] = lane == 0 ? (double)cnt : 0.0;
+    block_sums<NW, 1>(c, L, tid, par);
+    n_hi[0] = n_hi[1] = c[0];
+  }
+#pragma unroll
+  for (int v = 0; v < 2; ++v)
+    if (on[v] && n_hi[v] <= kTail) {
+      on[v] = false;
+      tail[v] = true;
     }
-    block_sums<NW, 2>(b, L, tid, par);
-    if (lo0 < hi0) {
-      if (b[0] > r1) {
-        hi0 = m0;
-        m0 = a0;
-        pa = pa_lo;
-      } else {
-        lo0 = m0 + 1;
-        m0 = b0;
-        pa = pa_hi;
+  while (on[0] || on[1]) {
+    int64_t m[2];
+    double p[2];
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      m[v] = (lo[v] + hi[v]) >> 1;
+      p[v] = on[v] ? pivot(svv[v], m[v]) : 0.0;
+    }
+    double b[4] = {0.0, 0.0, 0.0, 0.0};
+    int c0 = 0, c1 = 0;
+    if (on[0]) {
+#pragma unroll
+      for (int e = 0; e < EC; ++e) {
+        const bool le = x0[e] <= p[0];
+        b[0] += le ? w[e] : 0.0;
+        c0 += __popcll(__ballot(le));
       }
     }
-    if (lo1 < hi1) {
-      if (b[1] > r1) {
-        hi1 = m1;
-        m1 = a1;
-        pb = pb_lo;
+    if (on[1]) {
+#pragma unroll
+      for (int e = 0; e < EC; ++e) {
+        const bool le = x1[e] <= p[1];
+        b[1] += le ? w[e] : 0.0;
+        c1 += __popcll(__ballot(le));
+      }
+    }
+    b[2] = lane == 0 ? (double)c0 : 0.0;
+    b[3] = lane == 0 ? (double)c1 : 0.0;
+    block_sums<NW, 4>(b, L, tid, par);
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      if (!on[v]) continue;
+      if (b[v] > r1) {
+        hi[v] = m[v];
+        n_hi[v] = b[2 + v];
+        pv_hi[v] = p[v];
       } else {
-        lo1 = m1 + 1;
-        m1 = b1;
-        pb = pb_hi;
+        lo[v] = m[v] + 1;
+        f_lo[v] = b[v];
+        n_lo[v] = b[2 + v];
+        pv_lo[v] = p[v];
+      }
+      if (lo[v] == hi[v]) {
+        on[v] = false;
+        tc[v] = pivot(svv[v], lo[v]);
+      } else if (pivot(svv[v], lo[v]) == pv_hi[v]) {
+        on[v] = false;
+        tc[v] = pv_hi[v];  // every sorted value left in the bracket is this one
+      } else if (n_hi[v] - n_lo[v] <= kTail) {
+        on[v] = false;
+        tail[v] = true;
       }
     }
   }
-  if (!found0) tc[0] = pivot(sv0, lo0);
-  if (!found1) tc[1] = pivot(sv1, lo1);
+  if (tail[0] || tail[1]) {
+    // candidates per wavefront, then each one's place in the LDS list
+    auto count = [&](const double(&xv)[E], int v) {
+      int cnt = 0;
+#pragma unroll
+      for (int e = 0; e < EC; ++e)
+        cnt += __popcll(__ballot(xv[e] > pv_lo[v] && xv[e] <= pv_hi[v]));
+      if (lane == 0) L.tcnt[v][wv] = cnt;
+    };
+    auto gather = [&](const double(&xv)[E], int v) {
+      int base = 0;
+      for (int k = 0; k < wv; ++k) base += L.tcnt[v][k];
+#pragma unroll
+      for (int e = 0; e < EC; ++e) {
+        const bool c = xv[e] > pv_lo[v] && xv[e] <= pv_hi[v];
+        const uint64_t mk = (uint64_t)__ballot(c);
+        const int below = (int)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+        if (c) {
+          L.cx[v][base + below] = xv[e];
+          L.cw[v][base + below] = w[e];
+        }
+        base += __popcll(mk);
+      }
+    };
+    if (tail[0]) count(x0, 0);
+    if (tail[1]) count(x1, 1);
+    __syncthreads();
+    if (tail[0]) gather(x0, 0);
+    if (tail[1]) gather(x1, 1);
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        if (!tail[v]) continue;
+        const int cnt = (int)(n_hi[v] - n_lo[v]);
+        uint64_t key[2];
+        double ww[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int pos = lane * 2 + k;
+          if (pos < cnt) {
+            const uint64_t bits = dbits(L.cx[v][pos]);
+            key[k] = (bits >> 63) ? ~bits : (bits | (1ull << 63));  // order-preserving
+            ww[k] = L.cw[v][pos];
+          } else {
+            key[k] = ~0ull;
+            ww[k] = 0.0;
+          }
+        }
+        bitonic_sort<2, 1, double>(key, ww, lane, nullptr);
+        // the first sorted candidate at which F(<= sv[lo - 1]) plus the
+        // widths so far exceeds r1
+        const double excl = wave_excl_scan(ww[0] + ww[1], lane);
+        const double i0 = f_lo[v] + excl + ww[0], i1 = i0 + ww[1];
+        const bool h0 = i0 > r1 && 2 * lane < cnt, h1 = i1 > r1 && 2 * lane + 1 < cnt;
+        const uint64_t mk = (uint64_t)__ballot(h0 || h1);
+        int pos = cnt - 1;  // rounding: the largest candidate
+        if (mk) {
+          const int ln = __builtin_ctzll(mk);
+          pos = 2 * ln + (__shfl((int)h0, ln) ? 0 : 1);
+        }
+        const uint64_t k0 = (uint64_t)__shfl((long long)key[0], pos >> 1);
+        const uint64_t k1 = (uint64_t)__shfl((long long)key[1], pos >> 1);
+        const uint64_t kx = (pos & 1) ? k1 : k0;
+        const uint64_t bits = (kx >> 63) ? (kx & ~(1ull << 63)) : ~kx;
+        if (lane == 0) L.tres[v] = bitsd(bits);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+      if (tail[v]) tc[v] = uniform_f64(L.tres[v]);
+  }
   check(tc[0], tc[1]);
   if (!found0) {
     fl[0] = s[0];
@@ -286,158 +452,97 @@ __device__ void sel_search(const SweepArgs& a, int64_t row, int tid, SelLds<NW>&
   }
 
   // a cell holding each critical value (with positive width), for the next sweep
-  const SysParams& p = *a.sys;
-  const int d = D > 0 ? D : a.d;
-  const int32_t* wr = a.win + row * 2 * d;
-  const int nw = (int)(a.row_off[row + 1] - a.row_off[row]);
   if (tid == 0) {
     L.hit[0] = -1;
     L.hit[1] = -1;
   }
   __syncthreads();
   {
-    int W[kMaxDim], j[kMaxDim];
-    int32_t tt = 0;
-    int rem = tid;
-    IMPACT_FOR_DIMS_REV(i, d) {
-      W[i] = wr[d + i];
-      const int Wi = W[i] > 0 ? W[i] : 1;
-      j[i] = rem % Wi;
-      rem /= Wi;
-    }
-    IMPACT_FOR_DIMS(i, d) tt += (wr[i] + j[i]) * (int32_t)p.stride[i];
-    int dT[kMaxDim];
-    int32_t dt = 0, corr[kMaxDim];
-    {
-      int remT = T;
-      IMPACT_FOR_DIMS_REV(i, d) {
-        const int Wi = W[i] > 0 ? W[i] : 1;
-        dT[i] = remT % Wi;
-        remT /= Wi;
-      }
-      IMPACT_FOR_DIMS(i, d) {
-        const int32_t st = (int32_t)p.stride[i];
-        dt += dT[i] * st;
-        corr[i] = (i > 0 ? (int32_t)p.stride[i - 1] : 0) - W[i] * st;
-      }
-    }
+    const int d = D > 0 ? D : a.d;
+    RowWalk rw = rw0;
 #pragma unroll
     for (int e = 0; e < EC; ++e) {
       if (e * T + tid < nw && w[e] > 0.0) {
-        if (!found0 && x0[e] == tc[0]) L.hit[0] = tt;
-        if (!found1 && x1[e] == tc[1]) L.hit[1] = tt;
+        if (!found0 && x0[e] == tc[0]) L.hit[0] = rw.t;
+        if (!found1 && x1[e] == tc[1]) L.hit[1] = rw.t;
       }
-      int cy = 0;
-      tt += dt;
-      IMPACT_FOR_DIMS_REV(i, d) {
-        const int ji = j[i] + dT[i] + cy;
-        cy = ji >= W[i];
-        j[i] = cy ? ji - W[i] : ji;
-        tt += cy ? corr[i] : 0;
-      }
+      walk_step<D>(rw, d);
     }
   }
   __syncthreads();
   if (tid == 0) {
+    int32_t* hint = a.hint + row * 2;
     if (!found0) hint[0] = L.hit[0];
     if (!found1) hint[1] = L.hit[1];
   }
 }
 
-// Both LP values (V0 and V1) of one row.  Values are held signed (negated for
-// a maximising LP) so that both directions search for the smallest critical
-// value in ascending order.
-template <int NW, int E, int D>
-__device__ void sel_row(const SweepArgs& a, int64_t row, int tid, SelLds<NW>& L, int& par,
-                        double& q0, double& q1) {
+// Both LP values of one row from its first EC slots per thread (see sel_row).
+// The load pass also checks the hint values (tau0, tau1): F<, F<= and the
+// width * value below each, so that a row whose critical cells did not move
+// costs one pass.
+template <int NW, int EC, int E, int D>
+__device__ __forceinline__ void sel_row_body(const SweepArgs& a, int64_t row, int tid,
+                                             SelLds<NW>& L, int& par, const RowWalk& rw0,
+                                             int nw, int64_t base, bool have_hint, double tau0,
+                                             double tau1, double& q0, double& q1) {
   constexpr int T = 64 * NW;
-  const SysParams& p = *a.sys;
   const int d = D > 0 ? D : a.d;
-  const int64_t base = a.row_off[row];
-  const int nw = (int)(a.row_off[row + 1] - base);
-  const int32_t* wr = a.win + row * 2 * d;
   const bool mx = a.maximise != 0;
   const double sg = mx ? -1.0 : 1.0;
   const bool factors = a.storage == IMPACT_STORE_FACTORS;
 
-  int W[kMaxDim], fo[kMaxDim], j[kMaxDim], dT[kMaxDim];
-  int32_t corr[kMaxDim];
-  int32_t t = 0, dt = 0;
-  {
-    int rem = tid, remT = T, tot = 0;
-    IMPACT_FOR_DIMS_REV(i, d) {
-      W[i] = wr[d + i];
-      const int Wi = W[i] > 0 ? W[i] : 1;
-      j[i] = rem % Wi;
-      rem /= Wi;
-      dT[i] = remT % Wi;
-      remT /= Wi;
-    }
-    IMPACT_FOR_DIMS(i, d) {
-      const int32_t st = (int32_t)p.stride[i];
-      t += (wr[i] + j[i]) * st;
-      dt += dT[i] * st;
-      corr[i] = (i > 0 ? (int32_t)p.stride[i - 1] : 0) - W[i] * st;
-      fo[i] = tot;
-      tot += W[i];
-    }
-    if (factors) {
-      __syncthreads();  // the previous row's readers are done with L.fac
-      const double2* fr = a.fac + row * (int64_t)a.fs;
-      for (int k = tid; k < tot; k += T) L.fac[k] = fr[k];
-      __syncthreads();
-    }
-  }
-
-  // load the window cells: width and both values per slot
+  // the cells: width and both signed values per slot; loads use a valid
+  // address for slots past the row's cells so that none waits on a branch
   double w[E], x0[E], x1[E];
-  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // sum lo, sum w, lo v0, lo v1, w v0, w v1
-  const int Erow = (nw + T - 1) / T;
+  // sum lo, sum w, lo v0, lo v1, w v0, w v1, then the hint checks of V0 and V1
+  double acc[12];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    w[e] = 0.0;
-    x0[e] = 0.0;
-    x1[e] = 0.0;
-    if (e < Erow) {
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  {
+    RowWalk rw = rw0;
+#pragma unroll
+    for (int e = 0; e < EC; ++e) {
       const int slot = e * T + tid;
-      if (slot < nw) {
-        double lo, hi;
-        if (factors) {
-          lo = 1.0;
-          hi = 1.0;
-          IMPACT_FOR_DIMS(i, d) {
-            const double2 f = L.fac[fo[i] + j[i]];
-            lo *= f.x;
-            hi *= f.y;
-          }
-        } else {
-          const double2 b = a.ent[base + slot];
-          lo = b.x;
-          hi = b.y;
+      const bool ok = slot < nw;
+      double lo, hi;
+      if (factors) {
+        lo = 1.0;
+        hi = 1.0;
+        IMPACT_FOR_DIMS(i, d) {
+          const double2 f = L.fac[rw.fo[i] + (ok ? rw.j[i] : 0)];
+          lo *= f.x;
+          hi *= f.y;
         }
-        const double2 V = a.vin[t];
-        w[e] = hi - lo;
-        x0[e] = sg * V.x;
-        x1[e] = sg * V.y;
-        acc[0] += lo;
-        acc[1] += w[e];
-        acc[2] += lo * V.x;
-        acc[3] += lo * V.y;
-        acc[4] += w[e] * V.x;
-        acc[5] += w[e] * V.y;
+      } else {
+        const double2 b = a.ent[base + (ok ? slot : 0)];
+        lo = b.x;
+        hi = b.y;
       }
-      // next slot of this thread: add the digits of T, last dimension fastest
-      int cy = 0;
-      t += dt;
-      IMPACT_FOR_DIMS_REV(i, d) {
-        const int ji = j[i] + dT[i] + cy;
-        cy = ji >= W[i];
-        j[i] = cy ? ji - W[i] : ji;
-        t += cy ? corr[i] : 0;
-      }
+      const double2 V = a.vin[ok ? rw.t : 0];
+      lo = ok ? lo : 0.0;
+      const double wd = ok ? hi - lo : 0.0;
+      w[e] = wd;
+      x0[e] = ok ? sg * V.x : __builtin_inf();
+      x1[e] = ok ? sg * V.y : __builtin_inf();
+      acc[0] += lo;
+      acc[1] += wd;
+      acc[2] += lo * V.x;
+      acc[3] += lo * V.y;
+      acc[4] += wd * V.x;
+      acc[5] += wd * V.y;
+      const bool a_lt = x0[e] < tau0, a_le = x0[e] <= tau0;
+      const bool b_lt = x1[e] < tau1, b_le = x1[e] <= tau1;
+      acc[6] += a_lt ? wd : 0.0;
+      acc[7] += a_le ? wd : 0.0;
+      acc[8] += a_lt ? wd * x0[e] : 0.0;
+      acc[9] += b_lt ? wd : 0.0;
+      acc[10] += b_le ? wd : 0.0;
+      acc[11] += b_lt ? wd * x1[e] : 0.0;
+      walk_step<D>(rw, d);
     }
   }
-  block_sums<NW, 6>(acc, L, tid, par);
+  block_sums<NW, 12>(acc, L, tid, par);
 
   // OUT and TAIL: value out_val and the end value of the order
   const double4 o = a.ot[row];
@@ -466,29 +571,70 @@ __device__ void sel_row(const SweepArgs& a, int64_t row, int tid, SelLds<NW>& L,
   const double sw = acc[1];
   if (!(sw > r1)) {
     // every cell gets its full width; what is left goes to OUT if it comes last
-    double ql = 0.0;
+    double qlast = 0.0;
     if (!out_first) {
       const double r2 = r1 - sw, ow = o.y - o.x;
-      ql = (ow < r2 ? ow : r2) * a.out_val;
+      qlast = (ow < r2 ? ow : r2) * a.out_val;
     }
-    q0 = base0 + acc[4] + ql;
-    q1 = base1 + acc[5] + ql;
+    q0 = base0 + acc[4] + qlast;
+    q1 = base1 + acc[5] + qlast;
     return;
   }
-
-  // search for the critical values of both vectors over the first EC slots of
-  // every thread (slots past the row's cells have width 0 and count nothing)
-  double tc[2], fl[2], ql[2];
-  if (E <= 4 || Erow <= 4)
-    sel_search<NW, (E < 4 ? E : 4), E, D>(a, row, tid, L, par, w, x0, x1, r1, tc, fl, ql);
-  else if (E <= 8 || Erow <= 8)
-    sel_search<NW, (E < 8 ? E : 8), E, D>(a, row, tid, L, par, w, x0, x1, r1, tc, fl, ql);
-  else if (E <= 12 || Erow <= 12)
-    sel_search<NW, (E < 12 ? E : 12), E, D>(a, row, tid, L, par, w, x0, x1, r1, tc, fl, ql);
-  else
-    sel_search<NW, E, E, D>(a, row, tid, L, par, w, x0, x1, r1, tc, fl, ql);
+  // the hint values are the critical values when F< <= r1 < F<= at them
+  const bool found0 = have_hint && acc[6] <= r1 && acc[7] > r1;
+  const bool found1 = have_hint && acc[9] <= r1 && acc[10] > r1;
+  double tc[2] = {tau0, tau1}, fl[2] = {acc[6], acc[9]}, ql[2] = {acc[8], acc[11]};
+  if (!(found0 && found1))
+    sel_search<NW, EC, E, D>(a, row, tid, L, par, rw0, nw, w, x0, x1, r1, found0, found1, tc, fl,
+                             ql);
   q0 = base0 + sg * (ql[0] + (r1 - fl[0]) * tc[0]);
   q1 = base1 + sg * (ql[1] + (r1 - fl[1]) * tc[1]);
+}
+
+// Both LP values (V0 and V1) of one row.  Values are held signed (negated for
+// a maximising LP) so that both directions search for the smallest critical
+// value in ascending order.  The thread's slots are processed by a body
+// unrolled over the smallest of 4, 8, 12 and E slots that covers the row.
+template <int NW, int E, int D>
+__device__ __forceinline__ void sel_row(const SweepArgs& a, int64_t row, int tid, SelLds<NW>& L,
+                                        int& par, double& q0, double& q1) {
+  constexpr int T = 64 * NW;
+  const SysParams& p = *a.sys;
+  const int d = D > 0 ? D : a.d;
+  const int64_t base = a.row_off[row];
+  const int nw = (int)(a.row_off[row + 1] - base);
+  const int32_t* wr = a.win + row * 2 * d;
+  const double sg = a.maximise ? -1.0 : 1.0;
+  // the previous sweep's critical cells of this row, read first so that their
+  // values arrive while the cells load
+  const int32_t* hint = a.hint + row * 2;
+  const int32_t h0 = hint[0], h1 = hint[1];
+  const bool have_hint = h0 >= 0 && h1 >= 0;
+  const double tau0 = have_hint ? sg * a.vin[h0].x : 0.0;
+  const double tau1 = have_hint ? sg * a.vin[h1].y : 0.0;
+  RowWalk rw;
+  int tot;
+  walk_init<D>(p, wr, d, tid, T, rw, tot);
+  if (a.storage == IMPACT_STORE_FACTORS) {
+    __syncthreads();  // the previous row's readers are done with L.fac
+    const double2* fr = a.fac + row * (int64_t)a.fs;
+    for (int k = tid; k < tot; k += T) L.fac[k] = fr[k];
+    __syncthreads();
+  }
+  const int Erow = (nw + T - 1) / T;
+  if (Erow == 0)
+    sel_row_body<NW, 1, E, D>(a, row, tid, L, par, rw, nw, base, have_hint, tau0, tau1, q0, q1);
+  else if (E <= 4 || Erow <= 4)
+    sel_row_body<NW, (E < 4 ? E : 4), E, D>(a, row, tid, L, par, rw, nw, base, have_hint, tau0,
+                                            tau1, q0, q1);
+  else if (E <= 8 || Erow <= 8)
+    sel_row_body<NW, (E < 8 ? E : 8), E, D>(a, row, tid, L, par, rw, nw, base, have_hint, tau0,
+                                            tau1, q0, q1);
+  else if (E <= 12 || Erow <= 12)
+    sel_row_body<NW, (E < 12 ? E : 12), E, D>(a, row, tid, L, par, rw, nw, base, have_hint,
+                                              tau0, tau1, q0, q1);
+  else
+    sel_row_body<NW, E, E, D>(a, row, tid, L, par, rw, nw, base, have_hint, tau0, tau1, q0, q1);
 }
 
 // One SAFE state s: its rows (all inputs in the policy pass, PASS 0; the
@@ -497,7 +643,7 @@ __device__ void sel_row(const SweepArgs& a, int64_t row, int tid, SelLds<NW>& L,
 // the state's V1 - V0 on every thread.  With a disturbance player (nw > 1)
 // every (state, input) has nw rows and is valued by its worst one (eq. (5.1)).
 template <int NW, int E, int PASS, int D>
-__device__ double sel_state(const SweepArgs& a, int64_t s, SelLds<NW>& L) {
+__device__ __forceinline__ double sel_state(const SweepArgs& a, int64_t s, SelLds<NW>& L) {
   const int tid = threadIdx.x;
   const int U = PASS == 0 ? a.nu : 1;
   const int NWD = a.nw > 1 ? a.nw : 1;
@@ -542,8 +688,11 @@ __device__ double sel_state(const SweepArgs& a, int64_t s, SelLds<NW>& L) {
   return g > 0.0 ? g : 0.0;
 }
 
+// Two waves per SIMD at least: without the bound the compiler reaches for the
+// accumulation registers and leaves one wave per SIMD, which doubles the sweep.
 template <int NW, int E, int PASS, int D>
-__global__ __launch_bounds__(64 * NW) void k_sweep_sel(SweepArgs a) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 8)))
+void k_sweep_sel(SweepArgs a) {
   if (a.ctrl->done) return;
   __shared__ SelLds<NW> L;
   const int64_t si = blockIdx.x;
@@ -696,7 +845,8 @@ hipError_t launch_mq_value_sort(const QueryDesc* desc, const QueryCtrl* ctrl,
 // query at its own phase and step: a sweep of the state (phases 0 and 2) or
 // the close of a pass (phases 1 and 3).
 template <int NW, int E, int D>
-__global__ __launch_bounds__(64 * NW) void k_mq_sweep_sel(
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 8)))
+void k_mq_sweep_sel(
     const QueryDesc* __restrict__ desc, const QueryCtrl* __restrict__ ctrl,
     const int32_t* __restrict__ wq, const int32_t* __restrict__ ws, int64_t n_items,
     double* __restrict__ gap_item) {
