@@ -49,6 +49,12 @@ class _Imdp(C.Structure):
                 ("lo", C.POINTER(C.c_double)), ("hi", C.POINTER(C.c_double))]
 
 
+class _McNoise(C.Structure):
+    _fields_ = [("inv_cov", C.POINTER(C.c_double)), ("det_cov", C.c_double),
+                ("n_samples", C.c_int64), ("samples", C.POINTER(C.c_double)),
+                ("grid_pts", C.c_int32), ("kappa", C.c_double)]
+
+
 class _IterInfo(C.Structure):
     _fields_ = [("sweeps", C.c_int64 * 2), ("gap", C.c_double * 2),
                 ("converged", C.c_int32 * 2), ("n_safe", C.c_int64)]
@@ -81,6 +87,17 @@ def lib():
         L.orc_build.argtypes = [C.POINTER(_System), C.POINTER(_Grid), C.POINTER(_Inputs), pd, d,
                                 C.POINTER(C.c_int64), i64, C.POINTER(_Imdp)]
         L.orc_imdp_free.argtypes = [C.POINTER(_Imdp)]
+        L.orc_marginal_sigma.restype = C.c_int
+        L.orc_marginal_sigma.argtypes = [C.c_int, pd, pd]
+        L.orc_mc_cover_radius.restype = d
+        L.orc_mc_cover_radius.argtypes = [C.c_int, pd, pd, pd, C.c_int]
+        L.orc_mc_shift_bound.restype = d
+        L.orc_mc_shift_bound.argtypes = [C.c_int, pd, d, d, d, pd, pd]
+        L.orc_mc_cell_estimate.argtypes = [C.c_int, pd, d, pd, pd, pd, i64, pd, pd, pd]
+        L.orc_build_mc.restype = C.c_int
+        L.orc_build_mc.argtypes = [C.POINTER(_System), C.POINTER(_Grid), C.POINTER(_Inputs),
+                                   C.POINTER(_McNoise), d, C.POINTER(C.c_int64), i64,
+                                   C.POINTER(_Imdp)]
         L.orc_label.restype = C.c_int
         L.orc_label.argtypes = [C.POINTER(_Grid), i32, pd, i32, pd, C.POINTER(C.c_int8)]
         L.orc_lp_sorted.restype = d
@@ -196,6 +213,88 @@ def factor_bounds(a, b, mlo, mhi, sigma):
 
 def exit_prob(lb, ub, m, sigma):
     return lib().orc_exit_prob(lb, ub, m, sigma)
+
+
+def marginal_sigma(inv_cov):
+    """sqrt of the diagonal of the covariance whose inverse is ``inv_cov``."""
+    P = _f64(inv_cov)
+    d = int(round(np.sqrt(P.size)))
+    s = np.zeros(d)
+    if lib().orc_marginal_sigma(d, _dptr(P), _dptr(s)) != 0:
+        raise ValueError("inverse covariance is singular or not positive")
+    return s
+
+
+def mc_cover_radius(inv_cov, mlo, mhi, G):
+    """Mahalanobis covering radius of a G-per-dimension lattice over [mlo, mhi]."""
+    P, mlo, mhi = _f64(inv_cov), _f64(mlo), _f64(mhi)
+    return lib().orc_mc_cover_radius(len(mlo), _dptr(P), _dptr(mlo), _dptr(mhi), int(G))
+
+
+def mc_shift_bound(sigma, det_cov, rho, vol, zlo, zhi):
+    """Bound on the change of a cell's mass under a mean shift of Mahalanobis
+    length <= rho, with every y - m in the box [zlo, zhi]."""
+    sigma, zlo, zhi = _f64(sigma), _f64(zlo), _f64(zhi)
+    d = len(sigma)
+    norm = 1.0 / np.sqrt((2.0 * np.pi) ** d * det_cov)
+    return lib().orc_mc_shift_bound(d, _dptr(sigma), norm, float(rho), float(vol),
+                                    _dptr(zlo), _dptr(zhi))
+
+
+def mc_cell_estimate(inv_cov, det_cov, a, b, m, samples):
+    """Plain Monte Carlo N(m, Cov) mass of the box [a, b] and its standard error."""
+    P, a, b, m = _f64(inv_cov), _f64(a), _f64(b), _f64(m)
+    X = _f64(samples)
+    d = len(a)
+    norm = 1.0 / np.sqrt((2.0 * np.pi) ** d * det_cov)
+    p, se = C.c_double(), C.c_double()
+    lib().orc_mc_cell_estimate(d, _dptr(P), norm, _dptr(a), _dptr(b), _dptr(m),
+                               X.size // d, _dptr(X), C.byref(p), C.byref(se))
+    return p.value, se.value
+
+
+def _collect(out):
+    d, R, E = out.dim, out.n_rows, out.n_entries
+    return dict(
+        n_states=out.n_states, n_inputs=out.n_inputs, dim=d, windowed=bool(out.windowed),
+        win=np.ctypeslib.as_array(out.win, (R, 2 * d)).copy(),
+        ot=np.ctypeslib.as_array(out.ot, (R, 4)).copy(),
+        row_ptr=np.ctypeslib.as_array(out.row_ptr, (R + 1,)).copy(),
+        target=np.ctypeslib.as_array(out.target, (max(E, 1),))[:E].copy(),
+        lo=np.ctypeslib.as_array(out.lo, (max(E, 1),))[:E].copy(),
+        hi=np.ctypeslib.as_array(out.hi, (max(E, 1),))[:E].copy(),
+    )
+
+
+def _rows_arg(rows):
+    if rows is None:
+        return None, 0, None
+    rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+    return rows.ctypes.data_as(C.POINTER(C.c_int64)), len(rows), rows
+
+
+def build_mc(system, mc, k_sigma, rows=None):
+    """Rows of the abstraction under correlated noise (Section 4.1 full
+    covariance, Monte Carlo cell masses); same layout as ``build``.
+
+    ``mc``: dict with ``inv_cov`` (d x d), ``det_cov``, ``samples`` (N x d in
+    [0, 1)), ``grid_pts`` (G) and ``kappa``.  ``system["sigma"]`` is unused.
+    """
+    m = _Marshal(dict(system, sigma=np.ones(len(system["lb"]))))
+    P, X = _f64(mc["inv_cov"]), _f64(mc["samples"])
+    d = len(m.lb)
+    nz = _McNoise(_dptr(P), float(mc["det_cov"]), X.size // d, _dptr(X),
+                  int(mc["grid_pts"]), float(mc["kappa"]))
+    out = _Imdp()
+    rp, nr, keep = _rows_arg(rows)
+    rc = lib().orc_build_mc(C.byref(m.sys), C.byref(m.grid), C.byref(m.inp), C.byref(nz),
+                            float(k_sigma), rp, nr, C.byref(out))
+    try:
+        if rc != 0:
+            raise ValueError(f"oracle Monte Carlo build failed ({rc})")
+        return _collect(out)
+    finally:
+        lib().orc_imdp_free(C.byref(out))
 
 
 def build(system, k_sigma, rows=None):

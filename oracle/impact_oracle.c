@@ -776,3 +776,398 @@ int orc_iterate(int64_t n_states, int32_t n_inputs, const int64_t *row_ptr,
   free(pi);
   return capped;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Correlated Gaussian noise by Monte Carlo integration (Section 4.1: a full  */
+/* covariance given by its inverse and its determinant, cell masses by Monte  */
+/* Carlo integration with a user-chosen number of samples).                   */
+/*                                                                            */
+/* Readings (the section names the integrator, not the bound construction):   */
+/*  - the integral over a target cell is the plain Monte Carlo estimate: the   */
+/*    density N(y; m, Cov) at the caller's points of [0,1)^d mapped onto the   */
+/*    cell, averaged and multiplied by the cell volume; the points are an      */
+/*    input, shared by every cell;                                            */
+/*  - the min / max over the source cell (Def. 3.1), which the paper hands to  */
+/*    a numerical optimiser, is taken over a lattice of G^d candidate means,   */
+/*    the centres of a G-per-dimension split of the mean box, each estimate    */
+/*    widened by a bound on how far the cell's mass can move between the      */
+/*    candidate and any mean of its half-spacing box (orc_mc_shift_bound), so  */
+/*    the bounds hold for the whole mean box up to the Monte Carlo error;     */
+/*  - the Monte Carlo error is covered by kappa standard errors of each        */
+/*    estimate (sample standard deviation / sqrt(N)) on each side;            */
+/*  - windows use the marginal standard deviations sqrt(Cov_ii); OUT and TAIL  */
+/*    use union bounds over dimensions of the marginal exit masses, which     */
+/*    hold for any correlation.                                               */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Marginal standard deviations sqrt(Cov_ii) from the inverse covariance:
+ * Gauss-Jordan inversion with partial pivoting.  Returns 0, or -1 for a
+ * singular matrix or a non-positive diagonal of the inverse.
+ */
+int orc_marginal_sigma(int d, const double *inv_cov, double *sigma) {
+  double a[ORC_MAX_DIM][2 * ORC_MAX_DIM];
+  if (d < 1 || d > ORC_MAX_DIM) return -1;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < 2 * d; ++j)
+      a[i][j] = j < d ? inv_cov[i * d + j] : (j - d == i ? 1.0 : 0.0);
+  for (int col = 0; col < d; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < d; ++r)
+      if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
+    if (!(fabs(a[piv][col]) > 0.0)) return -1;
+    if (piv != col)
+      for (int j = 0; j < 2 * d; ++j) {
+        double t = a[col][j];
+        a[col][j] = a[piv][j];
+        a[piv][j] = t;
+      }
+    double p = a[col][col];
+    for (int j = 0; j < 2 * d; ++j) a[col][j] /= p;
+    for (int r = 0; r < d; ++r) {
+      if (r == col) continue;
+      double f = a[r][col];
+      if (f == 0.0) continue;
+      for (int j = 0; j < 2 * d; ++j) a[r][j] -= f * a[col][j];
+    }
+  }
+  for (int i = 0; i < d; ++i) {
+    double v = a[i][d + i];
+    if (!(v > 0.0) || !isfinite(v)) return -1;
+    sigma[i] = sqrt(v);
+  }
+  return 0;
+}
+
+/* e^T P e, summed as sum_i e_i * (sum_j P_ij e_j), both sums in index order. */
+static double quad_form(int d, const double *P, const double *e) {
+  double q = 0.0;
+  for (int i = 0; i < d; ++i) {
+    double t = 0.0;
+    for (int j = 0; j < d; ++j) t += P[i * d + j] * e[j];
+    q += e[i] * t;
+  }
+  return q;
+}
+
+/*
+ * Covering radius of the candidate lattice: with G candidates per dimension at
+ * the centres of a G-way split of [mlo, mhi], every mean of the box lies
+ * within h_i / 2 of its nearest candidate in each dimension (h_i = (mhi_i -
+ * mlo_i) / G).  Returns rho, the largest Mahalanobis length sqrt(e^T P e) over
+ * that half-spacing box, attained at one of its corners (a convex form is
+ * largest at a vertex).
+ */
+double orc_mc_cover_radius(int d, const double *inv_cov, const double *mlo, const double *mhi,
+                           int G) {
+  double half[ORC_MAX_DIM], e[ORC_MAX_DIM];
+  for (int i = 0; i < d; ++i) half[i] = 0.5 * ((mhi[i] - mlo[i]) / (double)G);
+  double best = 0.0;
+  for (int corner = 0; corner < (1 << d); ++corner) {
+    for (int i = 0; i < d; ++i) e[i] = (corner >> i) & 1 ? half[i] : -half[i];
+    double q = quad_form(d, inv_cov, e);
+    if (q > best) best = q;
+  }
+  return sqrt(best);
+}
+
+/*
+ * How far the N(m, Cov) mass of a cell of volume vol can move when the mean
+ * moves from a candidate by a shift of Mahalanobis length at most rho, with
+ * every y - m (y in the cell, m within the candidate's half-spacing box) in
+ * the box [zlo, zhi].  Two bounds, the smaller taken:
+ *  - total variation: no set's mass moves by more than erf(rho / (2 sqrt 2))
+ *    = 2 Phi(rho / 2) - 1 between N(m, Cov) and N(m', Cov);
+ *  - the mean-derivative of the cell mass along the shift, integrated over the
+ *    cell: |d^T P z| f(z) <= rho r f(z) with r = sqrt(z^T P z) (Cauchy-Schwarz
+ *    in the P inner product) and f(z) = norm exp(-r^2 / 2), so the change is
+ *    at most vol norm rho g(r_lb), g(r) = r exp(-r^2 / 2) at r >= 1 and
+ *    exp(-1/2) below (g's maximum), r_lb = max_i dist(0, [zlo_i, zhi_i]) /
+ *    sigma_i a lower bound on r over the box (|z_i| <= sigma_i r).
+ */
+double orc_mc_shift_bound(int d, const double *sigma, double norm, double rho, double vol,
+                          const double *zlo, const double *zhi) {
+  double tv = erf((rho * 0.5) * ORC_RSQRT2);
+  double r = 0.0;
+  for (int i = 0; i < d; ++i) {
+    double dist = zlo[i] > 0.0 ? zlo[i] : (zhi[i] < 0.0 ? -zhi[i] : 0.0);
+    double t = dist / sigma[i];
+    if (t > r) r = t;
+  }
+  double g = r > 1.0 ? r * exp(-0.5 * (r * r)) : exp(-0.5);
+  double lip = ((vol * norm) * rho) * g;
+  return lip < tv ? lip : tv;
+}
+
+/* 1 / sqrt((2 pi)^d det(Cov)), the Gaussian density's constant. */
+static double mc_norm(int d, double det_cov) {
+  double t = 1.0;
+  for (int i = 0; i < d; ++i) t *= 2.0 * ORC_PI;
+  return 1.0 / sqrt(t * det_cov);
+}
+
+/*
+ * Plain Monte Carlo estimate of the N(m, Cov) mass of the box [a, b]:
+ * p = vol * mean_k f(y_k), y_k = a + (b - a) * r_k, f the density, and its
+ * standard error vol * s / sqrt(N), s^2 the unbiased sample variance of
+ * f(y_k) (0 when N = 1).  Samples are summed in index order.
+ */
+void orc_mc_cell_estimate(int d, const double *inv_cov, double norm, const double *a,
+                          const double *b, const double *m, int64_t n, const double *samples,
+                          double *p, double *se) {
+  double wd[ORC_MAX_DIM], e[ORC_MAX_DIM];
+  double vol = 1.0;
+  for (int i = 0; i < d; ++i) {
+    wd[i] = b[i] - a[i];
+    vol *= wd[i];
+  }
+  double S = 0.0, S2 = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    for (int i = 0; i < d; ++i) {
+      double y = a[i] + wd[i] * samples[k * d + i];
+      e[i] = y - m[i];
+    }
+    double z = norm * exp(-0.5 * quad_form(d, inv_cov, e));
+    S += z;
+    S2 += z * z;
+  }
+  double mean = S / (double)n;
+  double var = 0.0;
+  if (n > 1) {
+    var = (S2 - ((double)n * mean) * mean) / (double)(n - 1);
+    if (var < 0.0) var = 0.0;
+  }
+  *p = vol * mean;
+  *se = vol * sqrt(var / (double)n);
+}
+
+/*
+ * OUT and TAIL of one row under correlated noise.  The exit event is the
+ * union of the per-dimension exits, each depending on its own mean coordinate
+ * and marginal standard deviation only, so
+ *   OUT_lo = max_i min over the mean interval of q_i (at the domain centre
+ *            clamped into it), OUT_hi = min(1, sum_i max of q_i (at an end));
+ * landing in the domain but outside the window needs an exit through an
+ * interior side of the window in some dimension, so
+ *   TAIL_hi = min(1 - OUT_lo, sum_i max over the mean interval of that exit
+ *             mass), TAIL_lo = 0.
+ */
+static void row_out_tail_union(const orc_grid *g, const double *sigma, double k_sigma,
+                               row_geom *r) {
+  double out_lo = 0.0, out_hi = 0.0, tail = 0.0;
+  for (int i = 0; i < g->dim; ++i) {
+    double lb = g->lb[i], ub = g->ub[i];
+    double qa = orc_exit_prob(lb, ub, r->mlo[i], sigma[i]);
+    double qb = orc_exit_prob(lb, ub, r->mhi[i], sigma[i]);
+    double qmax = qa > qb ? qa : qb;
+    double ctr = 0.5 * (lb + ub);
+    double mc = ctr < r->mlo[i] ? r->mlo[i] : (ctr > r->mhi[i] ? r->mhi[i] : ctr);
+    double qmin = orc_exit_prob(lb, ub, mc, sigma[i]);
+    if (qmin > qmax) qmin = qmax;
+    if (qmin > out_lo) out_lo = qmin;
+    out_hi += qmax;
+    if (k_sigma > 0.0) {
+      double p;
+      if (r->W[i] == 0) {
+        p = 1.0;
+      } else {
+        int64_t khi = r->klo[i] + r->W[i] - 1;
+        int has_a = r->klo[i] > 0, has_b = khi < g->n[i] - 1;
+        double A = orc_cell_edge(g, i, r->klo[i]);
+        double B = orc_cell_edge(g, i, khi + 1);
+        double pa = window_exit_prob(A, has_a, B, has_b, r->mlo[i], sigma[i]);
+        double pb = window_exit_prob(A, has_a, B, has_b, r->mhi[i], sigma[i]);
+        p = pa > pb ? pa : pb;
+      }
+      tail += p;
+    }
+  }
+  if (out_hi > 1.0) out_hi = 1.0;
+  r->out_lo = out_lo;
+  r->out_hi = out_hi;
+  r->tail_lo = 0.0;
+  r->tail_hi = 0.0;
+  if (k_sigma > 0.0) {
+    double cap = 1.0 - out_lo;
+    if (tail > cap) tail = cap;
+    if (tail < 0.0) tail = 0.0;
+    r->tail_hi = tail;
+  }
+}
+
+/*
+ * Entry bounds of one row's window cells under correlated noise: for each
+ * cell (C order over the window) the estimate at every candidate mean
+ * (C order over the G^d lattice), lo = min(p - kappa se - shift) and
+ * hi = max(p + kappa se + shift), shift the candidate's orc_mc_shift_bound,
+ * both clamped into [0, 1]; then OUT and,
+ * when windowed, TAIL.
+ */
+static void row_entries_mc(const orc_grid *g, const orc_mc_noise *mc, const double *sigma,
+                           const row_geom *r, int windowed, int32_t *target, double *lo,
+                           double *hi) {
+  int d = g->dim, G = mc->grid_pts;
+  double norm = mc_norm(d, mc->det_cov);
+  double rho = orc_mc_cover_radius(d, mc->inv_cov, r->mlo, r->mhi, G);
+  double h[ORC_MAX_DIM];
+  for (int i = 0; i < d; ++i) h[i] = (r->mhi[i] - r->mlo[i]) / (double)G;
+  int64_t n_cand = 1;
+  for (int i = 0; i < d; ++i) n_cand *= G;
+  int64_t stride[ORC_MAX_DIM];
+  stride[d - 1] = 1;
+  for (int i = d - 2; i >= 0; --i) stride[i] = stride[i + 1] * g->n[i + 1];
+  double a[ORC_MAX_DIM], b[ORC_MAX_DIM], m[ORC_MAX_DIM], zlo[ORC_MAX_DIM], zhi[ORC_MAX_DIM];
+  for (int64_t slot = 0; slot < r->n_cells; ++slot) {
+    int64_t rem = slot, t = 0;
+    int64_t j[ORC_MAX_DIM];
+    for (int i = d - 1; i >= 0; --i) {
+      j[i] = rem % r->W[i];
+      rem /= r->W[i];
+    }
+    for (int i = 0; i < d; ++i) {
+      int64_t k = r->klo[i] + j[i];
+      a[i] = orc_cell_edge(g, i, k);
+      b[i] = orc_cell_edge(g, i, k + 1);
+      t += k * stride[i];
+    }
+    double vol = 1.0;
+    for (int i = 0; i < d; ++i) vol *= b[i] - a[i];
+    double L = 0.0, U = 0.0;
+    for (int64_t c = 0; c < n_cand; ++c) {
+      int64_t cr = c;
+      for (int i = d - 1; i >= 0; --i) {
+        int64_t ci = cr % G;
+        cr /= G;
+        m[i] = r->mlo[i] + ((double)ci + 0.5) * h[i];
+        zlo[i] = a[i] - (m[i] + 0.5 * h[i]);
+        zhi[i] = b[i] - (m[i] - 0.5 * h[i]);
+      }
+      double p, se;
+      orc_mc_cell_estimate(d, mc->inv_cov, norm, a, b, m, mc->n_samples, mc->samples, &p, &se);
+      double mv = orc_mc_shift_bound(d, sigma, norm, rho, vol, zlo, zhi);
+      double l = (p - mc->kappa * se) - mv, u = (p + mc->kappa * se) + mv;
+      if (c == 0 || l < L) L = l;
+      if (c == 0 || u > U) U = u;
+    }
+    target[slot] = (int32_t)t;
+    lo[slot] = L < 0.0 ? 0.0 : (L > 1.0 ? 1.0 : L);
+    hi[slot] = U < 0.0 ? 0.0 : (U > 1.0 ? 1.0 : U);
+  }
+  int64_t e = r->n_cells;
+  target[e] = ORC_T_OUT;
+  lo[e] = r->out_lo;
+  hi[e] = r->out_hi;
+  if (windowed) {
+    target[e + 1] = ORC_T_TAIL;
+    lo[e + 1] = r->tail_lo;
+    hi[e + 1] = r->tail_hi;
+  }
+}
+
+/*
+ * Validation shared by the Monte Carlo build: sizes, samples in [0, 1), a
+ * positive determinant that matches the inverse (det(P) * det_cov within
+ * 1e-6 of 1, det(P) from the same elimination as the marginals).
+ */
+static int mc_validate(int d, const orc_mc_noise *mc, double *sigma) {
+  if (!mc || !mc->inv_cov || !mc->samples || mc->n_samples < 1 || mc->grid_pts < 1) return -1;
+  if (!(mc->det_cov > 0.0) || !isfinite(mc->det_cov) || !(mc->kappa >= 0.0)) return -1;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      double x = mc->inv_cov[i * d + j];
+      if (!isfinite(x) || x != mc->inv_cov[j * d + i]) return -1;
+    }
+  for (int64_t k = 0; k < mc->n_samples * d; ++k)
+    if (!(mc->samples[k] >= 0.0 && mc->samples[k] < 1.0)) return -1;
+  if (orc_marginal_sigma(d, mc->inv_cov, sigma) != 0) return -1;
+  /* det(P) by elimination with partial pivoting */
+  double a[ORC_MAX_DIM][ORC_MAX_DIM], det = 1.0;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) a[i][j] = mc->inv_cov[i * d + j];
+  for (int col = 0; col < d; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < d; ++r)
+      if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
+    if (piv != col) {
+      for (int j = 0; j < d; ++j) {
+        double t = a[col][j];
+        a[col][j] = a[piv][j];
+        a[piv][j] = t;
+      }
+      det = -det;
+    }
+    det *= a[col][col];
+    for (int r = col + 1; r < d; ++r) {
+      double f = a[r][col] / a[col][col];
+      for (int j = col; j < d; ++j) a[r][j] -= f * a[col][j];
+    }
+  }
+  if (!(det > 0.0) || fabs(det * mc->det_cov - 1.0) > 1e-6) return -1;
+  return 0;
+}
+
+/*
+ * Build under correlated noise (Section 4.1 full covariance; Alg. 2 loop with
+ * Monte Carlo cell masses).  Same row layout as orc_build.  Returns 0, or -1
+ * for invalid arguments (see mc_validate), -2 on allocation failure.
+ */
+int orc_build_mc(const orc_system *sys, const orc_grid *g, const orc_inputs *in,
+                 const orc_mc_noise *mc, double k_sigma, const int64_t *rows,
+                 int64_t n_rows, orc_imdp *out) {
+  memset(out, 0, sizeof(*out));
+  int d = g->dim;
+  if (d < 1 || d > ORC_MAX_DIM || in->count < 1) return -1;
+  double sigma[ORC_MAX_DIM];
+  if (mc_validate(d, mc, sigma) != 0) return -1;
+  int64_t n_states = 1;
+  for (int i = 0; i < d; ++i) n_states *= g->n[i];
+  int64_t total_rows = n_states * in->count;
+  if (!rows) n_rows = total_rows;
+  int windowed = k_sigma > 0.0;
+  out->n_states = n_states;
+  out->n_inputs = in->count;
+  out->n_rows = n_rows;
+  out->dim = d;
+  out->windowed = windowed;
+  out->win = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_rows * 2 * d));
+  out->ot = (double *)malloc(sizeof(double) * (size_t)(n_rows * 4));
+  out->row_ptr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_rows + 1));
+  if (!out->win || !out->ot || !out->row_ptr) return -2;
+  row_geom r;
+  out->row_ptr[0] = 0;
+  for (int64_t q = 0; q < n_rows; ++q) {
+    int64_t row = rows ? rows[q] : q;
+    if (row < 0 || row >= total_rows) return -1;
+    int64_t s = row / in->count;
+    int32_t u = (int32_t)(row % in->count);
+    if (orc_mean_box(sys, g, in, s, u, r.mlo, r.mhi) != 0) return -1;
+    row_window(g, sigma, k_sigma, &r);
+    row_out_tail_union(g, sigma, k_sigma, &r);
+    for (int i = 0; i < d; ++i) {
+      out->win[q * 2 * d + i] = (int32_t)r.klo[i];
+      out->win[q * 2 * d + d + i] = (int32_t)r.W[i];
+    }
+    out->ot[q * 4 + 0] = r.out_lo;
+    out->ot[q * 4 + 1] = r.out_hi;
+    out->ot[q * 4 + 2] = r.tail_lo;
+    out->ot[q * 4 + 3] = r.tail_hi;
+    out->row_ptr[q + 1] = out->row_ptr[q] + r.n_cells + 1 + windowed;
+  }
+  int64_t ne = out->row_ptr[n_rows];
+  out->n_entries = ne;
+  out->target = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ne > 0 ? ne : 1));
+  out->lo = (double *)malloc(sizeof(double) * (size_t)(ne > 0 ? ne : 1));
+  out->hi = (double *)malloc(sizeof(double) * (size_t)(ne > 0 ? ne : 1));
+  if (!out->target || !out->lo || !out->hi) return -2;
+  for (int64_t q = 0; q < n_rows; ++q) {
+    int64_t row = rows ? rows[q] : q;
+    int64_t s = row / in->count;
+    int32_t u = (int32_t)(row % in->count);
+    orc_mean_box(sys, g, in, s, u, r.mlo, r.mhi);
+    row_window(g, sigma, k_sigma, &r);
+    row_out_tail_union(g, sigma, k_sigma, &r);
+    int64_t b = out->row_ptr[q];
+    row_entries_mc(g, mc, sigma, &r, windowed, out->target + b, out->lo + b, out->hi + b);
+  }
+  return 0;
+}

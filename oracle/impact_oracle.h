@@ -97,6 +97,33 @@ int orc_build(const orc_system *sys, const orc_grid *g, const orc_inputs *in,
               int64_t n_rows, orc_imdp *out);
 void orc_imdp_free(orc_imdp *m);
 
+/* ---- correlated noise by Monte Carlo integration (Section 4.1) ---- */
+/* Full covariance given as its inverse P and det(Cov); cell masses by plain
+   Monte Carlo over the caller's points of [0,1)^dim (shared by every cell);
+   min / max over the source cell from a G^dim lattice of candidate means,
+   each widened by a bound on the mass moved by the lattice spacing; kappa
+   standard errors of each estimate added on each side. */
+typedef struct {
+  const double *inv_cov; /* dim * dim, row-major, symmetric positive definite */
+  double det_cov;        /* determinant of the covariance (not of its inverse) */
+  int64_t n_samples;     /* >= 1 */
+  const double *samples; /* n_samples * dim points of [0, 1)^dim             */
+  int32_t grid_pts;      /* G >= 1 candidate means per dimension             */
+  double kappa;          /* >= 0 standard errors added on each side          */
+} orc_mc_noise;
+
+int orc_marginal_sigma(int d, const double *inv_cov, double *sigma);
+double orc_mc_cover_radius(int d, const double *inv_cov, const double *mlo, const double *mhi,
+                           int G);
+double orc_mc_shift_bound(int d, const double *sigma, double norm, double rho, double vol,
+                          const double *zlo, const double *zhi);
+void orc_mc_cell_estimate(int d, const double *inv_cov, double norm, const double *a,
+                          const double *b, const double *m, int64_t n, const double *samples,
+                          double *p, double *se);
+int orc_build_mc(const orc_system *sys, const orc_grid *g, const orc_inputs *in,
+                 const orc_mc_noise *mc, double k_sigma, const int64_t *rows,
+                 int64_t n_rows, orc_imdp *out);
+
 /* ---- labelling ---- */
 int orc_label(const orc_grid *g, int32_t n_target, const double *target_boxes,
               int32_t n_avoid, const double *avoid_boxes, int8_t *cls);

@@ -133,6 +133,42 @@ def random_linear(rng, d=None):
     return system, spec
 
 
+def mc_points(n, d, seed=SEED + 7, kind="random"):
+    """Points of [0, 1)^d for the Monte Carlo cell integrals of correlated noise.
+
+    "random": n seeded uniform points.  "lattice": the midpoints of a tensor
+    grid with m = round(n^(1/d)) points per dimension (m^d points, first
+    coordinate slowest), a deterministic product midpoint rule.
+    """
+    if kind == "lattice":
+        m = max(1, int(round(n ** (1.0 / d))))
+        ax = (np.arange(m, dtype=np.float64) + 0.5) / m
+        return np.array(list(itertools.product(*([ax] * d))), dtype=np.float64).reshape(-1, d)
+    rng = np.random.default_rng(seed)
+    return rng.random((n, d))
+
+
+def robot2d_correlated(n=(40, 40), samples=256, grid_pts=2, kappa=3.0, corr=0.5, seed=SEED + 7):
+    """The paper's 2D robot with correlated noise (stand-in for a full-covariance
+    run, Section 4.1): x+ = x + 0.5 u + w on [-10,10]^2, 40x40 cells of width 0.5,
+    u in {-1,0,1}^2, Cov = 0.75 [[1, corr], [corr, 1]] (the study's variance,
+    with correlation ``corr``), +-6 marginal sigma windows; target [5,7]^2,
+    avoid [-2,2]^2, eps 1e-8.  Returns (system, spec, mc) with mc the inverse
+    covariance, its determinant and ``samples`` seeded uniform points,
+    ``grid_pts`` candidate means per dimension and ``kappa`` standard errors.
+    """
+    cov = 0.75 * np.array([[1.0, corr], [corr, 1.0]])
+    system = dict(kind="affine", A=np.eye(2), B=0.5 * np.eye(2), c=np.zeros(2),
+                  lb=[-10.0, -10.0], ub=[10.0, 10.0], n=list(n),
+                  inputs=_grid_inputs([-1.0, 0.0, 1.0], [-1.0, 0.0, 1.0]),
+                  sigma=[math.sqrt(0.75)] * 2, k_sigma=6.0)
+    spec = dict(kind="reach_avoid", target=[[[5.0, 5.0], [7.0, 7.0]]],
+                avoid=[[[-2.0, -2.0], [2.0, 2.0]]], eps=1e-8, max_sweeps=100000)
+    mc = dict(inv_cov=np.linalg.inv(cov), det_cov=float(np.linalg.det(cov)),
+              samples=mc_points(samples, 2, seed=seed), grid_pts=grid_pts, kappa=kappa)
+    return system, spec, mc
+
+
 def batched(count=384, seed=SEED):
     rng = np.random.default_rng(seed)
     return [random_linear(rng) for _ in range(count)]
