@@ -142,6 +142,51 @@ int impact_build_imdp(const impact_system *sys, const impact_grid *grid,
                       const impact_window *window, const impact_device *dev,
                       impact_imdp **out);
 
+/* Correlated Gaussian noise (Section 4.1, full covariance): the covariance is
+ * given by its inverse and its determinant, and cell masses are computed by
+ * Monte Carlo integration.  Host pointers, read during the call only.
+ *   inv_cov  : dim_x * dim_x, row-major, exactly symmetric, positive definite
+ *   det_cov  : det(Cov) > 0 (of the covariance, not of its inverse); must
+ *              agree with inv_cov (det(inv_cov) * det_cov within 1e-6 of 1)
+ *   n_samples: N >= 1 points, samples: N * dim_x coordinates in [0, 1), the
+ *              same points serving every cell (random or quasi-random)
+ *   grid_pts : G >= 1 candidate means per dimension, G^dim_x <= 4096
+ *   kappa    : >= 0 standard errors added to each side of every estimate */
+typedef struct {
+  const double *inv_cov;
+  double det_cov;
+  int64_t n_samples;
+  const double *samples;
+  int32_t grid_pts;
+  double kappa;
+} impact_mc_noise;
+
+/*
+ * impact_build_imdp for correlated noise, the cell masses of Def. 3.1 by Monte
+ * Carlo integration (Section 4.1).  For a window cell [a, b] and a mean m the
+ * estimate is vol * mean_k f(a + (b - a) r_k), f the N(m, Cov) density and r_k
+ * the caller's points, with standard error vol * s / sqrt(N) (s the sample
+ * standard deviation, 0 for N = 1).  The min / max over the source cell are
+ * taken over G^dim candidate means, the centres of a G-way split of the mean
+ * box, each estimate widened by kappa standard errors and by a bound on how
+ * far the cell's mass can move between the candidate and any mean within half
+ * a lattice spacing (the smaller of the total-variation distance and the
+ * integrated mean derivative); bounds are clamped into [0, 1].  Windows use
+ * the marginal standard deviations sqrt(Cov_ii); OUT and TAIL are union
+ * bounds over dimensions of the marginal exit masses.  The bounds hold for
+ * every point of the source cell up to the Monte Carlo error, which kappa
+ * covers statistically.  Storage is BOUNDS (AUTO selects it); the handle
+ * iterates like any other.
+ * Errors: as impact_build_imdp, plus E_INVAL for a null noise, samples or
+ * inv_cov, N < 1, G < 1, kappa < 0, a sample outside [0, 1), a non-symmetric,
+ * singular or non-positive-definite inverse covariance, a determinant that
+ * does not match it, or FACTORS storage; E_UNSUPPORTED for G^dim > 4096.
+ */
+int impact_build_imdp_mc(const impact_system *sys, const impact_grid *grid,
+                         const impact_inputs *inputs, const impact_mc_noise *noise,
+                         const impact_window *window, const impact_device *dev,
+                         impact_imdp **out);
+
 /* Finite disturbance set W-hat of an affine system, x+ = A x + B u + D w + c
  * + noise (eq. (5.1); Alg. 2 iterates over it like over the inputs).  Host
  * pointers, row-major: values count x dim_w, D dim_x x dim_w. */

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libimpact.so")
 SOURCES = ["sweep_sb_d3.hip", "sweep_sb_d2.hip", "sweep_sb_d5.hip", "sweep_sb_d0.hip",
-           "sweep.hip", "sweep_sel.hip", "abi.hip", "build.hip", "sweep_sb.hip", "mq.hip", "probe.hip"]
+           "sweep.hip", "sweep_sel.hip", "abi.hip", "build.hip", "build_mc.hip", "sweep_sb.hip", "mq.hip", "probe.hip"]
 
 
 def hipcc() -> str:

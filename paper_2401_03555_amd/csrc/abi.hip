@@ -633,9 +633,20 @@ const char* impact_version(void) { return "impact-gfx950 0.1"; }
 
 // Build n systems with one launch of each construction kernel over all of
 // their rows (Alg. 2's parallel loop spans every system).
+// Correlated noise of a Monte Carlo build, checked and prepared on the host.
+struct McSetup {
+  double P[IMPACT_MAX_DIM * IMPACT_MAX_DIM];  // inverse covariance, d x d row-major
+  double sigma[IMPACT_MAX_DIM];               // marginal standard deviations
+  double norm, kappa;
+  int32_t G;
+  int64_t N;
+  const double* samples;  // host, N x d
+};
+
 static int build_many(int32_t n, const impact_system* sys, const impact_grid* grid,
                       const impact_inputs* inputs, const impact_noise* noise,
-                      const impact_window* window, const impact_device* dev, impact_imdp** out) {
+                      const impact_window* window, const impact_device* dev, impact_imdp** out,
+                      const McSetup* mc = nullptr) {
   for (int32_t i = 0; i < n; ++i) out[i] = nullptr;
   for (int32_t i = 0; i < n; ++i) {
     const int rc = validate_build(&sys[i], &grid[i], &inputs[i], &noise[i], &window[i]);
@@ -661,6 +672,15 @@ static int build_many(int32_t n, const impact_system* sys, const impact_grid* gr
   int32_t d_max = 1;
   for (int32_t i = 0; i < n; ++i) {
     fill_params(hp[i], &sys[i], &grid[i], &inputs[i], &noise[i], &window[i]);
+    if (mc) {
+      const int d = hp[i].d;
+      hp[i].mc = 1;
+      hp[i].mc_grid = mc->G;
+      hp[i].mc_n = mc->N;
+      hp[i].mc_norm = mc->norm;
+      hp[i].mc_kappa = mc->kappa;
+      for (int k = 0; k < d * d; ++k) hp[i].mc_P[k] = mc->P[k];
+    }
     hp[i].row_base = row_base[i];
     hp[i].state_base = state_base[i];
     hp[i].win_base = win_total;
@@ -684,6 +704,8 @@ static int build_many(int32_t n, const impact_system* sys, const impact_grid* gr
     st->win = st->own<int32_t>(win_total);
     st->ot = st->own<double4>(R);
     st->row_off = st->own<int64_t>(R + 1);
+    double* d_samples = mc ? st->own<double>(mc->N * hp[0].d) : nullptr;
+    if (mc) hp[0].mc_samples = d_samples;
     ScratchT<Storage> tmp(st);
     int64_t* cnt = tmp.template get<int64_t>(R);
     int32_t* maxima = tmp.template get<int32_t>(2 * (int64_t)n);
@@ -707,6 +729,9 @@ static int build_many(int32_t n, const impact_system* sys, const impact_grid* gr
                            hipMemcpyHostToDevice, st->st));
     HIP_TRY(hipMemcpyAsync(st->d_sys, hp.data(), sizeof(SysParams) * n, hipMemcpyHostToDevice,
                            st->st));
+    if (mc)
+      HIP_TRY(hipMemcpyAsync(d_samples, mc->samples, sizeof(double) * mc->N * hp[0].d,
+                             hipMemcpyHostToDevice, st->st));
     HIP_TRY(hipMemcpyAsync(d_row_base, row_base.data(), sizeof(int64_t) * (n + 1),
                            hipMemcpyHostToDevice, st->st));
     HIP_TRY(hipMemcpyAsync(d_state_base, state_base.data(), sizeof(int64_t) * (n + 1),
@@ -748,7 +773,12 @@ static int build_many(int32_t n, const impact_system* sys, const impact_grid* gr
       st->fac = st->own<double2>(fac_total);
     else
       st->ent = st->own<double2>(total);
-    HIP_TRY(launch_expand(T, R, st->win, st->row_off, st->ent, st->fac, fs_max, d_max, st->st));
+    if (mc)
+      HIP_TRY(launch_mc_entries(st->d_sys, hp[0].d, R, total, st->win, st->row_off, st->ent,
+                                st->st));
+    else
+      HIP_TRY(launch_expand(T, R, st->win, st->row_off, st->ent, st->fac, fs_max, d_max,
+                            st->st));
     HIP_TRY(hipEventRecord(e1, st->st));
     HIP_TRY(launch_state_box_max(T, S, st->win, boxmax, st->st));
     HIP_TRY(hipMemcpyAsync(bm.data(), boxmax, sizeof(unsigned long long) * n,
@@ -811,6 +841,113 @@ int impact_build_imdp(const impact_system* sys, const impact_grid* grid,
   *out = nullptr;
   if (!sys || !grid || !inputs || !noise || !window) return fail(IMPACT_E_INVAL, "null argument");
   return build_many(1, sys, grid, inputs, noise, window, dev, out);
+}
+
+// Marginal standard deviations sqrt(Cov_ii) of Cov = P^-1: Gauss-Jordan
+// elimination of [P | I] with partial pivoting.  False for a singular P or a
+// non-positive diagonal of the inverse.
+static bool mc_marginals(int d, const double* P, double* sigma) {
+  double a[IMPACT_MAX_DIM][2 * IMPACT_MAX_DIM];
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < 2 * d; ++j) a[i][j] = j < d ? P[i * d + j] : (j - d == i ? 1.0 : 0.0);
+  for (int col = 0; col < d; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < d; ++r)
+      if (std::fabs(a[r][col]) > std::fabs(a[piv][col])) piv = r;
+    if (!(std::fabs(a[piv][col]) > 0.0)) return false;
+    if (piv != col)
+      for (int j = 0; j < 2 * d; ++j) std::swap(a[col][j], a[piv][j]);
+    const double pv = a[col][col];
+    for (int j = 0; j < 2 * d; ++j) a[col][j] /= pv;
+    for (int r = 0; r < d; ++r) {
+      if (r == col) continue;
+      const double f = a[r][col];
+      if (f == 0.0) continue;
+      for (int j = 0; j < 2 * d; ++j) a[r][j] -= f * a[col][j];
+    }
+  }
+  for (int i = 0; i < d; ++i) {
+    const double v = a[i][d + i];
+    if (!(v > 0.0) || !std::isfinite(v)) return false;
+    sigma[i] = std::sqrt(v);
+  }
+  return true;
+}
+
+// det(P) by forward elimination with partial pivoting.
+static double mc_det(int d, const double* P) {
+  double a[IMPACT_MAX_DIM][IMPACT_MAX_DIM], det = 1.0;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) a[i][j] = P[i * d + j];
+  for (int col = 0; col < d; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < d; ++r)
+      if (std::fabs(a[r][col]) > std::fabs(a[piv][col])) piv = r;
+    if (piv != col) {
+      for (int j = 0; j < d; ++j) std::swap(a[col][j], a[piv][j]);
+      det = -det;
+    }
+    det *= a[col][col];
+    if (a[col][col] == 0.0) return 0.0;
+    for (int r = col + 1; r < d; ++r) {
+      const double f = a[r][col] / a[col][col];
+      for (int j = col; j < d; ++j) a[r][j] -= f * a[col][j];
+    }
+  }
+  return det;
+}
+
+int impact_build_imdp_mc(const impact_system* sys, const impact_grid* grid,
+                         const impact_inputs* inputs, const impact_mc_noise* noise,
+                         const impact_window* window, const impact_device* dev,
+                         impact_imdp** out) {
+  g_err.clear();
+  if (!out) return fail(IMPACT_E_INVAL, "out is null");
+  *out = nullptr;
+  if (!sys || !grid || !inputs || !noise || !window) return fail(IMPACT_E_INVAL, "null argument");
+  const int d = grid->dim;
+  if (d < 1 || d > IMPACT_MAX_DIM) return fail(IMPACT_E_INVAL, "grid.dim must be in [1, 8]");
+  if (!noise->inv_cov || !noise->samples) return fail(IMPACT_E_INVAL, "inv_cov or samples is null");
+  if (noise->n_samples < 1) return fail(IMPACT_E_INVAL, "n_samples must be >= 1");
+  if (noise->grid_pts < 1) return fail(IMPACT_E_INVAL, "grid_pts must be >= 1");
+  if (!std::isfinite(noise->kappa) || noise->kappa < 0.0)
+    return fail(IMPACT_E_INVAL, "kappa must be finite and >= 0");
+  if (!std::isfinite(noise->det_cov) || !(noise->det_cov > 0.0))
+    return fail(IMPACT_E_INVAL, "det_cov must be finite and > 0");
+  if (window->storage == IMPACT_STORE_FACTORS)
+    return fail(IMPACT_E_INVAL, "correlated noise has no per-dimension factors (use BOUNDS)");
+  int64_t n_cand = 1;
+  for (int i = 0; i < d; ++i) {
+    n_cand *= noise->grid_pts;
+    if (n_cand > 4096) return fail(IMPACT_E_UNSUPPORTED, "grid_pts^dim must be at most 4096");
+  }
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      const double x = noise->inv_cov[i * d + j];
+      if (!std::isfinite(x) || x != noise->inv_cov[j * d + i])
+        return fail(IMPACT_E_INVAL, "inv_cov must be finite and symmetric");
+    }
+  for (int64_t k = 0; k < noise->n_samples * d; ++k)
+    if (!(noise->samples[k] >= 0.0 && noise->samples[k] < 1.0))
+      return fail(IMPACT_E_INVAL, "samples must lie in [0, 1)");
+  McSetup mc{};
+  if (!mc_marginals(d, noise->inv_cov, mc.sigma))
+    return fail(IMPACT_E_INVAL, "inv_cov is singular or not positive definite");
+  const double detP = mc_det(d, noise->inv_cov);
+  if (!(detP > 0.0) || std::fabs(detP * noise->det_cov - 1.0) > 1e-6)
+    return fail(IMPACT_E_INVAL, "det_cov does not match inv_cov");
+  for (int k = 0; k < d * d; ++k) mc.P[k] = noise->inv_cov[k];
+  double t = 1.0;
+  for (int i = 0; i < d; ++i) t *= 2.0 * kPi;
+  mc.norm = 1.0 / std::sqrt(t * noise->det_cov);
+  mc.kappa = noise->kappa;
+  mc.G = noise->grid_pts;
+  mc.N = noise->n_samples;
+  mc.samples = noise->samples;
+  const impact_noise marg{mc.sigma};
+  impact_window w2 = *window;
+  w2.storage = IMPACT_STORE_BOUNDS;
+  return build_many(1, sys, grid, inputs, &marg, &w2, dev, out, &mc);
 }
 
 int impact_build_imdp_dist(const impact_system* sys, const impact_grid* grid,

@@ -52,7 +52,10 @@ __global__ __launch_bounds__(kGeomThreads) void k_row_geom(BuildTable T, int64_t
       wr[d + i] = W[i];
     }
     double4 o;
-    out_tail(p, mlo, mhi, klo, W, &o);
+    if (p.mc)
+      out_tail_union(p, mlo, mhi, klo, W, &o);
+    else
+      out_tail(p, mlo, mhi, klo, W, &o);
     ot[r] = o;
     cnt[r] = ncell;
     const int64_t len = ncell + 1 + p.windowed;

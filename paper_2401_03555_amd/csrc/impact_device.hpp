@@ -52,6 +52,14 @@ struct SysParams {
   int64_t win_base;         // offset of its window table (int32 elements)
   int64_t fac_base;         // offset of its factor table (double2 elements)
   int32_t fs, pad1;         // factor stride (max over its rows of sum_i W_i)
+  // Correlated noise with Monte Carlo cell masses (mc = 1); sigma[] then holds
+  // the marginal standard deviations sqrt(Cov_ii).
+  int32_t mc, mc_grid;      // flag; candidate means per dimension (G)
+  int64_t mc_n;             // sample points
+  double mc_norm;           // 1 / sqrt((2 pi)^d det Cov)
+  double mc_kappa;          // standard errors added on each side
+  const double* mc_samples; // mc_n x d points of [0, 1) (device)
+  double mc_P[kMaxDim * kMaxDim];  // inverse covariance, row-major (d x d)
 };
 
 // Instances of one build: row r belongs to the last i with row_base[i] <= r.
@@ -267,6 +275,51 @@ __device__ inline void out_tail(const SysParams& p, const double* mlo, const dou
     if (t > cap) t = cap;
     if (t < 0.0) t = 0.0;
     tail_hi = t;
+  }
+  *ot = make_double4(out_lo, out_hi, 0.0, tail_hi);
+}
+
+// OUT and TAIL bounds of one row under correlated noise: union bounds over
+// the dimensions of the marginal exit masses (valid for any correlation).
+// OUT_lo = max_i min q_i, OUT_hi = min(1, sum_i max q_i); TAIL_hi =
+// min(1 - OUT_lo, sum_i max exit mass through the window's interior sides).
+__device__ inline void out_tail_union(const SysParams& p, const double* mlo, const double* mhi,
+                                      const int32_t* klo, const int32_t* W, double4* ot) {
+  double out_lo = 0.0, out_hi = 0.0, tail = 0.0;
+  IMPACT_FOR_DIMS(i, p.d) {
+    double lb = p.lb[i], ub = p.ub[i], sg = p.sigma[i];
+    double qa = exit_prob(lb, ub, mlo[i], sg);
+    double qb = exit_prob(lb, ub, mhi[i], sg);
+    double qmax = qa > qb ? qa : qb;
+    double ctr = 0.5 * (lb + ub);
+    double mc = ctr < mlo[i] ? mlo[i] : (ctr > mhi[i] ? mhi[i] : ctr);
+    double qmin = exit_prob(lb, ub, mc, sg);
+    if (qmin > qmax) qmin = qmax;
+    if (qmin > out_lo) out_lo = qmin;
+    out_hi += qmax;
+    if (p.windowed) {
+      double pw;
+      if (W[i] == 0) {
+        pw = 1.0;
+      } else {
+        int64_t khi = (int64_t)klo[i] + W[i] - 1;
+        bool has_a = klo[i] > 0, has_b = khi < p.n[i] - 1;
+        double A = cell_edge(p, i, klo[i]);
+        double B = cell_edge(p, i, khi + 1);
+        double pa = window_exit_prob(A, has_a, B, has_b, mlo[i], sg);
+        double pb = window_exit_prob(A, has_a, B, has_b, mhi[i], sg);
+        pw = pa > pb ? pa : pb;
+      }
+      tail += pw;
+    }
+  }
+  if (out_hi > 1.0) out_hi = 1.0;
+  double tail_hi = 0.0;
+  if (p.windowed) {
+    double cap = 1.0 - out_lo;
+    if (tail > cap) tail = cap;
+    if (tail < 0.0) tail = 0.0;
+    tail_hi = tail;
   }
   *ot = make_double4(out_lo, out_hi, 0.0, tail_hi);
 }

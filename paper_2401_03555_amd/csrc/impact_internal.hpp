@@ -110,6 +110,9 @@ hipError_t launch_row_geom(const BuildTable& T, int64_t n_rows, int32_t* win, do
 hipError_t launch_expand(const BuildTable& T, int64_t n_rows, const int32_t* win,
                          const int64_t* row_off, double2* ent, double2* fac, int32_t fs_max,
                          int32_t d_max, hipStream_t st);
+hipError_t launch_mc_entries(const SysParams* sys, int32_t d, int64_t n_rows, int64_t n_ent,
+                             const int32_t* win, const int64_t* row_off, double2* ent,
+                             hipStream_t st);
 hipError_t launch_export(const SysParams* sys, int64_t row0, int64_t nrows, const int32_t* win,
                          const double4* ot, const int64_t* row_off, const double2* ent,
                          const double2* fac, int32_t fs, int32_t d, int32_t windowed,

@@ -28,7 +28,8 @@ EXPORTS = ["impact_build_imdp", "impact_interval_iterate", "impact_last_iter_inf
            "impact_set_sweep_modes",
            "impact_build_imdp_batch", "impact_mq_create", "impact_mq_submit", "impact_mq_run",
            "impact_mq_poll", "impact_mq_query_info", "impact_mq_last_error", "impact_mq_free",
-           "impact_probe_fp64_fma", "impact_build_imdp_dist", "impact_interval_iterate_noalloc"]
+           "impact_probe_fp64_fma", "impact_build_imdp_dist", "impact_interval_iterate_noalloc",
+           "impact_build_imdp_mc"]
 SWEEP_MODES = {"auto": 0, "per_row": 1, "state_box": 2}
 
 _pd = C.POINTER(C.c_double)
@@ -51,6 +52,11 @@ class Inputs(C.Structure):
 
 class Noise(C.Structure):
     _fields_ = [("sigma", _pd)]
+
+
+class McNoise(C.Structure):
+    _fields_ = [("inv_cov", _pd), ("det_cov", C.c_double), ("n_samples", C.c_int64),
+                ("samples", _pd), ("grid_pts", C.c_int32), ("kappa", C.c_double)]
 
 
 class Disturbances(C.Structure):
@@ -164,6 +170,10 @@ def lib():
                                              C.POINTER(Disturbances), C.POINTER(Noise),
                                              C.POINTER(Window), C.POINTER(Device),
                                              C.POINTER(C.c_void_p)]
+        L.impact_build_imdp_mc.restype = C.c_int
+        L.impact_build_imdp_mc.argtypes = [C.POINTER(System), C.POINTER(Grid), C.POINTER(Inputs),
+                                           C.POINTER(McNoise), C.POINTER(Window),
+                                           C.POINTER(Device), C.POINTER(C.c_void_p)]
         L.impact_probe_fp64_fma.restype = C.c_int
         L.impact_probe_fp64_fma.argtypes = [C.c_int64, C.c_int32, _pd, C.c_void_p]
         _lib = L
@@ -366,6 +376,30 @@ def build_imdp(system, k_sigma=None, storage="bounds", stream=None, timing=False
         _check(lib().impact_build_imdp(C.byref(m.sys), C.byref(m.grid), C.byref(m.inp),
                                        C.byref(m.noise), C.byref(w), C.byref(dev.struct),
                                        C.byref(h)))
+    imdp = Imdp(h.value, dev)
+    if timing:
+        imdp.set_timing(True)
+    if sweep_mode != "auto":
+        imdp.set_sweep_mode(sweep_mode)
+    return imdp
+
+
+def build_imdp_mc(system, mc, k_sigma=None, stream=None, timing=False, sweep_mode="auto"):
+    """Build the abstraction of ``system`` under correlated noise (Monte Carlo
+    cell masses).  ``mc``: dict with ``inv_cov`` (d x d), ``det_cov``,
+    ``samples`` (N x d points of [0, 1)), ``grid_pts`` and ``kappa``;
+    ``system["sigma"]`` is not used."""
+    m = _Marshal(dict(system, sigma=np.ones(len(system["lb"]))))
+    P, X = _f64(mc["inv_cov"]), _f64(mc["samples"])
+    d = len(m.lb)
+    nz = McNoise(_dptr(P), float(mc["det_cov"]), X.size // d, _dptr(X), int(mc["grid_pts"]),
+                 float(mc["kappa"]))
+    dev = _TorchDevice(stream)
+    w = Window(float(system.get("k_sigma", 0.0) if k_sigma is None else k_sigma),
+               STORAGE["bounds"])
+    h = C.c_void_p()
+    _check(lib().impact_build_imdp_mc(C.byref(m.sys), C.byref(m.grid), C.byref(m.inp),
+                                      C.byref(nz), C.byref(w), C.byref(dev.struct), C.byref(h)))
     imdp = Imdp(h.value, dev)
     if timing:
         imdp.set_timing(True)
