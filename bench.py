@@ -47,8 +47,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="room5d",
-                    choices=["unicycle3d", "robot2d", "room5d"])
-    ap.add_argument("--components", default="unicycle3d",
+                    choices=["unicycle3d", "robot2d", "room5d", "robot2d_correlated"])
+    ap.add_argument("--components", default="unicycle3d,robot2d_correlated",
                     help="comma list of further workloads measured beside the headline one")
     ap.add_argument("--no-served", action="store_true",
                     help="skip the bounded served leg of the default line")
@@ -79,16 +79,25 @@ def parse():
     return ap.parse_args()
 
 
+WORKLOADS = {
+    "unicycle3d": "3D unicycle reach-avoid, 50x50x24 cells, 20 inputs, +-6 sigma windows, "
+                  "eps 1e-8",
+    "robot2d": "2D robot reach-avoid, 20x20 cells, 9 inputs, dense rows, eps 1e-8",
+    "room5d": "5D room safety, 10^5 cells, 4 inputs, +-6 sigma windows, 50 sweeps per pass",
+    "robot2d_correlated": "2D robot reach-avoid with correlated noise (Cov = 0.75 [[1, .5], "
+                          "[.5, 1]]), 40x40 cells, 9 inputs, +-6 marginal sigma windows, "
+                          "Monte Carlo cell masses (256 points, 2x2 candidate means, "
+                          "3 standard errors), eps 1e-8",
+}
+
+
 def workload(name):
+    """(system, spec, description, Monte Carlo noise or None) of a workload."""
     from paper_2401_03555_amd import workloads as W
-    system, spec = getattr(W, name)()
-    desc = {
-        "unicycle3d": "3D unicycle reach-avoid, 50x50x24 cells, 20 inputs, +-6 sigma windows, "
-                      "eps 1e-8",
-        "robot2d": "2D robot reach-avoid, 20x20 cells, 9 inputs, dense rows, eps 1e-8",
-        "room5d": "5D room safety, 10^5 cells, 4 inputs, +-6 sigma windows, 50 sweeps per pass",
-    }[name]
-    return system, spec, desc
+    out = getattr(W, name)()
+    system, spec = out[0], out[1]
+    mc = out[2] if len(out) > 2 else None
+    return system, spec, WORKLOADS[name], mc
 
 
 def algorithmic_bytes(imdp, policy, n_states, d):
@@ -118,18 +127,29 @@ def algorithmic_bytes(imdp, policy, n_states, d):
 FP64_PEAK_TFLOPS = 78.6
 
 
-def kernel_source_hash():
-    """Digest of what the state-box sweep kernels are compiled from (their
-    sources, the headers they include and the build flags), comments and
-    blank space removed: identifies the build whose hardware counters are
-    recorded under profiles/, and ignores edits to documentation only."""
+# the sources each recorded kernel family is compiled from, besides the C
+# header and the build flags
+KERNEL_SOURCES = {
+    "k_sweep_sb": [f"sweep_sb_d{d}.hip" for d in (0, 2, 3, 5)] + [
+        "sweep_sb.hpp", "sweep_common.hpp", "impact_internal.hpp", "impact_device.hpp"],
+    "k_sweep_sel": ["sweep_sel.hip", "sweep_common.hpp", "impact_internal.hpp",
+                    "impact_device.hpp"],
+    "k_mc_entries": ["build_mc.hip", "impact_internal.hpp", "impact_device.hpp"],
+    "build": ["build.hip", "impact_internal.hpp", "impact_device.hpp"],
+}
+
+
+def kernel_source_hash(kernel="k_sweep_sb"):
+    """Digest of what a kernel family is compiled from (its sources, the
+    headers they include and the build flags), comments and blank space
+    removed: identifies the build whose hardware counters are recorded under
+    profiles/, and ignores edits to documentation only."""
     import hashlib
     import re
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2401_03555_amd")
     csrc = os.path.join(pkg, "csrc")
-    names = [f"sweep_sb_d{d}.hip" for d in (0, 2, 3, 5)] + [
-        "sweep_sb.hpp", "sweep_common.hpp", "impact_internal.hpp", "impact_device.hpp"]
+    names = KERNEL_SOURCES.get(kernel, KERNEL_SOURCES["k_sweep_sb"])
     files = [os.path.join(csrc, n) for n in names] + [
         os.path.join(ROOT, "include", "impact.h"), os.path.join(pkg, "build_lib.py")]
     for f in files:
@@ -146,7 +166,7 @@ def _recorded(tag, field, kernel, storage, workload):
     """A per-launch figure of ``kernel`` recorded under profiles/ (lines
     ``<tag>: key=value ...``) for this kernel build, or None."""
     import glob
-    src = kernel_source_hash()
+    src = kernel_source_hash(kernel)
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(f) as fh:
             for line in fh:
@@ -177,10 +197,45 @@ def recorded_valu(kernel, storage, workload):
     return _recorded("valu", "valu_per_launch", kernel, storage, workload)
 
 
-def recorded_build_flops(storage, workload):
-    """FP64 operations per build (k_row_geom + k_expand) counted by the SQ
-    counters recorded under profiles/ (lines ``fp64: ...``), or None."""
-    return _recorded("fp64", "flops_per_build", "build", storage, workload)
+def recorded_build_flops(storage, workload, kernel="build"):
+    """FP64 operations per build (k_row_geom + k_expand, or the Monte Carlo
+    entry kernel) counted by the SQ counters recorded under profiles/ (lines
+    ``fp64: ...``), or None."""
+    return _recorded("fp64", "flops_per_build", kernel, storage, workload)
+
+
+def mc_build_roofline(imdp, d, mc, workload):
+    """The Monte Carlo construction against the FP64 vector units that bind it.
+
+    Evaluations: one density evaluation per (window cell, candidate mean,
+    sample point).  Algorithmic FP64 work per evaluation, besides its exp:
+    the sample point (2d), the offset from the mean (d), the quadratic form
+    (2d^2 + 2d), the scalings (2) and the two running sums (3).  The
+    fraction of the FP64 vector peak uses the FP64 instructions counted by the
+    SQ counters of this kernel build (exp included) when they are recorded.
+    """
+    info = imdp.info()
+    ex = imdp.export_rows(0, info["n_rows"], entries=False)
+    cells = int(ex["counts"].sum())
+    n_cand = int(mc["grid_pts"]) ** d
+    n_pts = len(mc["samples"])
+    evals = cells * n_cand * n_pts
+    t = info["build_ms"] * 1e-3
+    per_eval = 2 * d * d + 5 * d + 5
+    flops = recorded_build_flops("bounds", workload, "k_mc_entries")
+    return {
+        "kernels": "k_row_geom + scan + k_mc_entries",
+        "bound": "alu",
+        "build_ms": info["build_ms"],
+        "entries_per_s": info["n_entries"] / t,
+        "evaluations": evals,
+        "evals_per_s": evals / t,
+        "algorithmic_flops_per_eval": per_eval,
+        "algorithmic_tflops": evals * per_eval / t / 1e12,
+        "fp64_counted_tflops": None if flops is None else flops / t / 1e12,
+        "fp64_frac": None if flops is None else flops / t / (FP64_PEAK_TFLOPS * 1e12),
+        "peak_tflops": FP64_PEAK_TFLOPS,
+    }
 
 
 def build_roofline(imdp, d, workload):
@@ -228,7 +283,8 @@ def build_roofline(imdp, d, workload):
 # states of the bounded CPU-oracle sample per workload (about 10-15 s of
 # single-core oracle work: its build of the sample's rows and one sweep of
 # each pass over them)
-CPU_SAMPLE_STATES = {"room5d": 12000, "unicycle3d": 30000, "robot2d": 400}
+CPU_SAMPLE_STATES = {"room5d": 12000, "unicycle3d": 30000, "robot2d": 400,
+                     "robot2d_correlated": 200}
 
 
 def cpu_worker(job):
@@ -241,14 +297,19 @@ def cpu_worker(job):
     import numpy as np
     import oracle
     from paper_2401_03555_amd import workloads as W
-    system, spec = getattr(W, job["workload"])()
+    out = getattr(W, job["workload"])()
+    system, spec = out[0], out[1]
+    mc = out[2] if len(out) > 2 else None
     s0, s1 = job["states"]
     nu = len(system["inputs"])
     N = int(np.prod(system["n"]))
     states = np.arange(s0, s1, dtype=np.int64)
     rows = (states[:, None] * nu + np.arange(nu)[None, :]).ravel()
     t0 = time.perf_counter()
-    m = oracle.build(system, system["k_sigma"], rows=rows)
+    if mc is not None:
+        m = oracle.build_mc(system, mc, system["k_sigma"], rows=rows)
+    else:
+        m = oracle.build(system, system["k_sigma"], rows=rows)
     t_build = time.perf_counter() - t0
     counts = np.zeros(N * nu, dtype=np.int64)
     counts[rows] = np.diff(m["row_ptr"])
@@ -537,10 +598,14 @@ def measure_plain(args, tuner, name, steps, warmup):
     roofline of its policy-pass sweep from one instrumented step."""
     import torch
     from paper_2401_03555_amd import impact
-    system, spec, desc = workload(name)
+    system, spec, desc, mc = workload(name)
     max_sweeps = spec["max_sweeps"]
     storage, modes, choice = args.storage, (args.sweep_mode, args.sweep_mode), None
-    if "tuned" in (args.storage, args.sweep_mode):
+    if mc is not None:
+        # correlated noise: stored bounds only; the library's per-pass order
+        storage = "bounds"
+        modes = tuple("auto" if m == "tuned" else m for m in modes)
+    elif "tuned" in (args.storage, args.sweep_mode):
         # measured per-sweep times, weighted by the sweeps each pass runs on
         # this query (from one untimed solve under the equal-weight choice)
         choice = tuner.choose(system)
@@ -556,7 +621,10 @@ def measure_plain(args, tuner, name, steps, warmup):
     print(f"# {name}: storage {storage}, sweep modes {modes}", file=sys.stderr, flush=True)
 
     def step(timing=False):
-        imdp = impact.build_imdp(system, storage=storage, timing=timing)
+        if mc is not None:
+            imdp = impact.build_imdp_mc(system, mc, timing=timing)
+        else:
+            imdp = impact.build_imdp(system, storage=storage, timing=timing)
         imdp.set_sweep_modes(*modes)
         r = imdp.iterate(spec, max_sweeps=max_sweeps)
         return imdp, r
@@ -608,7 +676,8 @@ def measure_plain(args, tuner, name, steps, warmup):
         "iter_updates_per_s": updates / (iinfo["iterate_ms"] * 1e-3),
         "iterate_ms": iinfo["iterate_ms"],
         "fixed_pass_launch_ms": iinfo["launch_ms"][1] / max(1, iinfo["launches"][1]),
-        "build_roofline": build_roofline(imdp, d, name),
+        "build_roofline": (build_roofline(imdp, d, name) if mc is None
+                           else mc_build_roofline(imdp, d, mc, name)),
         "roofline": {
             "kernel": kernel + " policy pass (all inputs per SAFE state)",
             "bound": "hbm",
