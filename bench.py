@@ -52,9 +52,9 @@ def parse():
                     help="comma list of further workloads measured beside the headline one")
     ap.add_argument("--no-served", action="store_true",
                     help="skip the bounded served leg of the default line")
-    ap.add_argument("--served-rate", type=float, default=20.0,
+    ap.add_argument("--served-rate", type=float, default=1.0,
                     help="arrivals per second of the bounded served leg")
-    ap.add_argument("--served-seconds", type=float, default=3.0,
+    ap.add_argument("--served-seconds", type=float, default=20.0,
                     help="length of the bounded served leg's trace")
     ap.add_argument("--served-max-sweeps", type=int, default=1000)
     ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
@@ -67,6 +67,9 @@ def parse():
                     help="sweep cap per pass of the disturbed form")
     ap.add_argument("--instances", type=int, default=384)
     ap.add_argument("--batch-max-sweeps", type=int, default=1000)
+    ap.add_argument("--batch-horizon", default="0",
+                    help='horizon of the batched queries: 0 (infinite, stop on eps) or "auto" '
+                         "(Remark 5.2: self-convergence, then that many sweeps)")
     ap.add_argument("--batch-dims", default="2,3",
                     help="keep only the seeded instances of these dimensions")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
@@ -394,7 +397,8 @@ def run_batched(args, tuner):
     dims = {int(x) for x in args.batch_dims.split(",")}
     insts = [x for x in W.batched(count=args.instances) if len(x[0]["n"]) in dims]
     systems = [s for s, _ in insts]
-    specs = [dict(spec, max_sweeps=args.batch_max_sweeps) for _, spec in insts]
+    hz = "auto" if args.batch_horizon == "auto" else int(args.batch_horizon)
+    specs = [dict(spec, max_sweeps=args.batch_max_sweeps, horizon=hz) for _, spec in insts]
     # schedule choice (untimed): storage of the batch and engine graph chunk
     probe = impact.build_imdp_batch(systems, storage="factors")
     infos = [v.info() for v in probe]
@@ -445,8 +449,8 @@ def run_batched(args, tuner):
     sweeps = np.array([r["info"]["sweeps"] for r in res.values()])
     return {
         "workload": (f"{len(systems)} of {args.instances} seeded random linear instances "
-                     f"(dimensions {args.batch_dims}), reach-avoid, eps 1e-8, at most "
-                     f"{args.batch_max_sweeps} sweeps per pass"),
+                     f"(dimensions {args.batch_dims}), reach-avoid, eps 1e-8, horizon "
+                     f"{args.batch_horizon}, at most {args.batch_max_sweeps} sweeps per pass"),
         "instances": len(systems),
         "n_states": int(sum(i["n_states"] for i in infos)),
         "n_rows": int(sum(i["n_rows"] for i in infos)),
@@ -458,6 +462,9 @@ def run_batched(args, tuner):
         "plain_updates_per_s": plain_updates / t_plain,
         "instances_per_s": len(systems) / t_batched,
         "converged": int(sum(r["status"] == 0 for r in res.values())),
+        "self_converged": (int(sum(all(r["info"]["self_sweeps"][k] < args.batch_max_sweeps
+                                       for k in (0, 1)) for r in res.values()))
+                           if hz == "auto" else None),
         "sweeps_p50": [float(x) for x in np.percentile(sweeps, 50, axis=0)],
         "sweeps_max": [int(x) for x in sweeps.max(axis=0)],
         "max_abs_diff_vs_plain": worst,

@@ -143,6 +143,42 @@ def test_unicycle_mean_box_contains(orc):
         assert (mhi - mlo).max() < (hi - lo).max() + 0.3
 
 
+@pytest.mark.parametrize("n", [(6, 6, 7), (10, 10, 24), (4, 4, 3)])
+def test_unicycle_mean_box_is_tight(orc, n):
+    """Each successor coordinate is a sum of functions of separate state
+    coordinates (x0 + dt v cos th, x1 + dt v sin th, th + dt om), so its range
+    over the cell is reached: a dense tensor grid of the cell (its corners and
+    2,001 headings) attains the box up to the grid's resolution and the
+    2^-48 padding.  An over-wide enclosure (a missed extremum test, a
+    dropped clamp, cos/sin ranges taken over too wide a heading interval)
+    fails the tightness bound."""
+    system, _ = W.unicycle3d(n=n)
+    N = int(np.prod(n))
+    rng = np.random.default_rng(4)
+    for _ in range(30):
+        s = int(rng.integers(0, N))
+        u = int(rng.integers(0, 20))
+        mlo, mhi = orc.mean_box(system, s, u)
+        k = np.unravel_index(s, n)
+        lo = np.array([orc.cell_edge(system, i, k[i]) for i in range(3)])
+        hi = np.array([orc.cell_edge(system, i, k[i] + 1) for i in range(3)])
+        th = np.linspace(lo[2], hi[2], 2001)
+        v, om = system["inputs"][u]
+        x0 = np.array([lo[0], hi[0]])[:, None]
+        x1 = np.array([lo[1], hi[1]])[:, None]
+        f0 = (x0 + 0.1 * v * np.cos(th)[None, :]).ravel()
+        f1 = (x1 + 0.1 * v * np.sin(th)[None, :]).ravel()
+        f2 = th + 0.1 * om
+        smin = np.array([f0.min(), f1.min(), f2.min()])
+        smax = np.array([f0.max(), f1.max(), f2.max()])
+        # heading spacing h: the sampled extremum of dt v cos/sin is within
+        # dt v h^2 / 8 of the true one; padding <= 2^-48 * (|x| + dt v + |th|)
+        h = (hi[2] - lo[2]) / 2000
+        tol = 0.1 * v * h * h / 8 + 1e-12
+        assert (mlo <= smin + 1e-15).all() and (mhi >= smax - 1e-15).all()
+        assert (smin - mlo).max() <= tol and (mhi - smax).max() <= tol, (s, u, smin - mlo, mhi - smax)
+
+
 # --------------------------------------------------------------------------
 # Rows of the abstraction: containment, invariants, OUT / TAIL
 # --------------------------------------------------------------------------
