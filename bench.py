@@ -137,7 +137,7 @@ KERNEL_SOURCES = {
         "sweep_sb.hpp", "sweep_common.hpp", "impact_internal.hpp", "impact_device.hpp"],
     "k_sweep_sel": ["sweep_sel.hip", "sweep_common.hpp", "impact_internal.hpp",
                     "impact_device.hpp"],
-    "k_mc_entries": ["build_mc.hip", "impact_internal.hpp", "impact_device.hpp"],
+    "k_mc_rows": ["build_mc.hip", "build_mc.hpp", "impact_internal.hpp", "impact_device.hpp"],
     "build": ["build.hip", "impact_internal.hpp", "impact_device.hpp"],
 }
 
@@ -211,11 +211,14 @@ def mc_build_roofline(imdp, d, mc, workload):
     """The Monte Carlo construction against the FP64 vector units that bind it.
 
     Evaluations: one density evaluation per (window cell, candidate mean,
-    sample point).  Algorithmic FP64 work per evaluation, besides its exp:
-    the sample point (2d), the offset from the mean (d), the quadratic form
-    (2d^2 + 2d), the scalings (2) and the two running sums (3).  The
-    fraction of the FP64 vector peak uses the FP64 instructions counted by the
-    SQ counters of this kernel build (exp included) when they are recorded.
+    sample point).  The factored kernel (grids of at most 5 dimensions, at
+    most 16 candidates) forms each evaluation as a product of d table entries
+    that share prefixes across candidates, and adds it and its square to two
+    running sums: algorithmic FP64 work d + 2 per evaluation (d - 1 products,
+    one add, one fused multiply-add counted as 2), besides the per-point
+    tables and the per-candidate epilogue.  The fraction of the FP64 vector
+    peak uses the FP64 instructions counted by the SQ counters of this kernel
+    build when they are recorded under profiles/.
     """
     info = imdp.info()
     ex = imdp.export_rows(0, info["n_rows"], entries=False)
@@ -224,10 +227,10 @@ def mc_build_roofline(imdp, d, mc, workload):
     n_pts = len(mc["samples"])
     evals = cells * n_cand * n_pts
     t = info["build_ms"] * 1e-3
-    per_eval = 2 * d * d + 5 * d + 5
-    flops = recorded_build_flops("bounds", workload, "k_mc_entries")
+    per_eval = d + 2
+    flops = recorded_build_flops("bounds", workload, "k_mc_rows")
     return {
-        "kernels": "k_row_geom + scan + k_mc_entries",
+        "kernels": "k_row_geom + scan + k_mc_prep + k_mc_rows",
         "bound": "alu",
         "build_ms": info["build_ms"],
         "entries_per_s": info["n_entries"] / t,
@@ -238,48 +241,6 @@ def mc_build_roofline(imdp, d, mc, workload):
         "fp64_counted_tflops": None if flops is None else flops / t / 1e12,
         "fp64_frac": None if flops is None else flops / t / (FP64_PEAK_TFLOPS * 1e12),
         "peak_tflops": FP64_PEAK_TFLOPS,
-    }
-
-
-def build_roofline(imdp, d, workload):
-    """Construction against its two ceilings.
-
-    HBM: bytes the build must write -- per row 8*d B window + 32 B OUT/TAIL +
-    8 B row offset, plus 16 B per entry (bounds storage) or 16 B per factor
-    (sum of the window widths; factor storage).  FP64: the work the chosen
-    storage performs -- the erfc evaluations at both ends of every window edge
-    of every dimension (2 (W_i + 1) per dimension and row), and, with bounds
-    storage only, the 2(d-1) multiplies that form each entry's (lo, hi) from
-    its factors (factor storage leaves them to the sweeps) -- and, when the
-    SQ counters of this build are recorded, the fraction of the FP64 vector
-    peak they give.  Entries are counted as implied entries whatever the
-    storage.
-    """
-    info = imdp.info()
-    ex = imdp.export_rows(0, info["n_rows"], entries=False)
-    cells = int(ex["counts"].sum())
-    rows = info["n_rows"]
-    widths = ex["win"][:, d:]
-    fac = int(widths.sum())
-    bounds = info["storage"] != 2
-    payload = 16 * (cells if bounds else fac)
-    nbytes = payload + rows * (8 * d + 32 + 8)
-    t = info["build_ms"] * 1e-3
-    products = 2 * max(0, d - 1) * cells if bounds else 0
-    erfc = int(2 * (widths + 1).sum())
-    storage = "bounds" if bounds else "factors"
-    flops = recorded_build_flops(storage, workload)
-    return {
-        "kernels": "k_row_geom + scan + k_expand",
-        "build_ms": info["build_ms"],
-        "entries_per_s": info["n_entries"] / t,
-        "hbm_bytes": nbytes,
-        "hbm_gbs": nbytes / t / 1e9,
-        "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS,
-        "fp64_products": products,
-        "erfc_evals": erfc,
-        "erfc_per_s": erfc / t,
-        "fp64_frac": None if flops is None else flops / t / (FP64_PEAK_TFLOPS * 1e12),
     }
 
 

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "build_mc.hpp"
 #include "impact_internal.hpp"
 
 using namespace impact;
@@ -714,6 +715,8 @@ static int build_many(int32_t n, const impact_system* sys, const impact_grid* gr
     int64_t* d_state_base = tmp.template get<int64_t>(n + 1);
     const int64_t te = scan_tmp_elems(R);
     int64_t* stmp = tmp.template get<int64_t>(te);
+    double* d_gA = mc ? tmp.template get<double>(mc->N * (hp[0].d + 1)) : nullptr;
+    double* d_gmax = mc ? tmp.template get<double>(kMaxDim) : nullptr;
     std::vector<double> U_all(std::max<int64_t>(1, u_off[n]));
     for (int32_t i = 0; i < n; ++i) {
       hp[i].U = st->d_U + u_off[i];
@@ -774,8 +777,8 @@ static int build_many(int32_t n, const impact_system* sys, const impact_grid* gr
     else
       st->ent = st->own<double2>(total);
     if (mc)
-      HIP_TRY(launch_mc_entries(st->d_sys, hp[0].d, R, total, st->win, st->row_off, st->ent,
-                                st->st));
+      HIP_TRY(launch_mc_rows(st->d_sys, hp[0].d, R, total, st->win, st->row_off, st->ent,
+                             st->st, mc->G, d_gA, d_gmax));
     else
       HIP_TRY(launch_expand(T, R, st->win, st->row_off, st->ent, st->fac, fs_max, d_max,
                             st->st));

@@ -60,13 +60,37 @@ def _case(name):
                       sigma=[1.0] * 6, k_sigma=6.0)
         return system, dict(inv_cov=0.5 * (P + P.T), det_cov=float(np.linalg.det(cov)),
                             samples=W.mc_points(16, 6, seed=24), grid_pts=1, kappa=0.5)
+    if name == "robot_sharp":
+        # noise far narrower than a cell: the factored exponents could overflow,
+        # so the rows are evaluated directly
+        system, _, mc = W.robot2d_correlated(n=(10, 10), samples=32, grid_pts=2, kappa=2.0)
+        cov = np.linalg.inv(mc["inv_cov"]) * 1e-4
+        P = np.linalg.inv(cov)
+        return system, dict(mc, inv_cov=0.5 * (P + P.T), det_cov=float(np.linalg.det(cov)))
+    if name == "affine2_G4":
+        system = W.tiny_affine(d=2, n=8, seed=5)
+        P, det = _corr(system["sigma"], [[1.0, -0.4], [-0.4, 1.0]])
+        return system, dict(inv_cov=P, det_cov=det, samples=W.mc_points(100, 2, seed=25),
+                            grid_pts=4, kappa=1.5)
+    if name == "affine4_corr":
+        rng = np.random.default_rng(26)
+        M = rng.normal(size=(4, 4))
+        A = 0.7 * M / max(abs(np.linalg.eigvals(M)))
+        system = dict(kind="affine", A=A, B=0.2 * np.ones((4, 1)), c=np.zeros(4),
+                      lb=[-1.0] * 4, ub=[1.0] * 4, n=[4] * 4, inputs=[[-1.0], [0.0], [1.0]],
+                      sigma=[1.0] * 4, k_sigma=6.0)
+        R = np.eye(4) + 0.25 * (np.ones((4, 4)) - np.eye(4))
+        P, det = _corr([0.15] * 4, R)
+        return system, dict(inv_cov=P, det_cov=det, samples=W.mc_points(40, 4, seed=27),
+                            grid_pts=2, kappa=1.0)
     if name == "robot_dense_N1":
         system, _, mc = W.robot2d_correlated(n=(6, 6), samples=1, grid_pts=1, kappa=0.0)
         return dict(system, k_sigma=0.0), mc
     raise KeyError(name)
 
 
-CASES = ["robot_corr", "affine3_corr", "room5d_corr", "affine6_corr", "robot_dense_N1"]
+CASES = ["robot_corr", "affine3_corr", "room5d_corr", "affine6_corr", "robot_dense_N1",
+         "robot_sharp", "affine2_G4", "affine4_corr"]
 
 
 @pytest.mark.parametrize("name", CASES)
