@@ -154,3 +154,23 @@ def test_mc_rejects_bad_noise(I):
         with pytest.raises(I.ImpactError) as e:
             I.build_imdp_mc(system, dict(mc, **bad))
         assert e.value.code == code, bad
+
+
+@pytest.mark.parametrize("horizon", [0, "auto"])
+def test_mc_handle_in_the_engine_equals_plain_iterate(I, horizon):
+    """A correlated-noise abstraction is an ordinary handle: the multi-query
+    engine runs its query exactly as the plain call does (bitwise)."""
+    system, mc = _case("robot_corr")
+    spec = dict(SPECS["robot_corr"], eps=1e-8, max_sweeps=400, horizon=horizon)
+    imdp = I.build_imdp_mc(system, mc)
+    imdp.set_sweep_modes("state_box", "per_row")
+    plain = imdp.iterate(spec)
+    eng = I.Engine(max_queries=2)
+    qid = eng.submit(imdp, spec)
+    res = eng.run_all()[qid]
+    for k in ("lo", "hi", "policy"):
+        a, b = res[k].cpu().numpy(), plain[k].cpu().numpy()
+        assert np.array_equal(a, b), (k, np.abs(a - b).max())
+    assert tuple(res["info"]["sweeps"]) == tuple(plain["info"]["sweeps"])
+    eng.free()
+    imdp.free()
