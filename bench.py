@@ -244,6 +244,48 @@ def mc_build_roofline(imdp, d, mc, workload):
     }
 
 
+def build_roofline(imdp, d, workload):
+    """Construction against its two ceilings.
+
+    HBM: bytes the build must write -- per row 8*d B window + 32 B OUT/TAIL +
+    8 B row offset, plus 16 B per entry (bounds storage) or 16 B per factor
+    (sum of the window widths; factor storage).  FP64: the work the chosen
+    storage performs -- the erfc evaluations at both ends of every window edge
+    of every dimension (2 (W_i + 1) per dimension and row), and, with bounds
+    storage only, the 2(d-1) multiplies that form each entry's (lo, hi) from
+    its factors (factor storage leaves them to the sweeps) -- and, when the
+    SQ counters of this build are recorded, the fraction of the FP64 vector
+    peak they give.  Entries are counted as implied entries whatever the
+    storage.
+    """
+    info = imdp.info()
+    ex = imdp.export_rows(0, info["n_rows"], entries=False)
+    cells = int(ex["counts"].sum())
+    rows = info["n_rows"]
+    widths = ex["win"][:, d:]
+    fac = int(widths.sum())
+    bounds = info["storage"] != 2
+    payload = 16 * (cells if bounds else fac)
+    nbytes = payload + rows * (8 * d + 32 + 8)
+    t = info["build_ms"] * 1e-3
+    products = 2 * max(0, d - 1) * cells if bounds else 0
+    erfc = int(2 * (widths + 1).sum())
+    storage = "bounds" if bounds else "factors"
+    flops = recorded_build_flops(storage, workload)
+    return {
+        "kernels": "k_row_geom + scan + k_expand",
+        "build_ms": info["build_ms"],
+        "entries_per_s": info["n_entries"] / t,
+        "hbm_bytes": nbytes,
+        "hbm_gbs": nbytes / t / 1e9,
+        "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS,
+        "fp64_products": products,
+        "erfc_evals": erfc,
+        "erfc_per_s": erfc / t,
+        "fp64_frac": None if flops is None else flops / t / (FP64_PEAK_TFLOPS * 1e12),
+    }
+
+
 # states of the bounded CPU-oracle sample per workload (about 10-15 s of
 # single-core oracle work: its build of the sample's rows and one sweep of
 # each pass over them)
