@@ -497,7 +497,7 @@ __device__ __forceinline__ void sel_search(const SweepArgs& a, int64_t row, int 
 // The load pass also checks the hint values (tau0, tau1): F<, F<= and the
 // width * value below each, so that a row whose critical cells did not move
 // costs one pass.
-template <int NW, int EC, int E, int D>
+template <int NW, int EC, int E, int D, int ST>
 __device__ __forceinline__ void sel_row_body(const SweepArgs& a, int64_t row, int tid,
                                              SelLds<NW>& L, int& par, const RowWalk& rw0,
                                              int nw, int64_t base, bool have_hint, double tau0,
@@ -506,7 +506,7 @@ __device__ __forceinline__ void sel_row_body(const SweepArgs& a, int64_t row, in
   const int d = D > 0 ? D : a.d;
   const bool mx = a.maximise != 0;
   const double sg = mx ? -1.0 : 1.0;
-  const bool factors = a.storage == IMPACT_STORE_FACTORS;
+  const bool factors = ST == 0 ? a.storage == IMPACT_STORE_FACTORS : ST == 2;
 
   // the cells: width and both signed values per slot; loads use a valid
   // address for slots past the row's cells so that none waits on a branch
@@ -611,7 +611,9 @@ __device__ __forceinline__ void sel_row_body(const SweepArgs& a, int64_t row, in
 // a maximising LP) so that both directions search for the smallest critical
 // value in ascending order.  The thread's slots are processed by a body
 // unrolled over the smallest of 4, 8, 12 and E slots that covers the row.
-template <int NW, int E, int D>
+// ST: the storage of the bounds, 1 stored, 2 factors, 0 read from the
+// arguments (the engine's kernels, whose queries may differ).
+template <int NW, int E, int D, int ST>
 __device__ __forceinline__ void sel_row(const SweepArgs& a, int64_t row, int tid, SelLds<NW>& L,
                                         int& par, double& q0, double& q1) {
   constexpr int T = 64 * NW;
@@ -631,7 +633,7 @@ __device__ __forceinline__ void sel_row(const SweepArgs& a, int64_t row, int tid
   RowWalk rw;
   int tot;
   walk_init<D>(p, wr, d, tid, T, rw, tot);
-  if (a.storage == IMPACT_STORE_FACTORS) {
+  if (ST == 0 ? a.storage == IMPACT_STORE_FACTORS : ST == 2) {
     __syncthreads();  // the previous row's readers are done with L.fac
     const double2* fr = a.fac + row * (int64_t)a.fs;
     for (int k = tid; k < tot; k += T) L.fac[k] = fr[k];
@@ -639,18 +641,18 @@ __device__ __forceinline__ void sel_row(const SweepArgs& a, int64_t row, int tid
   }
   const int Erow = (nw + T - 1) / T;
   if (Erow == 0)
-    sel_row_body<NW, 1, E, D>(a, row, tid, L, par, rw, nw, base, have_hint, tau0, tau1, q0, q1);
+    sel_row_body<NW, 1, E, D, ST>(a, row, tid, L, par, rw, nw, base, have_hint, tau0, tau1, q0, q1);
   else if (E <= 4 || Erow <= 4)
-    sel_row_body<NW, (E < 4 ? E : 4), E, D>(a, row, tid, L, par, rw, nw, base, have_hint, tau0,
+    sel_row_body<NW, (E < 4 ? E : 4), E, D, ST>(a, row, tid, L, par, rw, nw, base, have_hint, tau0,
                                             tau1, q0, q1);
   else if (E <= 8 || Erow <= 8)
-    sel_row_body<NW, (E < 8 ? E : 8), E, D>(a, row, tid, L, par, rw, nw, base, have_hint, tau0,
+    sel_row_body<NW, (E < 8 ? E : 8), E, D, ST>(a, row, tid, L, par, rw, nw, base, have_hint, tau0,
                                             tau1, q0, q1);
   else if (E <= 12 || Erow <= 12)
-    sel_row_body<NW, (E < 12 ? E : 12), E, D>(a, row, tid, L, par, rw, nw, base, have_hint,
+    sel_row_body<NW, (E < 12 ? E : 12), E, D, ST>(a, row, tid, L, par, rw, nw, base, have_hint,
                                               tau0, tau1, q0, q1);
   else
-    sel_row_body<NW, E, E, D>(a, row, tid, L, par, rw, nw, base, have_hint, tau0, tau1, q0, q1);
+    sel_row_body<NW, E, E, D, ST>(a, row, tid, L, par, rw, nw, base, have_hint, tau0, tau1, q0, q1);
 }
 
 // One SAFE state s: its rows (all inputs in the policy pass, PASS 0; the
@@ -658,7 +660,7 @@ __device__ __forceinline__ void sel_row(const SweepArgs& a, int64_t row, int tid
 // the workgroup; writes vout[s] (and pi[s] in the policy pass) and returns
 // the state's V1 - V0 on every thread.  With a disturbance player (nw > 1)
 // every (state, input) has nw rows and is valued by its worst one (eq. (5.1)).
-template <int NW, int E, int PASS, int D>
+template <int NW, int E, int PASS, int D, int ST>
 __device__ __forceinline__ double sel_state(const SweepArgs& a, int64_t s, SelLds<NW>& L) {
   const int tid = threadIdx.x;
   const int U = PASS == 0 ? a.nu : 1;
@@ -668,7 +670,7 @@ __device__ __forceinline__ double sel_state(const SweepArgs& a, int64_t s, SelLd
     const int ui = m / NWD, wi = m - ui * NWD;
     const int u = PASS == 0 ? ui : a.pi[s];
     double q0, q1;
-    sel_row<NW, E, D>(a, (s * a.nu + u) * NWD + wi, tid, L, par, q0, q1);
+    sel_row<NW, E, D, ST>(a, (s * a.nu + u) * NWD + wi, tid, L, par, q0, q1);
     if (tid == 0) {
       L.qb0[m] = q0;
       L.qb1[m] = q1;
@@ -706,31 +708,39 @@ __device__ __forceinline__ double sel_state(const SweepArgs& a, int64_t s, SelLd
 
 // Two waves per SIMD at least: without the bound the compiler reaches for the
 // accumulation registers and leaves one wave per SIMD, which doubles the sweep.
-template <int NW, int E, int PASS, int D>
+template <int NW, int E, int PASS, int D, int ST>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 8)))
 void k_sweep_sel(SweepArgs a) {
   if (a.ctrl->done) return;
   __shared__ SelLds<NW> L;
   const int64_t si = blockIdx.x;
-  const double g = sel_state<NW, E, PASS, D>(a, a.safe[si], L);
+  const double g = sel_state<NW, E, PASS, D, ST>(a, a.safe[si], L);
   if (threadIdx.x == 0) a.gap_part[si] = g;
 }
 
-template <int PASS, int D>
-static hipError_t launch_sel_pd(const SweepArgs& a, int32_t max_row, hipStream_t st) {
+template <int PASS, int D, int ST>
+static hipError_t launch_sel_pds(const SweepArgs& a, int32_t max_row, hipStream_t st) {
   const dim3 g((unsigned)a.n_safe);
   const int cells = max_row;  // upper bound on window cells per row
   if (cells <= 256 * 8)
-    hipLaunchKernelGGL((k_sweep_sel<4, 8, PASS, D>), g, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_sweep_sel<4, 8, PASS, D, ST>), g, dim3(256), 0, st, a);
   else if (cells <= 256 * 16)
-    hipLaunchKernelGGL((k_sweep_sel<4, 16, PASS, D>), g, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_sweep_sel<4, 16, PASS, D, ST>), g, dim3(256), 0, st, a);
   else if (cells <= 512 * 16)
-    hipLaunchKernelGGL((k_sweep_sel<8, 16, PASS, D>), g, dim3(512), 0, st, a);
+    hipLaunchKernelGGL((k_sweep_sel<8, 16, PASS, D, ST>), g, dim3(512), 0, st, a);
   else if (cells <= 1024 * 16)
-    hipLaunchKernelGGL((k_sweep_sel<16, 16, PASS, D>), g, dim3(1024), 0, st, a);
+    hipLaunchKernelGGL((k_sweep_sel<16, 16, PASS, D, ST>), g, dim3(1024), 0, st, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+// The storage of the bounds as a template argument: the load pass then holds
+// no per-slot branch between the stored and the factored form.
+template <int PASS, int D>
+static hipError_t launch_sel_pd(const SweepArgs& a, int32_t max_row, hipStream_t st) {
+  return a.storage == IMPACT_STORE_FACTORS ? launch_sel_pds<PASS, D, 2>(a, max_row, st)
+                                           : launch_sel_pds<PASS, D, 1>(a, max_row, st);
 }
 
 template <int PASS>
@@ -882,9 +892,9 @@ void k_mq_sweep_sel(
     a.pass = phase >> 1;
     a.maximise = Dq.max_lp[phase >> 1];
     if (phase == 0)
-      g = sel_state<NW, E, 0, D>(a, ws[item], L);
+      g = sel_state<NW, E, 0, D, 0>(a, ws[item], L);
     else
-      g = sel_state<NW, E, 1, D>(a, ws[item], L);
+      g = sel_state<NW, E, 1, D, 0>(a, ws[item], L);
   } else if ((phase == 1 || phase == 3) && threadIdx.x == 0) {
     mq_close_state(Dq, ctrl[q], phase, ws[item]);
   }
