@@ -16,6 +16,26 @@ __device__ __forceinline__ uint64_t dbits(double x) { return (uint64_t)__double_
 __device__ __forceinline__ double bitsd(uint64_t b) { return __longlong_as_double((long long)b); }
 
 // Values that are equal on every lane of a wavefront, moved to scalar registers.
+// q = n / w and r = n % w for 0 <= n < 2^22 and 1 <= w < 2^22: a float
+// estimate of the quotient (off by at most one) corrected exactly, a handful
+// of instructions instead of an integer division's expansion (the window and
+// box digit decompositions of the sweeps divide small numbers by runtime
+// extents).
+__device__ __forceinline__ void divmod_small(int n, int w, int& q, int& r) {
+  int qq = (int)((float)n * __builtin_amdgcn_rcpf((float)w));
+  int rr = n - qq * w;
+  if (rr < 0) {
+    qq -= 1;
+    rr += w;
+  }
+  if (rr >= w) {
+    qq += 1;
+    rr -= w;
+  }
+  q = qq;
+  r = rr;
+}
+
 __device__ __forceinline__ int32_t uniform_i32(int32_t x) {
   return __builtin_amdgcn_readfirstlane(x);
 }
@@ -363,12 +383,14 @@ __device__ void load_row(const SweepArgs& a, const SysParams& p, int64_t row, in
   int64_t t = 0;
   int tot = 0;
   {
-    int64_t rem = first < nw ? first : 0;
+    int rem = first < nw ? first : 0;
     IMPACT_FOR_DIMS_REV(i, d) {
       W[i] = wr[d + i];
       klo[i] = wr[i];
-      j[i] = nw > 0 ? (int32_t)(rem % W[i]) : 0;
-      rem = nw > 0 ? rem / W[i] : 0;
+      if (nw > 0)
+        divmod_small(rem, W[i], rem, j[i]);
+      else
+        j[i] = 0;
     }
     IMPACT_FOR_DIMS(i, d) {
       t += ((int64_t)klo[i] + j[i]) * p.stride[i];

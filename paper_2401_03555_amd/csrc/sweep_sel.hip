@@ -195,24 +195,6 @@ struct RowWalk {
   int32_t t, dt;
 };
 
-// q = n / w and r = n % w for 0 <= n < 2^22 and 1 <= w < 2^22: a float
-// estimate of the quotient (off by at most one) corrected exactly, a handful
-// of instructions instead of an integer division's expansion.
-__device__ __forceinline__ void divmod_small(int n, int w, int& q, int& r) {
-  int qq = (int)((float)n * __builtin_amdgcn_rcpf((float)w));
-  int rr = n - qq * w;
-  if (rr < 0) {
-    qq -= 1;
-    rr += w;
-  }
-  if (rr >= w) {
-    qq += 1;
-    rr -= w;
-  }
-  q = qq;
-  r = rr;
-}
-
 template <int D>
 __device__ __forceinline__ void walk_init(const SysParams& p, const int32_t* wr, int d, int tid,
                                           int stride, RowWalk& rw, int& tot) {
