@@ -207,7 +207,8 @@ typedef struct {
  * chooses the input only.  Such handles sweep both passes by state box
  * (one sort per state serving all its input and disturbance rows) when a
  * state's rows fit a box of 512 cells and the per-row mode is not set, and
- * per row otherwise; the multi-query engine rejects them.  Errors as impact_build_imdp, plus E_INVAL for count or dim_w < 1,
+ * per row otherwise; the multi-query engine runs them with the selection
+ * sweep.  Errors as impact_build_imdp, plus E_INVAL for count or dim_w < 1,
  * null values or D, or non-finite entries; E_UNSUPPORTED for a non-affine
  * system, dim_u + dim_w > 8 or more than 256 (input, disturbance) pairs.
  */
@@ -410,9 +411,12 @@ int impact_mq_create(const impact_device *dev, int32_t max_queries, impact_mq **
  * once the query finishes (cells outside the SAFE set immediately).  The
  * abstraction handle may be released after submitting (the engine keeps its
  * device storage alive until the query is polled).  *id receives the query id.
- * Errors: E_INVAL (bad spec/eps/buffers), E_UNSUPPORTED (no free slot, an
- * abstraction with a disturbance player, or IMPACT_HORIZON_AUTO), E_NOMEM,
- * E_HIP. */
+ * Queries take every horizon of impact_spec, IMPACT_HORIZON_AUTO included,
+ * and abstractions with a disturbance player (their queries run the
+ * selection sweep, which values each input by its worst disturbance row).
+ * Errors: E_INVAL (bad spec/eps/buffers), E_UNSUPPORTED (no free slot, rows
+ * longer than 4096 entries, more than 256 inputs, or more than 256 (input,
+ * disturbance) rows per state), E_NOMEM, E_HIP. */
 int impact_mq_submit(impact_mq *mq, const impact_imdp *imdp, const impact_spec *spec, double eps,
                      double *lo, double *hi, int32_t *policy, int32_t *id);
 

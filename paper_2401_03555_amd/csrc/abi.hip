@@ -293,6 +293,7 @@ int imdp_view(const impact_imdp* h, ImdpView* v) {
   v->a.sys = h->dp;
   v->a.fs = h->fs;
   v->a.nu = h->nu;
+  v->a.nw = h->nw;
   v->a.d = h->d;
   v->a.windowed = h->windowed;
   v->a.storage = h->storage;

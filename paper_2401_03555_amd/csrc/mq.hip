@@ -496,9 +496,9 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
   if (!std::isfinite(eps) || !(eps > 0.0)) return mq_fail(IMPACT_E_INVAL, "eps must be > 0");
   ImdpView v;
   if (imdp_view(h, &v) != IMPACT_OK) return mq_fail(IMPACT_E_INVAL, "bad abstraction handle");
-  if (v.nw > 1)
-    return mq_fail(IMPACT_E_UNSUPPORTED,
-                   "abstractions with a disturbance player run through impact_interval_iterate");
+  // the selection sweep holds a state's row values in LDS, 256 of them
+  if ((int64_t)v.nu * (v.nw > 1 ? v.nw : 1) > 256)
+    return mq_fail(IMPACT_E_UNSUPPORTED, "more than 256 (input, disturbance) rows per state");
   const int d = v.d;
   for (int b = 0; b < spec->n_target; ++b)
     for (int i = 0; i < d; ++i)
@@ -588,12 +588,14 @@ int impact_mq_submit(impact_mq* m, const impact_imdp* h, const impact_spec* spec
     D.upper_first = spec->pessimistic ? 0 : 1;
     D.max_lp[0] = spec->pessimistic ? safety : !safety;
     D.max_lp[1] = spec->pessimistic ? !safety : safety;
-    D.box_class = v.max_row <= 512;
+    // a disturbance player (eq. (5.1)) takes the selection sweep, which values
+    // each (state, input) by its worst disturbance row in both passes
+    D.box_class = v.max_row <= 512 && v.nw <= 1;
     if (!D.box_class) {
       // selection sweep: two sort buffers of both value components, row hints
       D.vs[0] = (double*)get(sizeof(double) * 2 * (size_t)std::max<int64_t>(1, N));
       D.vs[1] = (double*)get(sizeof(double) * 2 * (size_t)std::max<int64_t>(1, N));
-      const int64_t rows = N * v.nu;
+      const int64_t rows = N * v.nu * (v.nw > 1 ? v.nw : 1);
       D.a.hint = (int32_t*)get(sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(1, rows));
       D.a.n_cells = N;
       MQ_TRY(launch_fill_i32(D.a.hint, 2 * rows, -1, m->st));

@@ -733,10 +733,6 @@ def test_disturbance_with_long_rows_uses_the_workgroup_path(I):
 
 def test_disturbance_rejections(I):
     system = _disturbed(5)
-    g = I.build_imdp(system)
-    eng = I.Engine(max_queries=2)
-    with pytest.raises(I.ImpactError, match="disturbance"):
-        eng.submit(g, dict(DIST_SPECS["reach_avoid"], eps=1e-8, max_sweeps=10))
     with pytest.raises(ValueError):
         I.build_imdp_batch([system])
     uni = dict(W.unicycle3d(n=(6, 6, 4))[0], D=np.eye(3), disturbances=[[0.0, 0.0, 0.0]])
@@ -748,6 +744,45 @@ def test_disturbance_rejections(I):
     many = dict(system, disturbances=np.zeros((90, 2)))   # 3 inputs x 90 > 256 rows per state
     with pytest.raises(I.ImpactError, match="256"):
         I.build_imdp(many)
+
+
+@pytest.mark.parametrize("horizon", [0, "auto"])
+@pytest.mark.parametrize("pessimistic", [True, False], ids=["pess", "opt"])
+@pytest.mark.parametrize("kind", list(DIST_SPECS))
+def test_disturbance_player_in_the_engine_matches_oracle(I, kind, pessimistic, horizon):
+    """The multi-query engine runs disturbed abstractions with the selection
+    sweep (worst disturbance row per input): against the oracle, both
+    policies, the infinite and the automatic horizon, with other queries in
+    flight."""
+    system = _disturbed(21 if kind == "safety" else 12)
+    spec = dict(DIST_SPECS[kind], eps=1e-8, max_sweeps=3000, pessimistic=pessimistic,
+                horizon=horizon)
+    say(f"disturbed engine: {kind} pessimistic={pessimistic} horizon={horizon}")
+    g = I.build_imdp(system)
+    other = I.build_imdp(W.tiny_affine(d=2, n=9, seed=2))
+    eng = I.Engine(max_queries=4)
+    qid = eng.submit(g, spec)
+    eng.submit(other, dict(kind="reach", target=[[[0.5, 0.5], [1.5, 1.5]]], avoid=[], eps=1e-6,
+                           max_sweeps=200))
+    rg = eng.run_all()[qid]
+    m = oracle.build(system, system["k_sigma"])
+    cls = oracle.label(system, spec["target"], spec["avoid"])
+    args = (m["n_states"], 3, m["row_ptr"], m["target"], m["lo"], m["hi"], cls, spec["kind"],
+            spec["eps"], spec["max_sweeps"])
+    if horizon == "auto":
+        ro = oracle.iterate_auto_horizon(*args, want_q0=True, optimistic=not pessimistic,
+                                         n_dist=3)
+        assert rg["info"]["horizon"] == ro["horizon"]
+        assert tuple(rg["info"]["self_sweeps"]) == tuple(ro["self_sweeps"])
+        lo, hi = rg["lo"].cpu().numpy(), rg["hi"].cpu().numpy()
+        kp = "hi" if not pessimistic else "lo"
+        assert np.abs(dict(lo=lo, hi=hi)[kp] - ro[kp]).max() <= VALUE_TOL
+    else:
+        ro = oracle.iterate(*args, want_q0=True, optimistic=not pessimistic, n_dist=3)
+        assert rg["status"] == ro["status"]
+        compare_iter(rg, ro, cls, kind != "safety", f"disturbed engine {kind}", q0=ro["q0"],
+                     model=m, spec=spec, optimistic=not pessimistic, n_dist=3)
+    eng.free()
 
 
 def test_disturbance_robot2d_state_box_equals_per_row(I):
