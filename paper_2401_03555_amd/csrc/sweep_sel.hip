@@ -152,6 +152,8 @@ struct SelLds {
   double red[2][NW][12];       // block sums, double-buffered
   double2 fac[kMaxFactors];    // the row's factors (FACTORS storage)
   double qb0[kMaxItems], qb1[kMaxItems];
+  double2 htau[kMaxItems];     // per row of the state: the hint cells' signed values
+  int32_t hok[kMaxItems];      // ... and whether the row has hints
   int32_t hit[2];              // a cell holding the critical value, per vector
   double cx[2][kTail], cw[2][kTail];  // gathered candidates (signed value, width)
   int32_t tcnt[2][NW];         // candidates per wavefront
@@ -597,21 +599,14 @@ __device__ __forceinline__ void sel_row_body(const SweepArgs& a, int64_t row, in
 // arguments (the engine's kernels, whose queries may differ).
 template <int NW, int E, int D, int ST>
 __device__ __forceinline__ void sel_row(const SweepArgs& a, int64_t row, int tid, SelLds<NW>& L,
-                                        int& par, double& q0, double& q1) {
+                                        int& par, bool have_hint, double tau0, double tau1,
+                                        double& q0, double& q1) {
   constexpr int T = 64 * NW;
   const SysParams& p = *a.sys;
   const int d = D > 0 ? D : a.d;
   const int64_t base = a.row_off[row];
   const int nw = (int)(a.row_off[row + 1] - base);
   const int32_t* wr = a.win + row * 2 * d;
-  const double sg = a.maximise ? -1.0 : 1.0;
-  // the previous sweep's critical cells of this row, read first so that their
-  // values arrive while the cells load
-  const int32_t* hint = a.hint + row * 2;
-  const int32_t h0 = hint[0], h1 = hint[1];
-  const bool have_hint = h0 >= 0 && h1 >= 0;
-  const double tau0 = have_hint ? sg * a.vin[h0].x : 0.0;
-  const double tau1 = have_hint ? sg * a.vin[h1].y : 0.0;
   RowWalk rw;
   int tot;
   walk_init<D>(p, wr, d, tid, T, rw, tot);
@@ -647,12 +642,45 @@ __device__ __forceinline__ double sel_state(const SweepArgs& a, int64_t s, SelLd
   const int tid = threadIdx.x;
   const int U = PASS == 0 ? a.nu : 1;
   const int NWD = a.nw > 1 ? a.nw : 1;
+  const double sg = a.maximise ? -1.0 : 1.0;
+  // the previous sweep's critical cells of a row and their values (only the
+  // row itself rewrites its hints)
+  auto hint_of = [&](int m, bool& ok, double& t0, double& t1) {
+    const int ui = m / NWD, wi = m - ui * NWD;
+    const int u = PASS == 0 ? ui : a.pi[s];
+    const int32_t* hint = a.hint + ((s * a.nu + u) * NWD + wi) * 2;
+    const int32_t h0 = hint[0], h1 = hint[1];
+    ok = h0 >= 0 && h1 >= 0;
+    t0 = ok ? sg * a.vin[h0].x : 0.0;
+    t1 = ok ? sg * a.vin[h1].y : 0.0;
+  };
+  if (PASS == 0) {
+    // every row's, read up front: a row's load pass then starts without
+    // waiting on the two dependent loads
+    for (int m = tid; m < U * NWD; m += 64 * NW) {
+      bool ok;
+      double t0, t1;
+      hint_of(m, ok, t0, t1);
+      L.hok[m] = ok;
+      L.htau[m] = make_double2(t0, t1);
+    }
+    __syncthreads();
+  }
   int par = 0;
   for (int m = 0; m < U * NWD; ++m) {
     const int ui = m / NWD, wi = m - ui * NWD;
     const int u = PASS == 0 ? ui : a.pi[s];
     double q0, q1;
-    sel_row<NW, E, D, ST>(a, (s * a.nu + u) * NWD + wi, tid, L, par, q0, q1);
+    bool ok;
+    double t0, t1;
+    if (PASS == 0) {
+      ok = L.hok[m] != 0;
+      t0 = L.htau[m].x;
+      t1 = L.htau[m].y;
+    } else {
+      hint_of(m, ok, t0, t1);
+    }
+    sel_row<NW, E, D, ST>(a, (s * a.nu + u) * NWD + wi, tid, L, par, ok, t0, t1, q0, q1);
     if (tid == 0) {
       L.qb0[m] = q0;
       L.qb1[m] = q1;
