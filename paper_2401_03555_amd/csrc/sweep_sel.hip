@@ -153,7 +153,9 @@ struct SelLds {
   double2 fac[kMaxFactors];    // the row's factors (FACTORS storage)
   double qb0[kMaxItems], qb1[kMaxItems];
   double2 htau[kMaxItems];     // per row of the state: the hint cells' signed values
-  int32_t hok[kMaxItems];      // ... and whether the row has hints
+  int32_t hok[kMaxItems];      // ... whether the row has hints
+  int64_t hbase[kMaxItems];    // ... the offset of its cells
+  int32_t hnw[kMaxItems];      // ... and their count
   int32_t hit[2];              // a cell holding the critical value, per vector
   double cx[2][kTail], cw[2][kTail];  // gathered candidates (signed value, width)
   int32_t tcnt[2][NW];         // candidates per wavefront
@@ -600,12 +602,10 @@ __device__ __forceinline__ void sel_row_body(const SweepArgs& a, int64_t row, in
 template <int NW, int E, int D, int ST>
 __device__ __forceinline__ void sel_row(const SweepArgs& a, int64_t row, int tid, SelLds<NW>& L,
                                         int& par, bool have_hint, double tau0, double tau1,
-                                        double& q0, double& q1) {
+                                        int64_t base, int nw, double& q0, double& q1) {
   constexpr int T = 64 * NW;
   const SysParams& p = *a.sys;
   const int d = D > 0 ? D : a.d;
-  const int64_t base = a.row_off[row];
-  const int nw = (int)(a.row_off[row + 1] - base);
   const int32_t* wr = a.win + row * 2 * d;
   RowWalk rw;
   int tot;
@@ -663,6 +663,10 @@ __device__ __forceinline__ double sel_state(const SweepArgs& a, int64_t s, SelLd
       hint_of(m, ok, t0, t1);
       L.hok[m] = ok;
       L.htau[m] = make_double2(t0, t1);
+      const int64_t row = (s * a.nu + m / NWD) * NWD + (m - (m / NWD) * NWD);
+      const int64_t b0 = a.row_off[row];
+      L.hbase[m] = b0;
+      L.hnw[m] = (int)(a.row_off[row + 1] - b0);
     }
     __syncthreads();
   }
@@ -671,16 +675,23 @@ __device__ __forceinline__ double sel_state(const SweepArgs& a, int64_t s, SelLd
     const int ui = m / NWD, wi = m - ui * NWD;
     const int u = PASS == 0 ? ui : a.pi[s];
     double q0, q1;
+    const int64_t row = (s * a.nu + u) * NWD + wi;
     bool ok;
     double t0, t1;
+    int64_t base;
+    int nw;
     if (PASS == 0) {
       ok = L.hok[m] != 0;
       t0 = L.htau[m].x;
       t1 = L.htau[m].y;
+      base = L.hbase[m];
+      nw = L.hnw[m];
     } else {
       hint_of(m, ok, t0, t1);
+      base = a.row_off[row];
+      nw = (int)(a.row_off[row + 1] - base);
     }
-    sel_row<NW, E, D, ST>(a, (s * a.nu + u) * NWD + wi, tid, L, par, ok, t0, t1, q0, q1);
+    sel_row<NW, E, D, ST>(a, row, tid, L, par, ok, t0, t1, base, nw, q0, q1);
     if (tid == 0) {
       L.qb0[m] = q0;
       L.qb1[m] = q1;
