@@ -727,6 +727,45 @@ __device__ __forceinline__ double sel_state(const SweepArgs& a, int64_t s, SelLd
   return g > 0.0 ? g : 0.0;
 }
 
+// The fixed-input pass without a disturbance player has one row per state:
+// a workgroup takes kSelFixedStates states (SAFE-list positions s0, s0 + 1,
+// ...), reads their rows' hints and offsets up front, and solves the rows one
+// after another; each state's V1 - V0 goes to its own partial.
+constexpr int kSelFixedStates = 4;
+
+template <int NW, int E, int D, int ST>
+__device__ __forceinline__ void sel_fixed_states(const SweepArgs& a, int64_t s0, int cnt,
+                                                 SelLds<NW>& L) {
+  const int tid = threadIdx.x;
+  const double sg = a.maximise ? -1.0 : 1.0;
+  for (int m = tid; m < cnt; m += 64 * NW) {
+    const int64_t s = a.safe[s0 + m];
+    const int64_t row = s * a.nu + a.pi[s];
+    const int32_t* hint = a.hint + row * 2;
+    const int32_t h0 = hint[0], h1 = hint[1];
+    const bool ok = h0 >= 0 && h1 >= 0;
+    L.hok[m] = ok;
+    L.htau[m] = make_double2(ok ? sg * a.vin[h0].x : 0.0, ok ? sg * a.vin[h1].y : 0.0);
+    const int64_t b0 = a.row_off[row];
+    L.hbase[m] = b0;
+    L.hnw[m] = (int)(a.row_off[row + 1] - b0);
+  }
+  __syncthreads();
+  int par = 0;
+  for (int m = 0; m < cnt; ++m) {
+    const int64_t s = a.safe[s0 + m];
+    const int64_t row = s * a.nu + a.pi[s];
+    double q0, q1;
+    sel_row<NW, E, D, ST>(a, row, tid, L, par, L.hok[m] != 0, L.htau[m].x, L.htau[m].y,
+                          L.hbase[m], L.hnw[m], q0, q1);
+    if (tid == 0) {
+      a.vout[s] = make_double2(q0, q1);
+      const double g = q1 - q0;
+      a.gap_part[s0 + m] = g > 0.0 ? g : 0.0;
+    }
+  }
+}
+
 // Two waves per SIMD at least: without the bound the compiler reaches for the
 // accumulation registers and leaves one wave per SIMD, which doubles the sweep.
 template <int NW, int E, int PASS, int D, int ST>
@@ -734,6 +773,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 8)))
 void k_sweep_sel(SweepArgs a) {
   if (a.ctrl->done) return;
   __shared__ SelLds<NW> L;
+  if (PASS == 1 && a.nw <= 1) {
+    const int64_t s0 = (int64_t)blockIdx.x * kSelFixedStates;
+    const int64_t left = a.n_safe - s0;
+    sel_fixed_states<NW, E, D, ST>(a, s0, left < kSelFixedStates ? (int)left : kSelFixedStates,
+                                   L);
+    return;
+  }
   const int64_t si = blockIdx.x;
   const double g = sel_state<NW, E, PASS, D, ST>(a, a.safe[si], L);
   if (threadIdx.x == 0) a.gap_part[si] = g;
@@ -741,7 +787,8 @@ void k_sweep_sel(SweepArgs a) {
 
 template <int PASS, int D, int ST>
 static hipError_t launch_sel_pds(const SweepArgs& a, int32_t max_row, hipStream_t st) {
-  const dim3 g((unsigned)a.n_safe);
+  const int64_t per = (PASS == 1 && a.nw <= 1) ? kSelFixedStates : 1;
+  const dim3 g((unsigned)((a.n_safe + per - 1) / per));
   const int cells = max_row;  // upper bound on window cells per row
   if (cells <= 256 * 8)
     hipLaunchKernelGGL((k_sweep_sel<4, 8, PASS, D, ST>), g, dim3(256), 0, st, a);
