@@ -731,7 +731,7 @@ __device__ __forceinline__ double sel_state(const SweepArgs& a, int64_t s, SelLd
 // a workgroup takes kSelFixedStates states (SAFE-list positions s0, s0 + 1,
 // ...), reads their rows' hints and offsets up front, and solves the rows one
 // after another; each state's V1 - V0 goes to its own partial.
-constexpr int kSelFixedStates = 4;
+constexpr int kSelFixedStates = 8;
 
 template <int NW, int E, int D, int ST>
 __device__ __forceinline__ void sel_fixed_states(const SweepArgs& a, int64_t s0, int cnt,
