@@ -708,6 +708,24 @@ def measure_plain(args, tuner, name, steps, warmup):
         },
     }
     imdp.free()
+    if mc is None and binfo["storage"] == 2:
+        # the same sweep with stored bounds, whose bytes are the ones the HBM
+        # roofline prices (factor storage trades them for VALU work)
+        im2 = impact.build_imdp(system, storage="bounds", timing=True)
+        im2.set_sweep_modes(*modes)
+        r2 = im2.iterate(spec, max_sweeps=max_sweeps)
+        i2 = r2["info"]
+        b2, _, _ = algorithmic_bytes(im2, r2["policy"].cpu().numpy(), binfo["n_states"], d)
+        l2 = i2["launch_ms"][0] / max(1, i2["launches"][0])
+        a2 = b2 * i2["sweeps"][0] / max(1, i2["launches"][0]) / (l2 * 1e-3) / 1e9
+        out["roofline"]["stored_bounds"] = {
+            "achieved": a2, "frac": a2 / HBM_PEAK_GBS, "bytes_per_sweep": b2,
+            "avg_launch_ms": l2, "traffic": recorded_traffic(kernel, "bounds", name),
+            "valu_issue_frac": (lambda v: None if v is None else
+                                v / (l2 * 1e-3) / VALU_ISSUE_PEAK)(
+                recorded_valu(kernel, "bounds", name)),
+        }
+        im2.free()
     return out
 
 
