@@ -164,13 +164,16 @@ hipError_t launch_mq_sweep_row(const QueryDesc* desc, const QueryCtrl* ctrl, con
 // Queries with rows beyond 512 entries (selection sweep): the value vectors of
 // the listed query slots sorted (qlist in device memory, nq slots, max_cells
 // their largest n_cells; the result lands in vs[p & 1], p =
-// value_sort_passes(max_cells)), then one workgroup per item.
+// value_sort_passes(max_cells)), then one workgroup per item (wq, ws: the
+// class's items, which start at position begin of the whole work list;
+// storage: the common storage mode of the class's queries, 0 if mixed).
 hipError_t launch_mq_value_sort(const QueryDesc* desc, const QueryCtrl* ctrl,
                                 const int32_t* qlist, int32_t nq, int64_t max_cells,
                                 hipStream_t st);
 hipError_t launch_mq_sweep_sel(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
-                               const int32_t* ws, int64_t n_items, double* gap_item,
-                               int32_t max_row, int32_t d, hipStream_t st);
+                               const int32_t* ws, int64_t n_items, int64_t begin,
+                               double* gap_item, int32_t max_row, int32_t d, int32_t storage,
+                               hipStream_t st);
 // Items of queries in the self-convergence stage of Remark 5.2: gap_item =
 // max(|V0' - V0|, |V1' - V1|) of the item's state over this step's sweep.
 hipError_t launch_mq_self_delta(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,

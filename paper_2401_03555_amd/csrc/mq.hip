@@ -168,6 +168,7 @@ int elems_slot(int e) { return e == 1 ? 0 : e == 2 ? 1 : e == 4 ? 2 : 3; }
 struct MqClass {
   int64_t begin = 0, n = 0, max_box = 1;
   int32_t max_row = 1;
+  int32_t storage = -1;  // common storage mode of its queries, 0 if mixed
   bool box = true;
 };
 
@@ -329,6 +330,8 @@ void rebuild(impact_mq* m) {
     c.n += q.n_safe;
     c.max_box = std::max(c.max_box, q.max_box);
     c.max_row = std::max(c.max_row, q.max_row);
+    const int32_t sto = m->h_desc[k].a.storage;
+    c.storage = c.storage < 0 || c.storage == sto ? sto : 0;
     seg.push_back(S);
   }
   // long-row queries: one sort of every one of them per step, over the
@@ -407,8 +410,8 @@ void enqueue_step(impact_mq* m) {
                                  m->gap + k.begin, k.max_row, d, m->st));
     } else {
       MQ_TRY(launch_mq_sweep_sel(m->d_desc, m->d_ctrl, m->wq + k.begin, m->ws + k.begin, k.n,
-                                 m->gap + k.begin, k.max_row, (c - kMqBoxClasses) >= 2 ? 5 : 0,
-                                 m->st));
+                                 k.begin, m->gap + k.begin, k.max_row,
+                                 (c - kMqBoxClasses) >= 2 ? 5 : 0, k.storage, m->st));
     }
   }
   if (m->n_auto > 0)

@@ -728,18 +728,18 @@ __device__ __forceinline__ double sel_state(const SweepArgs& a, int64_t s, SelLd
 }
 
 // The fixed-input pass without a disturbance player has one row per state:
-// a workgroup takes kSelFixedStates states (SAFE-list positions s0, s0 + 1,
-// ...), reads their rows' hints and offsets up front, and solves the rows one
-// after another; each state's V1 - V0 goes to its own partial.
+// a workgroup takes kSelFixedStates states (states[0 .. cnt)), reads their
+// rows' hints and offsets up front, and solves the rows one after another;
+// each state's V1 - V0 goes to its own partial gap[m].
 constexpr int kSelFixedStates = 8;
 
 template <int NW, int E, int D, int ST>
-__device__ __forceinline__ void sel_fixed_states(const SweepArgs& a, int64_t s0, int cnt,
-                                                 SelLds<NW>& L) {
+__device__ __forceinline__ void sel_fixed_states(const SweepArgs& a, const int32_t* states,
+                                                 double* gap, int cnt, SelLds<NW>& L) {
   const int tid = threadIdx.x;
   const double sg = a.maximise ? -1.0 : 1.0;
   for (int m = tid; m < cnt; m += 64 * NW) {
-    const int64_t s = a.safe[s0 + m];
+    const int64_t s = states[m];
     const int64_t row = s * a.nu + a.pi[s];
     const int32_t* hint = a.hint + row * 2;
     const int32_t h0 = hint[0], h1 = hint[1];
@@ -753,7 +753,7 @@ __device__ __forceinline__ void sel_fixed_states(const SweepArgs& a, int64_t s0,
   __syncthreads();
   int par = 0;
   for (int m = 0; m < cnt; ++m) {
-    const int64_t s = a.safe[s0 + m];
+    const int64_t s = states[m];
     const int64_t row = s * a.nu + a.pi[s];
     double q0, q1;
     sel_row<NW, E, D, ST>(a, row, tid, L, par, L.hok[m] != 0, L.htau[m].x, L.htau[m].y,
@@ -761,7 +761,7 @@ __device__ __forceinline__ void sel_fixed_states(const SweepArgs& a, int64_t s0,
     if (tid == 0) {
       a.vout[s] = make_double2(q0, q1);
       const double g = q1 - q0;
-      a.gap_part[s0 + m] = g > 0.0 ? g : 0.0;
+      gap[m] = g > 0.0 ? g : 0.0;
     }
   }
 }
@@ -776,8 +776,8 @@ void k_sweep_sel(SweepArgs a) {
   if (PASS == 1 && a.nw <= 1) {
     const int64_t s0 = (int64_t)blockIdx.x * kSelFixedStates;
     const int64_t left = a.n_safe - s0;
-    sel_fixed_states<NW, E, D, ST>(a, s0, left < kSelFixedStates ? (int)left : kSelFixedStates,
-                                   L);
+    sel_fixed_states<NW, E, D, ST>(a, a.safe + s0, a.gap_part + s0,
+                                   left < kSelFixedStates ? (int)left : kSelFixedStates, L);
     return;
   }
   const int64_t si = blockIdx.x;
@@ -937,13 +937,18 @@ hipError_t launch_mq_value_sort(const QueryDesc* desc, const QueryCtrl* ctrl,
 
 // One workgroup per (query, SAFE state) item of the long-row queries, each
 // query at its own phase and step: a sweep of the state (phases 0 and 2) or
-// the close of a pass (phases 1 and 3).
-template <int NW, int E, int D>
+// the close of a pass (phases 1 and 3).  In the fixed-input pass of a query
+// without a disturbance player the workgroup of every kSelFixedStates-th item
+// of the query's segment (items begin + item, counted in the whole work list)
+// solves that item and the next ones of the same query, as the single-query
+// sweep does, and the others return.  ST: the storage of every query in the
+// launch (0: mixed, tested per query).
+template <int NW, int E, int D, int ST>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 8)))
 void k_mq_sweep_sel(
     const QueryDesc* __restrict__ desc, const QueryCtrl* __restrict__ ctrl,
     const int32_t* __restrict__ wq, const int32_t* __restrict__ ws, int64_t n_items,
-    double* __restrict__ gap_item) {
+    int64_t begin, double* __restrict__ gap_item) {
   __shared__ SelLds<NW> L;
   const int64_t item = blockIdx.x;
   if (item >= n_items) return;
@@ -959,38 +964,65 @@ void k_mq_sweep_sel(
     a.reach = !Dq.safety;
     a.pass = phase >> 1;
     a.maximise = Dq.max_lp[phase >> 1];
+    if (phase == 2 && a.nw <= 1) {
+      const int64_t at = begin + item;
+      if ((at - Dq.work_begin) % kSelFixedStates != 0) return;
+      const int64_t left = Dq.work_end - at;
+      sel_fixed_states<NW, E, D, ST>(a, ws + item, gap_item + item,
+                                     left < kSelFixedStates ? (int)left : kSelFixedStates, L);
+      return;
+    }
     if (phase == 0)
-      g = sel_state<NW, E, 0, D, 0>(a, ws[item], L);
+      g = sel_state<NW, E, 0, D, ST>(a, ws[item], L);
     else
-      g = sel_state<NW, E, 1, D, 0>(a, ws[item], L);
+      g = sel_state<NW, E, 1, D, ST>(a, ws[item], L);
   } else if ((phase == 1 || phase == 3) && threadIdx.x == 0) {
     mq_close_state(Dq, ctrl[q], phase, ws[item]);
   }
   if (threadIdx.x == 0) gap_item[item] = g;
 }
 
-template <int D>
-static hipError_t launch_mq_sel_d(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
-                                  const int32_t* ws, int64_t n_items, double* gap_item,
-                                  int32_t max_row, hipStream_t st) {
+template <int D, int ST>
+static hipError_t launch_mq_sel_ds(const QueryDesc* desc, const QueryCtrl* ctrl,
+                                   const int32_t* wq, const int32_t* ws, int64_t n_items,
+                                   int64_t begin, double* gap_item, int32_t max_row,
+                                   hipStream_t st) {
   const dim3 g((unsigned)n_items);
   if (max_row <= 256 * 8)
-    hipLaunchKernelGGL((k_mq_sweep_sel<4, 8, D>), g, dim3(256), 0, st, desc, ctrl, wq, ws,
-                       n_items, gap_item);
+    hipLaunchKernelGGL((k_mq_sweep_sel<4, 8, D, ST>), g, dim3(256), 0, st, desc, ctrl, wq, ws,
+                       n_items, begin, gap_item);
   else if (max_row <= 256 * 16)
-    hipLaunchKernelGGL((k_mq_sweep_sel<4, 16, D>), g, dim3(256), 0, st, desc, ctrl, wq, ws,
-                       n_items, gap_item);
+    hipLaunchKernelGGL((k_mq_sweep_sel<4, 16, D, ST>), g, dim3(256), 0, st, desc, ctrl, wq, ws,
+                       n_items, begin, gap_item);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
+template <int D>
+static hipError_t launch_mq_sel_d(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
+                                  const int32_t* ws, int64_t n_items, int64_t begin,
+                                  double* gap_item, int32_t max_row, int32_t storage,
+                                  hipStream_t st) {
+  switch (storage) {
+    case IMPACT_STORE_BOUNDS:
+      return launch_mq_sel_ds<D, 1>(desc, ctrl, wq, ws, n_items, begin, gap_item, max_row, st);
+    case IMPACT_STORE_FACTORS:
+      return launch_mq_sel_ds<D, 2>(desc, ctrl, wq, ws, n_items, begin, gap_item, max_row, st);
+    default:
+      return launch_mq_sel_ds<D, 0>(desc, ctrl, wq, ws, n_items, begin, gap_item, max_row, st);
+  }
+}
+
 hipError_t launch_mq_sweep_sel(const QueryDesc* desc, const QueryCtrl* ctrl, const int32_t* wq,
-                               const int32_t* ws, int64_t n_items, double* gap_item,
-                               int32_t max_row, int32_t d, hipStream_t st) {
+                               const int32_t* ws, int64_t n_items, int64_t begin,
+                               double* gap_item, int32_t max_row, int32_t d, int32_t storage,
+                               hipStream_t st) {
   if (n_items == 0) return hipSuccess;
-  return d == 5 ? launch_mq_sel_d<5>(desc, ctrl, wq, ws, n_items, gap_item, max_row, st)
-                : launch_mq_sel_d<0>(desc, ctrl, wq, ws, n_items, gap_item, max_row, st);
+  return d == 5 ? launch_mq_sel_d<5>(desc, ctrl, wq, ws, n_items, begin, gap_item, max_row,
+                                     storage, st)
+                : launch_mq_sel_d<0>(desc, ctrl, wq, ws, n_items, begin, gap_item, max_row,
+                                     storage, st);
 }
 
 }  // namespace impact
