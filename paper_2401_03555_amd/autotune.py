@@ -11,6 +11,11 @@ abstraction -- and cached under a shape key (device, dimension, input count,
 row count, longest and mean row length, rounded to powers of two), in memory
 and optionally in a JSON file, so one measurement serves every later system of
 that shape.
+
+The first sweeps of a pass cost more than the later ones (the selection
+sweep's per-row hints start cold), so each candidate is timed over two probe
+lengths: the mean of the short probe prices the first TUNE_SWEEPS sweeps of a
+pass, and the extra sweeps of the long probe price every later one.
 """
 import json
 import math
@@ -22,6 +27,7 @@ import numpy as np
 from . import impact
 
 TUNE_SWEEPS = 6
+TUNE_SWEEPS_LONG = 16
 MODES = ("state_box", "per_row")
 CHUNKS = (8, 16, 32, 64)
 
@@ -52,9 +58,10 @@ def _bounds_bytes(info):
 
 
 class Autotuner:
-    def __init__(self, path=None, budget_bytes=None, sweeps=TUNE_SWEEPS):
+    def __init__(self, path=None, budget_bytes=None, sweeps=TUNE_SWEEPS, long=TUNE_SWEEPS_LONG):
         self.path = path
         self.sweeps = sweeps
+        self.long = long
         self.budget = budget_bytes
         self.table = {}
         self.log = []
@@ -76,21 +83,38 @@ class Autotuner:
         return int(torch.cuda.mem_get_info()[0] * 0.5)
 
     def _time_modes(self, imdp, d):
-        """Mean ms per sweep of each pass under every entry order (rows beyond
-        512 entries sweep by selection whatever the order: one measurement)."""
+        """Per entry order (rows beyond 512 entries sweep by selection whatever
+        the order: one measurement): the mean ms per sweep of each pass over
+        its first sweeps, then the ms per sweep of each pass after them."""
         imdp.set_timing(True)
         out = {}
         modes = MODES if imdp.info()["max_row"] <= 512 else MODES[:1]
         for mode in modes:
             imdp.set_sweep_modes(mode, mode)
             imdp.iterate(_probe_spec(d, 1))          # first-use costs out of the timing
-            r = imdp.iterate(_probe_spec(d, self.sweeps))
-            i = r["info"]
-            out[mode] = tuple(float(i["sweep_ms"][p]) / max(1, i["sweeps"][p]) for p in (0, 1))
+            i1 = imdp.iterate(_probe_spec(d, self.sweeps))["info"]
+            i2 = imdp.iterate(_probe_spec(d, max(self.long, self.sweeps)))["info"]
+            start, later = [], []
+            for p in (0, 1):
+                t1, n1 = float(i1["sweep_ms"][p]), int(i1["sweeps"][p])
+                t2, n2 = float(i2["sweep_ms"][p]), int(i2["sweeps"][p])
+                start.append(t1 / max(1, n1))
+                # a pass that stopped before the long probe's cap, or timing
+                # noise beyond the difference: later sweeps priced as the first
+                later.append((t2 - t1) / (n2 - n1) if n2 > n1 and t2 > t1 else start[-1])
+            out[mode] = tuple(start + later)
         for mode in MODES:
             out.setdefault(mode, out[modes[0]])
         imdp.set_timing(False)
         return out
+
+    def _pass_ms(self, t, p, w):
+        """Predicted ms of ``w`` sweeps of pass ``p`` from a measurement ``t``:
+        (first0, first1, later0, later1), or (ms0, ms1) for every sweep."""
+        first = t[p]
+        later = t[2 + p] if len(t) >= 4 else first
+        k = min(w, float(self.sweeps))
+        return k * first + (w - k) * later
 
     def choose(self, system, weights=(1.0, 1.0)):
         """The tuned choice for ``system``: storage and per-pass sweep modes.
@@ -120,12 +144,12 @@ class Autotuner:
         w0, w1 = (float(x) for x in weights)
         best = None
         for storage, t in measured.items():
-            p1 = min(MODES, key=lambda m: t[m][0])
-            p2 = min(MODES, key=lambda m: t[m][1])
-            cost = w0 * t[p1][0] + w1 * t[p2][1]
-            if best is None or cost < best["weighted_ms"]:
-                best = dict(storage=storage, policy_pass=p1, fixed_pass=p2, weighted_ms=cost,
-                            ms_per_sweep=[t[p1][0], t[p2][1]])
+            p1 = min(MODES, key=lambda m: self._pass_ms(t[m], 0, w0))
+            p2 = min(MODES, key=lambda m: self._pass_ms(t[m], 1, w1))
+            c0, c1 = self._pass_ms(t[p1], 0, w0), self._pass_ms(t[p2], 1, w1)
+            if best is None or c0 + c1 < best["weighted_ms"]:
+                best = dict(storage=storage, policy_pass=p1, fixed_pass=p2, weighted_ms=c0 + c1,
+                            ms_per_sweep=[c0 / max(w0, 1e-30), c1 / max(w1, 1e-30)])
         return dict(best, weights=[w0, w1], measured=measured, key=key, cached=cached)
 
     def build(self, system, **kw):

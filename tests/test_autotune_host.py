@@ -62,3 +62,34 @@ def test_sample_takes_largest_and_seeded_rest():
     got = [np.prod(s["n"]) * len(s["inputs"]) for s in sub]
     assert len(sub) == 10 and got[:5] == top
     assert [id(s) for s in t._sample(systems, 10)] == [id(s) for s in sub]
+
+
+def test_first_and_later_sweeps_priced_apart(monkeypatch, tmp_path):
+    """A measurement (first0, first1, later0, later1): the first TUNE_SWEEPS
+    sweeps of a pass at the first rate, every later one at the later rate."""
+    monkeypatch.setattr(A, "_device", lambda: "dev")
+
+    class Probe:
+        def info(self):
+            return _info()
+
+        def free(self):
+            pass
+
+    monkeypatch.setattr(A.impact, "build_imdp", lambda system, storage="bounds": Probe())
+    path = tmp_path / "tune.json"
+    key = A.imdp_key(_info())
+    # factors: dearer first sweeps, cheaper later ones than bounds
+    measured = {"factors": {"state_box": [12.4, 4.8, 7.1, 2.4], "per_row": [12.4, 4.8, 7.1, 2.4]},
+                "bounds": {"state_box": [12.3, 4.7, 7.5, 2.7], "per_row": [12.3, 4.7, 7.5, 2.7]}}
+    path.write_text(json.dumps({key: {"measured": measured}}))
+    t = A.Autotuner(path=str(path))
+    assert t.choose({"n": [2, 2, 2]})["storage"] == "bounds"       # one sweep of each pass
+    c = t.choose({"n": [2, 2, 2]}, weights=(50, 50))
+    s = A.TUNE_SWEEPS
+    assert c["storage"] == "factors"
+    assert abs(c["weighted_ms"] - (s * 12.4 + (50 - s) * 7.1 + s * 4.8 + (50 - s) * 2.4)) < 1e-9
+    assert abs(c["ms_per_sweep"][0] - (s * 12.4 + (50 - s) * 7.1) / 50) < 1e-12
+    # fewer sweeps than the first-rate span: every one at the first rate
+    c = t.choose({"n": [2, 2, 2]}, weights=(3, 0))
+    assert c["storage"] == "bounds" and abs(c["weighted_ms"] - 3 * 12.3) < 1e-9
