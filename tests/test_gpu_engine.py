@@ -111,6 +111,36 @@ def test_engine_alone_equals_in_the_mix(I):
         _same(res[qid], alone[name], f"{name} in the mix")
 
 
+def test_engine_long_rows_mixed_storage_ragged_segments(I):
+    """Selection-sweep queries of both storage modes in one launch (the kernel
+    then reads each query's storage), with SAFE sets of 591, 571 and 627
+    states: none a multiple of the fixed-input pass's eight-state groups, so
+    every later query's segment starts inside a group.  Each result equals
+    the same query run alone by the plain call (bitwise)."""
+    system = _long_rows()
+    specs = [dict(kind="reach_avoid", target=[[[1.0, 1.0], [2.0, 2.0]]],
+                  avoid=[[[-0.5, -0.5], [0.5, 0.5]]], eps=1e-8, max_sweeps=60),
+             dict(kind="safety", target=[], avoid=[[[-2.0, -2.0], [-1.0, 0.3]]], eps=1e-8,
+                  max_sweeps=40),
+             dict(kind="reach", target=[[[-1.0, -1.0], [0.0, 0.0]]], avoid=[], eps=1e-6,
+                  max_sweeps=50)]
+    safe = [int((np.asarray(oracle.label(system, sp["target"], sp["avoid"])) == 0).sum())
+            for sp in specs]
+    assert safe == [591, 571, 627]
+    imdps = {st: _engine_modes(I.build_imdp(system, storage=st)) for st in ("bounds", "factors")}
+    assert imdps["bounds"].info()["max_row"] > 512
+    plain = {(st, k): imdps[st].iterate(sp) for st in imdps for k, sp in enumerate(specs)}
+    for together in (("bounds", "factors"), ("factors",)):
+        eng = I.Engine(max_queries=8)
+        ids = {eng.submit(imdps[st], sp): (st, k) for k, sp in enumerate(specs) for st in together}
+        res = eng.run_all()
+        for qid, key in ids.items():
+            _same(res[qid], plain[key], f"{key} with {together}")
+        eng.free()
+    for im in imdps.values():
+        im.free()
+
+
 def test_engine_matches_oracle_on_batched_instances(I):
     import torch
     rng = np.random.default_rng(7)
