@@ -162,22 +162,76 @@ struct SelLds {
   double tres[2];              // critical value found by the candidate sort
 };
 
-// Sums over the workgroup of K per-thread values, the same on every thread
-// (wavefront butterflies, then the wavefronts' partials in a fixed order).
+// One reduce-scatter level across lane bit M (32 or 16): lanes where bit M
+// is clear keep the first half of the K partial sums and receive their
+// partner's copy of it, lanes where it is set the second half.  The gfx950
+// lane swaps do the exchange in the VALU: v_permlane32_swap trades the upper
+// 32 lanes of its first operand with the lower 32 of its second, and
+// v_permlane16_swap the odd 16-lane rows of the first with the even rows of
+// the second, so swapping (x[k], x[k + K/2]) leaves every lane its own and
+// its partner's copy of the value it keeps.
+template <int M>
+__device__ __forceinline__ double swap_add(double first, double second) {
+  const uint64_t a = dbits(first), b = dbits(second);
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  uint32_t d0, d1, s0, s1;
+  if constexpr (M == 32) {
+    const auto l = __builtin_amdgcn_permlane32_swap(a0, b0, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(a1, b1, false, false);
+    d0 = l[0]; s0 = l[1]; d1 = h[0]; s1 = h[1];
+  } else {
+    const auto l = __builtin_amdgcn_permlane16_swap(a0, b0, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(a1, b1, false, false);
+    d0 = l[0]; s0 = l[1]; d1 = h[0]; s1 = h[1];
+  }
+  return bitsd(((uint64_t)d1 << 32) | d0) + bitsd(((uint64_t)s1 << 32) | s0);
+}
+
+template <int M, int K>
+__device__ __forceinline__ void scatter_half(const double (&x)[K], double (&y)[K / 2],
+                                             int lane) {
+  (void)lane;
+#pragma unroll
+  for (int k = 0; k < K / 2; ++k) y[k] = swap_add<M>(x[k], x[k + K / 2]);
+}
+
+// Sums over the workgroup of K per-thread values, the same on every thread.
+// Within a wavefront the K values (padded with zeros to a multiple of 4) are
+// reduce-scattered across lane bits 32 and 16, which leaves each 16-lane row
+// a quarter of them to sum inside the row; a single value (an integer count)
+// takes a plain butterfly.  Every value is added in the same order whatever
+// K and its place among them, so a sum formed in the load pass equals the
+// same sum formed by the closing pass bit for bit.  Then the wavefronts'
+// partials are added in a fixed order.
 template <int NW, int K>
 __device__ __forceinline__ void block_sums(double (&x)[K], SelLds<NW>& L, int tid, int& par) {
   static_assert(K <= 12, "block_sums holds at most 12 values per wavefront");
-#pragma unroll
-  for (int k = 0; k < K; ++k) x[k] = wave_sum(x[k]);
+  const int lane = tid & 63, wv = tid >> 6;
   if (NW == 1) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) x[k] = uniform_f64(x[k]);
+    for (int k = 0; k < K; ++k) x[k] = uniform_f64(wave_sum(x[k]));
     return;
   }
-  const int lane = tid & 63, wv = tid >> 6;
-  if (lane == 0) {
+  if constexpr (K == 1) {
+    x[0] = wave_sum(x[0]);
+    if (lane == 0) L.red[par][wv][0] = x[0];
+  } else {
+    constexpr int P = (K + 3) / 4 * 4;
+    double xp[P], h[P / 2], q[P / 4];
 #pragma unroll
-    for (int k = 0; k < K; ++k) L.red[par][wv][k] = x[k];
+    for (int k = 0; k < P; ++k) xp[k] = k < K ? x[k] : 0.0;
+    scatter_half<32, P>(xp, h, lane);
+    scatter_half<16, P / 2>(h, q, lane);
+    // the row sums read neighbouring lanes: every lane takes part
+#pragma unroll
+    for (int k = 0; k < P / 4; ++k) q[k] = group_sum_dpp<16>(q[k]);
+    if ((lane & 15) == 0) {
+      const int b = ((lane & 32) ? P / 2 : 0) + ((lane & 16) ? P / 4 : 0);
+#pragma unroll
+      for (int k = 0; k < P / 4; ++k)
+        if (b + k < K) L.red[par][wv][b + k] = q[k];
+    }
   }
   __syncthreads();
 #pragma unroll
