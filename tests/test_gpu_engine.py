@@ -141,6 +141,29 @@ def test_engine_long_rows_mixed_storage_ragged_segments(I):
         im.free()
 
 
+def test_engine_room5d_long_rows_equal_plain(I):
+    """The 5D room at 5 cells per dimension (rows of up to 1,026 entries: the
+    5D selection-sweep kernels): safety and reach-avoid queries on stored and
+    factored bounds, each storage alone and both in one launch, equal the
+    plain call bitwise."""
+    system = W.room5d(cells=5)[0]
+    specs = [dict(kind="safety", target=[], avoid=[], eps=1e-8, max_sweeps=25),
+             dict(kind="reach_avoid", target=[[[20.2] * 5, [21.0] * 5]],
+                  avoid=[[[19.0] * 5, [19.8] * 5]], eps=1e-8, max_sweeps=25)]
+    imdps = {st: _engine_modes(I.build_imdp(system, storage=st)) for st in ("bounds", "factors")}
+    assert imdps["bounds"].info()["max_row"] > 512
+    plain = {(st, k): imdps[st].iterate(sp) for st in imdps for k, sp in enumerate(specs)}
+    for together in (("bounds",), ("factors",), ("bounds", "factors")):
+        eng = I.Engine(max_queries=8)
+        ids = {eng.submit(imdps[st], sp): (st, k) for k, sp in enumerate(specs) for st in together}
+        res = eng.run_all()
+        for qid, key in ids.items():
+            _same(res[qid], plain[key], f"room5d {key} with {together}")
+        eng.free()
+    for im in imdps.values():
+        im.free()
+
+
 def test_engine_matches_oracle_on_batched_instances(I):
     import torch
     rng = np.random.default_rng(7)
